@@ -1,0 +1,154 @@
+"""Python binding of libmsort.so, the gfx950 stable merge sort library.
+
+Argument marshalling only: every step of every sort runs in the library's HIP
+kernels.  Tensors supply device pointers and torch supplies the current HIP
+stream; nothing here computes.  If the library has not been built, importing
+works but every call raises ``RuntimeError`` -- there is no fallback.
+
+Names follow the C ABI in ``include/msort.h``: ``ms_sort``, ``ms_sort_pairs``
+and so on, each taking torch tensors instead of raw pointers.
+"""
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmsort.so")
+
+MS_KEY_U32, MS_KEY_I32, MS_KEY_U64, MS_KEY_I64 = 0, 1, 2, 3
+STATUS = {0: "MS_OK", 1: "MS_ERR_INVALID_ARG", 2: "MS_ERR_UNSUPPORTED",
+          3: "MS_ERR_OUT_OF_MEMORY", 4: "MS_ERR_HIP", 5: "MS_ERR_INTERNAL"}
+
+KEY_TYPES = {torch.uint32: MS_KEY_U32, torch.int32: MS_KEY_I32,
+             torch.uint64: MS_KEY_U64, torch.int64: MS_KEY_I64}
+
+PROFILE_KERNELS = {"tile_sort": 0, "partition": 1, "merge": 2, "seg_classify": 3,
+                   "seg_small": 4, "seg_large": 5, "mlp_train": 6, "learned_hist": 7,
+                   "learned_scatter": 8, "bucket_sort": 9, "learned_other": 10}
+
+_lib = None
+
+
+class MSortError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {detail}")
+
+
+def _declare(lib):
+    c = ctypes
+    sz, vp, i32 = c.c_size_t, c.c_void_p, c.c_int
+    sig = {
+        "ms_version": (i32, []),
+        "ms_status_string": (c.c_char_p, [i32]),
+        "ms_last_error": (c.c_char_p, []),
+        "ms_sort": (i32, [vp, sz, i32, vp]),
+        "ms_sort_pairs": (i32, [vp, vp, sz, i32, sz, vp]),
+        "ms_temp_bytes": (sz, [sz, i32, sz]),
+        "ms_plan_query": (i32, [sz, i32, sz, c.POINTER(i32), c.POINTER(i32), c.POINTER(i32),
+                                c.POINTER(i32)]),
+        "ms_release_workspace": (i32, []),
+        "ms_profile_enable": (i32, [i32]),
+        "ms_profile_reset": (i32, []),
+        "ms_profile_read": (i32, [i32, c.POINTER(c.c_uint64), c.POINTER(c.c_double)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise MSortError(status, where, lib().ms_last_error().decode())
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _key_type(t: torch.Tensor, key_type=None) -> int:
+    if key_type is not None:
+        return int(key_type)
+    try:
+        return KEY_TYPES[t.dtype]
+    except KeyError:
+        raise TypeError(f"unsupported key dtype {t.dtype}; pass key_type explicitly") from None
+
+
+def _dev(t: torch.Tensor, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def ms_sort(keys: torch.Tensor, key_type=None) -> torch.Tensor:
+    """Sort ``keys`` in place (ascending) on the current stream; returns it."""
+    _dev(keys, "keys")
+    _check(lib().ms_sort(ctypes.c_void_p(keys.data_ptr()), keys.numel(), _key_type(keys, key_type),
+                         _stream(keys)), "ms_sort")
+    return keys
+
+
+def ms_sort_pairs(keys: torch.Tensor, vals: torch.Tensor, key_type=None):
+    """Stable in-place sort of (keys, vals) by key; returns (keys, vals)."""
+    _dev(keys, "keys")
+    _dev(vals, "vals")
+    if vals.numel() != keys.numel():
+        raise ValueError("keys and vals differ in length")
+    _check(lib().ms_sort_pairs(ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()),
+                               keys.numel(), _key_type(keys, key_type), vals.element_size(),
+                               _stream(keys)), "ms_sort_pairs")
+    return keys, vals
+
+
+def ms_temp_bytes(n: int, key_type: int, val_bytes: int = 0) -> int:
+    return int(lib().ms_temp_bytes(n, key_type, val_bytes))
+
+
+def ms_plan_query(n: int, key_type: int, val_bytes: int = 0) -> dict:
+    t, mt, p, ip = (ctypes.c_int() for _ in range(4))
+    _check(lib().ms_plan_query(n, key_type, val_bytes, ctypes.byref(t), ctypes.byref(mt),
+                               ctypes.byref(p), ctypes.byref(ip)), "ms_plan_query")
+    return {"tile": t.value, "merge_tile": mt.value, "passes": p.value,
+            "tile_sort_in_place": bool(ip.value)}
+
+
+def ms_release_workspace():
+    _check(lib().ms_release_workspace(), "ms_release_workspace")
+
+
+def ms_profile_enable(on: bool = True):
+    _check(lib().ms_profile_enable(1 if on else 0), "ms_profile_enable")
+
+
+def ms_profile_reset():
+    _check(lib().ms_profile_reset(), "ms_profile_reset")
+
+
+def ms_profile_read(kernel) -> tuple:
+    """(launches, total_ms) for a kernel class name or id since the last reset."""
+    k = PROFILE_KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    n = ctypes.c_uint64()
+    ms = ctypes.c_double()
+    _check(lib().ms_profile_read(k, ctypes.byref(n), ctypes.byref(ms)), "ms_profile_read")
+    return int(n.value), float(ms.value)
+
+
+def version() -> int:
+    return int(lib().ms_version())

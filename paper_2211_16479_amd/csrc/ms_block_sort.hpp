@@ -1,0 +1,227 @@
+// Tile sort: sorts one tile of up to WG*IPT elements inside one workgroup.
+//
+// This is the GPU form of the paper's chunk-parallel step (section
+// "Multiprocessing Merge Sort": the array is cut into equal chunks that are
+// sorted independently) with the hybrid variant's leaf cutoff (the
+// sequential_mergesort figure) becoming the tile size.  Within a tile:
+//   1. blocked load: thread t holds tile positions [t*IPT, t*IPT + IPT);
+//      slots past the tile's end are padded with an item that sorts last;
+//   2. each thread sorts its IPT items with a bitonic network in registers;
+//   3. wavefront merges: runs of IPT, 2*IPT, ..., 32*IPT items are merged in
+//      pairs by bitonic merge stages whose partners sit in other lanes, with
+//      the xor lane moves (DPP / ds_swizzle / ds_bpermute) of ms_common.hpp;
+//   4. LDS merge-path levels merge the wave runs up to the whole tile; each
+//      thread finds its output diagonal by binary search and merges IPT
+//      outputs serially, left run first on ties;
+//   5. store (and, for pairs, fetch each value by its input position).
+// Bitonic stages compare (key, input position) items for pairs, a strict
+// total order, so they produce exactly the stable order.
+#pragma once
+#include "ms_common.hpp"
+
+namespace ms {
+
+template <class IT, class T>
+__device__ __forceinline__ void cmpswap(T& a, T& b) {
+  T lo = IT::vmin(a, b), hi = IT::vmax(a, b);
+  a = lo;
+  b = hi;
+}
+
+// Bitonic sort of N register items ("flip" form: every stage ascending).
+template <class IT, int N, class T>
+__device__ __forceinline__ void register_sort(T (&v)[N]) {
+#pragma unroll
+  for (int size = 2; size <= N; size *= 2) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const int j = i ^ (size - 1);
+      if (j > i) cmpswap<IT>(v[i], v[j]);
+    }
+#pragma unroll
+    for (int s = size / 4; s >= 1; s /= 2) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int j = i ^ s;
+        if (j > i) cmpswap<IT>(v[i], v[j]);
+      }
+    }
+  }
+}
+
+// Half-cleaner stage between lanes lane and lane^SL (same register index).
+template <class IT, int SL, int N, class T>
+__device__ __forceinline__ void lane_half_clean(T (&v)[N], int lane) {
+  const bool lower = (lane & SL) == 0;
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    T p = xor_lane<SL>(v[r]);
+    v[r] = lower ? IT::vmin(v[r], p) : IT::vmax(v[r], p);
+  }
+  if constexpr (SL > 1) lane_half_clean<IT, SL / 2>(v, lane);
+}
+
+// Merge sorted runs spanning L2/2 lanes each into runs spanning L2 lanes.
+template <class IT, int L2, int N, class T>
+__device__ __forceinline__ void wave_merge_level(T (&v)[N], int lane) {
+  // flip stage: flat index f pairs with f ^ (L2*N - 1), i.e. lane ^ (L2-1),
+  // register N-1-r; the lower half of each block keeps the minimum.
+  {
+    const bool lower = (lane & (L2 / 2)) == 0;
+    T p[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) p[r] = xor_lane<L2 - 1>(v[N - 1 - r]);
+#pragma unroll
+    for (int r = 0; r < N; ++r) v[r] = lower ? IT::vmin(v[r], p[r]) : IT::vmax(v[r], p[r]);
+  }
+  if constexpr (L2 >= 4) lane_half_clean<IT, L2 / 4>(v, lane);
+  // remaining half cleaners inside each lane's registers
+#pragma unroll
+  for (int s = N / 2; s >= 1; s /= 2) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const int j = i ^ s;
+      if (j > i) cmpswap<IT>(v[i], v[j]);
+    }
+  }
+}
+
+template <class IT, int L2, int N, class T>
+__device__ __forceinline__ void wave_merges(T (&v)[N], int lane) {
+  wave_merge_level<IT, L2>(v, lane);
+  if constexpr (L2 < 64) wave_merges<IT, L2 * 2>(v, lane);
+}
+
+// One LDS merge-path level: sorted runs of R items (blocked in registers
+// across the workgroup) become runs of 2R.  lds must hold WG*N items.
+template <class IT, int WG, int N, class T>
+__device__ __forceinline__ void lds_merge_level(T (&v)[N], T* lds, int R) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < N; ++r) lds[tid * N + r] = v[r];
+  __syncthreads();
+  const int per_blk = (2 * R) / N;  // threads per merged run
+  const int blk = tid / per_blk;
+  const int d = (tid - blk * per_blk) * N;
+  const T* A = lds + blk * 2 * R;
+  const T* B = A + R;
+  int lo = d > R ? d - R : 0, hi = d < R ? d : R;
+  while (lo < hi) {
+    const int m = (lo + hi) >> 1;
+    if (IT::less(B[d - 1 - m], A[m])) hi = m; else lo = m + 1;
+  }
+  int i = lo, j = d - lo;
+  T a = A[i < R ? i : R - 1], b = B[j < R ? j : R - 1];
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    const bool take_b = (j < R) && (i >= R || IT::less(b, a));
+    v[r] = take_b ? b : a;
+    if (take_b) { ++j; b = B[j < R ? j : R - 1]; }
+    else { ++i; a = A[i < R ? i : R - 1]; }
+  }
+  __syncthreads();
+}
+
+template <class K, class V, int WG, int IPT>
+struct TileSort {
+  static constexpr bool PAIRS = HasVal<V>::value;
+  using IT = Item<K, PAIRS>;
+  using T = typename IT::T;
+  static constexpr int TILE = WG * IPT;
+  static constexpr int NW = WG / 64;
+  static_assert(WG % 64 == 0 && (WG & (WG - 1)) == 0 && WG <= 1024, "WG");
+  static_assert((IPT & (IPT - 1)) == 0 && IPT >= 2 && IPT <= 32, "IPT");
+  static constexpr size_t LDS_ITEMS = (NW > 1) ? sizeof(T) * TILE : 0;
+  static constexpr size_t LDS_VALS = PAIRS ? sizeof(typename std::conditional<PAIRS, V, int>::type) * TILE : 0;
+  static constexpr size_t LDS_BYTES = LDS_ITEMS + LDS_VALS;
+
+  // Sort in_k[0, len) (len <= TILE) into out_k[0, len); values likewise.
+  // in and out may alias (the whole tile is read before anything is written).
+  template <class VV>
+  static __device__ __forceinline__ void run(const K* in_k, const VV* in_v, K* out_k, VV* out_v,
+                                             uint32_t len, unsigned char* smem) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    T* lds = reinterpret_cast<T*>(smem);
+    VV* lds_v = reinterpret_cast<VV*>(smem + LDS_ITEMS);
+    if constexpr (PAIRS) {
+      for (uint32_t e = tid; e < len; e += WG) lds_v[e] = in_v[e];
+    }
+    T v[IPT];
+    const uint32_t e0 = uint32_t(tid) * IPT;
+    const bool full = e0 + IPT <= len &&
+                      ((reinterpret_cast<uintptr_t>(in_k + e0) & 15) == 0);
+    if (full) {
+      K kk[IPT];
+      load_run<K, IPT>(in_k + e0, kk);
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) v[r] = IT::make(kk[r], e0 + r);
+    } else {
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const uint32_t e = e0 + r;
+        v[r] = e < len ? IT::make(in_k[e], e) : IT::pad(e);
+      }
+    }
+    register_sort<IT>(v);
+    wave_merges<IT, 2>(v, lane);
+    if constexpr (NW > 1) {
+      // all loads of this tile are done before the first barrier, so the
+      // output may overwrite the input in place
+#pragma unroll
+      for (int R = 64 * IPT; R < TILE; R *= 2) lds_merge_level<IT, WG>(v, lds, R);
+    } else {
+      __syncthreads();
+    }
+    // store
+    K ko[IPT];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) ko[r] = IT::key(v[r]);
+    const bool full_out = e0 + IPT <= len &&
+                          ((reinterpret_cast<uintptr_t>(out_k + e0) & 15) == 0);
+    if (full_out) {
+      store_run<K, IPT>(out_k + e0, ko);
+    } else {
+#pragma unroll
+      for (int r = 0; r < IPT; ++r)
+        if (e0 + r < len) out_k[e0 + r] = ko[r];
+    }
+    if constexpr (PAIRS) {
+      VV vo[IPT];
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const uint32_t p = IT::pos(v[r]);
+        vo[r] = lds_v[p < len ? p : 0];
+      }
+      const bool fv = e0 + IPT <= len && ((reinterpret_cast<uintptr_t>(out_v + e0) & 15) == 0);
+      if (fv) {
+        store_run<VV, IPT>(out_v + e0, vo);
+      } else {
+#pragma unroll
+        for (int r = 0; r < IPT; ++r)
+          if (e0 + r < len) out_v[e0 + r] = vo[r];
+      }
+    }
+  }
+};
+
+// One workgroup per tile of the array: tiles [t*TILE, min(n, (t+1)*TILE)).
+template <class K, class V, int WG, int IPT>
+__global__ __launch_bounds__(WG) void block_sort_kernel(const K* in_k, const V* in_v, K* out_k, V* out_v,
+                                                        uint64_t n_host, DevCtl ctl) {
+  using TS = TileSort<K, V, WG, IPT>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (gated_off(ctl)) return;
+  const uint64_t n = live_n(ctl, n_host);
+  const uint64_t base = uint64_t(blockIdx.x) * TS::TILE;
+  if (base >= n) return;
+  const uint64_t rem = n - base;
+  const uint32_t len = rem < uint64_t(TS::TILE) ? uint32_t(rem) : uint32_t(TS::TILE);
+  if constexpr (TS::PAIRS) {
+    TS::run(in_k + base, in_v + base, out_k + base, out_v + base, len, smem);
+  } else {
+    TS::template run<int>(in_k + base, nullptr, out_k + base, nullptr, len, smem);
+  }
+}
+
+}  // namespace ms

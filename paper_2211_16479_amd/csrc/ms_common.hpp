@@ -1,0 +1,200 @@
+// Shared device-side building blocks of the gfx950 merge sort.
+//
+// Ordering used everywhere: ascending, stable.  Keys compare as unsigned
+// (u32/u64) or signed (i32/i64).  Whenever two runs are merged, the run that
+// came first in the input (the left run) wins ties; this is the reading of the
+// paper's undefined merge() that makes the sort stable (section "Sequential
+// Merge Sort").
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ms {
+
+// ---------------------------------------------------------------- value tag
+struct NoVal {};  // keys-only sorts
+
+template <class V>
+struct HasVal { static constexpr bool value = true; };
+template <>
+struct HasVal<NoVal> { static constexpr bool value = false; };
+
+// ------------------------------------------------------------- sort items
+// Inside one tile the block sort orders "items".  Keys-only: the key itself
+// (equal keys are identical bits, so the order among them is unobservable).
+// Key/value pairs: the key together with its tile-local input position, so
+// that the (key, position) order -- a strict total order -- is exactly the
+// stable order; the value is fetched by position at the end.
+template <class K>
+struct KeyBits;
+template <>
+struct KeyBits<uint32_t> { static __device__ __forceinline__ uint32_t ord(uint32_t k) { return k; } static __device__ __forceinline__ uint32_t unord(uint32_t b) { return b; } };
+template <>
+struct KeyBits<int32_t> { static __device__ __forceinline__ uint32_t ord(int32_t k) { return uint32_t(k) ^ 0x80000000u; } static __device__ __forceinline__ int32_t unord(uint32_t b) { return int32_t(b ^ 0x80000000u); } };
+
+template <class K>
+__device__ __forceinline__ K key_max();
+template <> __device__ __forceinline__ uint32_t key_max<uint32_t>() { return 0xFFFFFFFFu; }
+template <> __device__ __forceinline__ int32_t key_max<int32_t>() { return 0x7FFFFFFF; }
+template <> __device__ __forceinline__ uint64_t key_max<uint64_t>() { return ~0ull; }
+template <> __device__ __forceinline__ int64_t key_max<int64_t>() { return 0x7FFFFFFFFFFFFFFFll; }
+
+struct Key64Pos {
+  uint64_t k;    // key bits (the key type decides how they compare)
+  uint32_t pos;  // tile-local input position
+  uint32_t pad;
+};
+
+template <class K, bool PAIRS, bool WIDE = (sizeof(K) == 8)>
+struct Item;
+
+// keys only: the key
+template <class K, bool WIDE>
+struct Item<K, false, WIDE> {
+  using T = K;
+  static __device__ __forceinline__ T make(K k, uint32_t) { return k; }
+  static __device__ __forceinline__ T pad(uint32_t) { return key_max<K>(); }
+  static __device__ __forceinline__ K key(const T& t) { return t; }
+  static __device__ __forceinline__ uint32_t pos(const T&) { return 0; }
+  static __device__ __forceinline__ bool less(const T& a, const T& b) { return a < b; }
+  static __device__ __forceinline__ T vmin(const T& a, const T& b) { return a < b ? a : b; }
+  static __device__ __forceinline__ T vmax(const T& a, const T& b) { return a < b ? b : a; }
+};
+
+// 32-bit keys with values: (order-preserving key bits << 32) | position
+template <class K>
+struct Item<K, true, false> {
+  using T = uint64_t;
+  static __device__ __forceinline__ T make(K k, uint32_t p) { return (uint64_t(KeyBits<K>::ord(k)) << 32) | p; }
+  static __device__ __forceinline__ T pad(uint32_t p) { return (0xFFFFFFFFull << 32) | p; }
+  static __device__ __forceinline__ K key(const T& t) { return KeyBits<K>::unord(uint32_t(t >> 32)); }
+  static __device__ __forceinline__ uint32_t pos(const T& t) { return uint32_t(t); }
+  static __device__ __forceinline__ bool less(const T& a, const T& b) { return a < b; }
+  static __device__ __forceinline__ T vmin(const T& a, const T& b) { return a < b ? a : b; }
+  static __device__ __forceinline__ T vmax(const T& a, const T& b) { return a < b ? b : a; }
+};
+
+// 64-bit keys with values: key and position side by side
+template <class K>
+struct Item<K, true, true> {
+  using T = Key64Pos;
+  static __device__ __forceinline__ T make(K k, uint32_t p) { T t; t.k = uint64_t(k); t.pos = p; t.pad = 0; return t; }
+  static __device__ __forceinline__ T pad(uint32_t p) { return make(key_max<K>(), p); }
+  static __device__ __forceinline__ K key(const T& t) { return K(t.k); }
+  static __device__ __forceinline__ uint32_t pos(const T& t) { return t.pos; }
+  static __device__ __forceinline__ bool less(const T& a, const T& b) {
+    K ka = K(a.k), kb = K(b.k);
+    return ka < kb || (ka == kb && a.pos < b.pos);
+  }
+  static __device__ __forceinline__ T vmin(const T& a, const T& b) { return less(b, a) ? b : a; }
+  static __device__ __forceinline__ T vmax(const T& a, const T& b) { return less(a, b) ? b : a; }
+};
+
+// ------------------------------------------------------- cross-lane xor moves
+// xor_lane<M>(v): the value v held by lane (lane ^ M) of the same wavefront.
+// Each mask uses the cheapest gfx950 route: DPP quad permutes for 1, 2, 3,
+// DPP row_half_mirror / row_mirror for 7 / 15, ds_swizzle (bit mode, xor
+// within 32 lanes) for 4, 8, 16, 31 and ds_bpermute for the full-wave 63.
+template <int M>
+__device__ __forceinline__ uint32_t xor_lane32(uint32_t v) {
+  if constexpr (M == 1) return __builtin_amdgcn_mov_dpp(int(v), 0xB1, 0xF, 0xF, false);
+  else if constexpr (M == 2) return __builtin_amdgcn_mov_dpp(int(v), 0x4E, 0xF, 0xF, false);
+  else if constexpr (M == 3) return __builtin_amdgcn_mov_dpp(int(v), 0x1B, 0xF, 0xF, false);
+  else if constexpr (M == 7) return __builtin_amdgcn_mov_dpp(int(v), 0x141, 0xF, 0xF, false);
+  else if constexpr (M == 15) return __builtin_amdgcn_mov_dpp(int(v), 0x140, 0xF, 0xF, false);
+  else if constexpr (M == 4 || M == 8 || M == 16 || M == 31)
+    return __builtin_amdgcn_ds_swizzle(int(v), (M << 10) | 0x1F);
+  else {
+    static_assert(M > 0 && M < 64, "lane mask");
+    const int lane = __lane_id();
+    return __builtin_amdgcn_ds_bpermute((lane ^ M) << 2, int(v));
+  }
+}
+
+template <int M>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v) { return xor_lane32<M>(v); }
+template <int M>
+__device__ __forceinline__ int32_t xor_lane(int32_t v) { return int32_t(xor_lane32<M>(uint32_t(v))); }
+template <int M>
+__device__ __forceinline__ uint64_t xor_lane(uint64_t v) {
+  uint32_t lo = xor_lane32<M>(uint32_t(v)), hi = xor_lane32<M>(uint32_t(v >> 32));
+  return (uint64_t(hi) << 32) | lo;
+}
+template <int M>
+__device__ __forceinline__ int64_t xor_lane(int64_t v) { return int64_t(xor_lane<M>(uint64_t(v))); }
+template <int M>
+__device__ __forceinline__ Key64Pos xor_lane(const Key64Pos& v) {
+  Key64Pos r;
+  r.k = xor_lane<M>(v.k);
+  r.pos = xor_lane32<M>(v.pos);
+  r.pad = 0;
+  return r;
+}
+
+// ---------------------------------------------------- small helpers
+__host__ __device__ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
+
+// Vector store of N consecutive 32- or 64-bit elements when the address is
+// aligned for it; element count N is a compile-time multiple of the vector.
+template <class E, int N>
+__device__ __forceinline__ void store_run(E* __restrict__ dst, const E (&v)[N]) {
+  if constexpr (sizeof(E) == 4 && N % 4 == 0) {
+#pragma unroll
+    for (int i = 0; i < N; i += 4) {
+      uint4 w;
+      w.x = __builtin_bit_cast(uint32_t, v[i]);
+      w.y = __builtin_bit_cast(uint32_t, v[i + 1]);
+      w.z = __builtin_bit_cast(uint32_t, v[i + 2]);
+      w.w = __builtin_bit_cast(uint32_t, v[i + 3]);
+      *reinterpret_cast<uint4*>(dst + i) = w;
+    }
+  } else if constexpr (sizeof(E) == 8 && N % 2 == 0) {
+#pragma unroll
+    for (int i = 0; i < N; i += 2) {
+      uint4 w;
+      uint64_t a = __builtin_bit_cast(uint64_t, v[i]), b = __builtin_bit_cast(uint64_t, v[i + 1]);
+      w.x = uint32_t(a); w.y = uint32_t(a >> 32); w.z = uint32_t(b); w.w = uint32_t(b >> 32);
+      *reinterpret_cast<uint4*>(dst + i) = w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) dst[i] = v[i];
+  }
+}
+
+template <class E, int N>
+__device__ __forceinline__ void load_run(const E* __restrict__ src, E (&v)[N]) {
+  if constexpr (sizeof(E) == 4 && N % 4 == 0) {
+#pragma unroll
+    for (int i = 0; i < N; i += 4) {
+      uint4 w = *reinterpret_cast<const uint4*>(src + i);
+      v[i] = __builtin_bit_cast(E, w.x); v[i + 1] = __builtin_bit_cast(E, w.y);
+      v[i + 2] = __builtin_bit_cast(E, w.z); v[i + 3] = __builtin_bit_cast(E, w.w);
+    }
+  } else if constexpr (sizeof(E) == 8 && N % 2 == 0) {
+#pragma unroll
+    for (int i = 0; i < N; i += 2) {
+      uint4 w = *reinterpret_cast<const uint4*>(src + i);
+      v[i] = __builtin_bit_cast(E, uint64_t(w.x) | (uint64_t(w.y) << 32));
+      v[i + 1] = __builtin_bit_cast(E, uint64_t(w.z) | (uint64_t(w.w) << 32));
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = src[i];
+  }
+}
+
+// Optional device-side controls shared by the sort kernels: an element count
+// that lives in device memory (set by an earlier kernel) and a gate flag that
+// lets a kernel return at once when its stage is not needed.
+struct DevCtl {
+  const uint64_t* n_dev;  // if non-null, the element count (<= the host bound)
+  const int* gate;        // if non-null and *gate == 0, the kernel does nothing
+};
+
+__device__ __forceinline__ bool gated_off(const DevCtl& c) { return c.gate && *c.gate == 0; }
+__device__ __forceinline__ uint64_t live_n(const DevCtl& c, uint64_t n_host) {
+  return c.n_dev ? *c.n_dev : n_host;
+}
+
+}  // namespace ms

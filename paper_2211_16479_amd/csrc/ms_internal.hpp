@@ -1,0 +1,53 @@
+// Library-internal declarations shared by the C-ABI and the launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/msort.h"
+#include "ms_common.hpp"
+
+namespace ms {
+
+// Kernel classes timed by the event profiler.
+enum ProfKernel {
+  PK_BLOCK_SORT = 0,
+  PK_PARTITION = 1,
+  PK_MERGE = 2,
+  PK_SEG_CLASSIFY = 3,
+  PK_SEG_SMALL = 4,
+  PK_SEG_LARGE = 5,
+  PK_LEARN_TRAIN = 6,
+  PK_LEARN_HIST = 7,
+  PK_LEARN_SCATTER = 8,
+  PK_LEARN_BUCKET = 9,
+  PK_LEARN_OTHER = 10,
+  PK_COUNT = 11
+};
+
+// Records a start/stop event pair around a launch when profiling is on.
+struct ProfScope {
+  ProfScope(int kernel, hipStream_t s);
+  ~ProfScope();
+  int kernel;
+  hipStream_t stream;
+  int slot;
+};
+
+void set_error(const std::string& msg);
+ms_status hip_fail(hipError_t e, const char* what);
+
+// Scratch memory owned by the library, one buffer per (device, stream),
+// grown on demand in stream order.
+ms_status get_workspace(hipStream_t s, size_t bytes, void** out);
+
+// Plain merge sort of n keys (and values) already resident on the device.
+// ctl may carry a device-side count (n is then an upper bound) and a gate.
+template <class K, class V>
+ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, void* ws);
+template <class K, class V>
+size_t plain_temp_bytes(uint64_t n);
+template <class K, class V>
+void plain_geometry(int* tile, int* merge_tile);
+
+}  // namespace ms

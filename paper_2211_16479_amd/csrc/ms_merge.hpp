@@ -1,0 +1,168 @@
+// Global merge passes.
+//
+// After the tile sort the array holds sorted runs of width T.  Pass p merges
+// runs 2j and 2j+1 of width W = T * 2^p into one run of width 2W; the last
+// run of an odd count, and a short last run, simply take part with an empty
+// or short partner.  Each pass is one level of the paper's merge tree
+// (section "Merging the subarrays", where each loop iteration halves the
+// number of sorted pieces), run for all pairs at once; pairing is between
+// adjacent runs, which keeps the sort stable (the paper's rank tree pairs r
+// with r + split, which would not be).
+//
+// A pass is two kernels:
+//   partition: for every merge tile k (outputs [k*Tm, (k+1)*Tm) of its pair)
+//     a binary search on the merge-path diagonal d = k*Tm - pair_base finds
+//     i(d) = how many of the first d outputs come from run A, under the
+//     left-wins-ties rule (A[m] goes first when A[m] <= B[d-1-m]);
+//   merge: workgroup k stages A[i(d_k), i(d_k+1)) and B[d_k - i(d_k), ...)
+//     in LDS with coalesced loads, each thread finds its own sub-diagonal by
+//     the same search and merges IPT outputs serially, then stores them.
+#pragma once
+#include "ms_common.hpp"
+
+namespace ms {
+
+struct PassGeom {
+  uint64_t pb, a_end, b_end;  // pair base, end of run A, end of run B
+};
+
+__device__ __forceinline__ PassGeom pass_geom(uint64_t g, uint64_t n, uint64_t W) {
+  PassGeom q;
+  q.pb = (g / (2 * W)) * (2 * W);
+  q.a_end = q.pb + W < n ? q.pb + W : n;
+  q.b_end = q.pb + 2 * W < n ? q.pb + 2 * W : n;
+  return q;
+}
+
+// Number of outputs among the first d of merge(A, B) that come from A.
+template <class K>
+__device__ __forceinline__ uint64_t merge_path_split(const K* A, uint64_t la, const K* B, uint64_t lb,
+                                                     uint64_t d) {
+  uint64_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
+  while (lo < hi) {
+    const uint64_t m = (lo + hi) >> 1;
+    if (B[d - 1 - m] < A[m]) hi = m; else lo = m + 1;
+  }
+  return lo;
+}
+
+template <class K>
+__global__ __launch_bounds__(256) void partition_kernel(const K* __restrict__ src, uint64_t n_host, DevCtl ctl,
+                                                        uint64_t W, uint32_t Tm, uint64_t num_tiles,
+                                                        int64_t* __restrict__ part) {
+  if (gated_off(ctl)) return;
+  const uint64_t n = live_n(ctl, n_host);
+  const uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= num_tiles) return;
+  const uint64_t g = k * Tm;
+  if (g >= n) return;
+  const PassGeom q = pass_geom(g, n, W);
+  const uint64_t i = merge_path_split(src + q.pb, q.a_end - q.pb, src + q.a_end, q.b_end - q.a_end, g - q.pb);
+  part[k] = int64_t(q.pb + i);
+}
+
+template <class K, class V, int WG, int IPT>
+struct MergeTile {
+  static constexpr bool PAIRS = HasVal<V>::value;
+  static constexpr int TM = WG * IPT;
+  static constexpr size_t LDS_KEYS = sizeof(K) * TM;
+  static constexpr size_t LDS_BYTES = LDS_KEYS + (PAIRS ? sizeof(typename std::conditional<PAIRS, V, int>::type) * TM : 0);
+
+  // Merge A = src[a0, a0+la) and B = src[b0, b0+lb) (la + lb <= TM) into
+  // dst[o0, o0+la+lb); A's elements win ties.
+  template <class VV>
+  static __device__ __forceinline__ void run(const K* __restrict__ src_k, const VV* __restrict__ src_v,
+                                             K* __restrict__ dst_k, VV* __restrict__ dst_v,
+                                             uint64_t a0, uint32_t la, uint64_t b0, uint32_t lb, uint64_t o0,
+                                             unsigned char* smem) {
+    const int tid = threadIdx.x;
+    K* sk = reinterpret_cast<K*>(smem);
+    VV* sv = reinterpret_cast<VV*>(smem + LDS_KEYS);
+    const uint32_t total = la + lb;
+    // coalesced staging of both pieces, A then B
+    for (uint32_t e = tid; e < total; e += WG) {
+      const uint64_t g = e < la ? a0 + e : b0 + (e - la);
+      sk[e] = src_k[g];
+      if constexpr (PAIRS) sv[e] = src_v[g];
+    }
+    __syncthreads();
+    const uint32_t d = uint32_t(tid) * IPT;
+    if (d >= total) return;
+    const K* A = sk;
+    const K* B = sk + la;
+    uint32_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
+    while (lo < hi) {
+      const uint32_t m = (lo + hi) >> 1;
+      if (B[d - 1 - m] < A[m]) hi = m; else lo = m + 1;
+    }
+    uint32_t i = lo, j = d - lo;
+    const uint32_t last = total - 1;
+    K a = sk[i < last ? i : last];
+    K b = sk[la + j < last ? la + j : last];
+    K ko[IPT];
+    uint32_t src_idx[IPT];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+      const bool take_b = (j < lb) && (i >= la || b < a);
+      ko[r] = take_b ? b : a;
+      src_idx[r] = take_b ? la + j : i;
+      if (take_b) { ++j; const uint32_t x = la + j; b = sk[x < last ? x : last]; }
+      else { ++i; a = sk[i < last ? i : last]; }
+    }
+    const uint32_t cnt = total - d < uint32_t(IPT) ? total - d : uint32_t(IPT);
+    K* out = dst_k + o0 + d;
+    if (cnt == IPT && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+      store_run<K, IPT>(out, ko);
+    } else {
+#pragma unroll
+      for (int r = 0; r < IPT; ++r)
+        if (uint32_t(r) < cnt) out[r] = ko[r];
+    }
+    if constexpr (PAIRS) {
+      VV vo[IPT];
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) vo[r] = sv[src_idx[r] < last ? src_idx[r] : last];
+      VV* ov = dst_v + o0 + d;
+      if (cnt == IPT && (reinterpret_cast<uintptr_t>(ov) & 15) == 0) {
+        store_run<VV, IPT>(ov, vo);
+      } else {
+#pragma unroll
+        for (int r = 0; r < IPT; ++r)
+          if (uint32_t(r) < cnt) ov[r] = vo[r];
+      }
+    }
+  }
+};
+
+template <class K, class V, int WG, int IPT>
+__global__ __launch_bounds__(WG) void merge_kernel(const K* __restrict__ src_k, const V* __restrict__ src_v,
+                                                   K* __restrict__ dst_k, V* __restrict__ dst_v,
+                                                   uint64_t n_host, DevCtl ctl, uint64_t W,
+                                                   const int64_t* __restrict__ part) {
+  using MT = MergeTile<K, V, WG, IPT>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (gated_off(ctl)) return;
+  const uint64_t n = live_n(ctl, n_host);
+  const uint64_t k = blockIdx.x;
+  const uint64_t g0 = k * MT::TM;
+  if (g0 >= n) return;
+  const uint64_t g1 = g0 + MT::TM < n ? g0 + MT::TM : n;
+  const PassGeom q = pass_geom(g0, n, W);
+  const uint64_t i0 = uint64_t(part[k]);
+  const uint64_t j0 = q.a_end + (g0 - q.pb) - (i0 - q.pb);
+  uint64_t i1, j1;
+  if (g1 == q.b_end) {
+    i1 = q.a_end;
+    j1 = q.b_end;
+  } else {
+    i1 = uint64_t(part[k + 1]);
+    j1 = q.a_end + (g1 - q.pb) - (i1 - q.pb);
+  }
+  if constexpr (MT::PAIRS) {
+    MT::run(src_k, src_v, dst_k, dst_v, i0, uint32_t(i1 - i0), j0, uint32_t(j1 - j0), g0, smem);
+  } else {
+    MT::template run<int>(src_k, nullptr, dst_k, nullptr, i0, uint32_t(i1 - i0), j0, uint32_t(j1 - j0), g0, smem);
+  }
+}
+
+}  // namespace ms

@@ -1,0 +1,119 @@
+// Plain merge sort launcher: tile sort, then merge-path passes with
+// ping-pong buffers (see ms_plan.hpp for the pass count and parity).
+#include <type_traits>
+
+#include "ms_block_sort.hpp"
+#include "ms_internal.hpp"
+#include "ms_merge.hpp"
+#include "ms_plan.hpp"
+
+namespace ms {
+
+// Lets a kernel take more than the default dynamic LDS (once per kernel).
+template <class F>
+static hipError_t allow_lds(F* kernel, size_t bytes) {
+  if (bytes <= 48 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             int(bytes));
+}
+
+// Tile and merge-tile geometry per (key width, value width).
+template <class K, class V>
+struct PlainCfg {
+  static constexpr bool PAIRS = HasVal<V>::value;
+  static constexpr bool WIDE = sizeof(K) == 8;
+  static constexpr int BS_WG = 256;
+  static constexpr int BS_IPT = (WIDE && PAIRS) ? 8 : 16;
+  static constexpr int MG_WG = 256;
+  static constexpr int MG_IPT = (WIDE || (PAIRS && sizeof(typename std::conditional<PAIRS, V, int>::type) == 8)) ? 8 : 16;
+  static constexpr int TILE = BS_WG * BS_IPT;
+  static constexpr int MTILE = MG_WG * MG_IPT;
+  static_assert((2 * TILE) % MTILE == 0, "a merge tile must never straddle two run pairs");
+};
+
+template <class K, class V>
+void plain_geometry(int* tile, int* merge_tile) {
+  *tile = PlainCfg<K, V>::TILE;
+  *merge_tile = PlainCfg<K, V>::MTILE;
+}
+
+template <class K, class V>
+size_t plain_temp_bytes(uint64_t n) {
+  using C = PlainCfg<K, V>;
+  const int P = plan_passes(n, C::TILE);
+  const size_t vb = C::PAIRS ? sizeof(typename std::conditional<C::PAIRS, V, int>::type) : 0;
+  return plain_layout(n, sizeof(K), vb, C::MTILE, P).bytes;
+}
+
+template <class K, class V>
+ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, void* ws) {
+  using C = PlainCfg<K, V>;
+  using BS = TileSort<K, V, C::BS_WG, C::BS_IPT>;
+  using MT = MergeTile<K, V, C::MG_WG, C::MG_IPT>;
+  if (n == 0) return MS_OK;
+  const int P = plan_passes(n, C::TILE);
+  const size_t vb = C::PAIRS ? sizeof(typename std::conditional<C::PAIRS, V, int>::type) : 0;
+  const PlainLayout L = plain_layout(n, sizeof(K), vb, C::MTILE, P);
+  char* w = static_cast<char*>(ws);
+  K* tk = P ? reinterpret_cast<K*>(w + L.keys_off) : nullptr;
+  V* tv = (P && C::PAIRS) ? reinterpret_cast<V*>(w + L.vals_off) : nullptr;
+  int64_t* part = P ? reinterpret_cast<int64_t*>(w + L.part_off) : nullptr;
+
+  K* cur_k = tile_sort_in_place(P) ? keys : tk;
+  V* cur_v = tile_sort_in_place(P) ? vals : tv;
+  const uint64_t tiles = ceil_div(n, C::TILE);
+  static const hipError_t lds_ok = [] {
+    hipError_t a = allow_lds(&block_sort_kernel<K, V, C::BS_WG, C::BS_IPT>, BS::LDS_BYTES);
+    hipError_t b = allow_lds(&merge_kernel<K, V, C::MG_WG, C::MG_IPT>, MT::LDS_BYTES);
+    return a != hipSuccess ? a : b;
+  }();
+  if (lds_ok != hipSuccess) return hip_fail(lds_ok, "LDS size attribute");
+  {
+    ProfScope ps(PK_BLOCK_SORT, s);
+    block_sort_kernel<K, V, C::BS_WG, C::BS_IPT>
+        <<<dim3(unsigned(tiles)), dim3(C::BS_WG), BS::LDS_BYTES, s>>>(keys, vals, cur_k, cur_v, n, ctl);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "tile sort launch");
+  const uint64_t mtiles = ceil_div(n, C::MTILE);
+  for (int p = 0; p < P; ++p) {
+    const uint64_t W = uint64_t(C::TILE) << p;
+    K* nxt_k = (cur_k == keys) ? tk : keys;
+    V* nxt_v = (cur_k == keys) ? tv : vals;
+    {
+      ProfScope ps(PK_PARTITION, s);
+      partition_kernel<K><<<dim3(unsigned(ceil_div(mtiles, 256))), dim3(256), 0, s>>>(cur_k, n, ctl, W, C::MTILE,
+                                                                                       mtiles, part);
+    }
+    {
+      ProfScope ps(PK_MERGE, s);
+      merge_kernel<K, V, C::MG_WG, C::MG_IPT>
+          <<<dim3(unsigned(mtiles)), dim3(C::MG_WG), MT::LDS_BYTES, s>>>(cur_k, cur_v, nxt_k, nxt_v, n, ctl, W, part);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "merge pass launch");
+    cur_k = nxt_k;
+    cur_v = nxt_v;
+  }
+  return MS_OK;
+}
+
+#define MS_INSTANTIATE(K, V)                                                                  \
+  template ms_status plain_sort<K, V>(K*, V*, uint64_t, DevCtl, hipStream_t, void*);         \
+  template size_t plain_temp_bytes<K, V>(uint64_t);                                           \
+  template void plain_geometry<K, V>(int*, int*);
+
+MS_INSTANTIATE(uint32_t, NoVal)
+MS_INSTANTIATE(int32_t, NoVal)
+MS_INSTANTIATE(uint64_t, NoVal)
+MS_INSTANTIATE(int64_t, NoVal)
+MS_INSTANTIATE(uint32_t, uint32_t)
+MS_INSTANTIATE(int32_t, uint32_t)
+MS_INSTANTIATE(uint64_t, uint32_t)
+MS_INSTANTIATE(int64_t, uint32_t)
+MS_INSTANTIATE(uint32_t, uint64_t)
+MS_INSTANTIATE(int32_t, uint64_t)
+MS_INSTANTIATE(uint64_t, uint64_t)
+MS_INSTANTIATE(int64_t, uint64_t)
+
+}  // namespace ms

@@ -1,0 +1,42 @@
+// Host-side planning arithmetic of the plain merge sort (no HIP calls, so it
+// is exercised by CPU tests through ms_plan_query()).
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ms {
+
+// Merge passes after the tile sort: runs of width T double each pass until
+// one run covers n, i.e. ceil(log2(ceil(n / T))) passes (0 when n <= T).
+inline int plan_passes(uint64_t n, uint64_t T) {
+  if (n <= T) return 0;
+  const uint64_t runs = (n + T - 1) / T;
+  int p = 0;
+  while ((uint64_t(1) << p) < runs) ++p;
+  return p;
+}
+
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Buffer parity: the tile sort writes the caller's buffer when the pass count
+// is even, the scratch buffer when it is odd, so that the last pass lands in
+// the caller's buffer without a copy.
+inline bool tile_sort_in_place(int passes) { return passes % 2 == 0; }
+
+// Scratch layout of one plain sort: [keys n*kb | values n*vb | partitions].
+struct PlainLayout {
+  size_t keys_off, vals_off, part_off, bytes;
+};
+
+inline PlainLayout plain_layout(uint64_t n, size_t kb, size_t vb, uint64_t merge_tile, int passes) {
+  PlainLayout L{};
+  if (passes == 0) return L;
+  L.keys_off = 0;
+  L.vals_off = align_up(n * kb, 256);
+  L.part_off = align_up(L.vals_off + n * vb, 256);
+  L.bytes = align_up(L.part_off + (ceil_div(n, merge_tile) + 1) * sizeof(int64_t), 256);
+  return L;
+}
+
+}  // namespace ms

@@ -1,0 +1,76 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/*.h declares, rejects bad arguments before touching the device, and
+plans passes as ceil(log2(ceil(n / tile)))."""
+import ctypes
+import glob
+import math
+import os
+import re
+
+import pytest
+
+import paper_2211_16479_amd as msort
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(ms_[a-z0-9_]+)\s*\(",
+                             text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(msort.LIB_PATH)
+    names = declared_functions()
+    assert "ms_sort" in names and "ms_sort_pairs" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_version():
+    L = msort.lib()
+    assert L.ms_version() >= 100
+    for s in range(6):
+        assert L.ms_status_string(s)
+    assert L.ms_status_string(99) == b"unknown status"
+
+
+def test_argument_checks_enqueue_nothing():
+    L = msort.lib()
+    # n == 0 is a no-op, even with NULL pointers
+    assert L.ms_sort(None, 0, 0, None) == 0
+    assert L.ms_sort_pairs(None, None, 0, 0, 4, None) == 0
+    # NULL with n > 0
+    assert L.ms_sort(None, 10, 0, None) == 1
+    assert b"NULL" in L.ms_last_error()
+    # unknown key type, bad value widths
+    assert L.ms_sort(ctypes.c_void_p(16), 10, 7, None) == 2
+    assert L.ms_sort_pairs(ctypes.c_void_p(16), ctypes.c_void_p(64), 10, 0, 3, None) == 2
+    assert L.ms_sort_pairs(ctypes.c_void_p(16), None, 10, 0, 4, None) == 1
+    assert L.ms_sort_pairs(ctypes.c_void_p(16), ctypes.c_void_p(16), 10, 0, 4, None) == 1
+    assert L.ms_profile_read(99, None, None) == 1
+
+
+@pytest.mark.parametrize("kt,vb", [(0, 0), (1, 4), (3, 0), (2, 8), (3, 4), (0, 8)])
+def test_plan_arithmetic(kt, vb):
+    for n in [0, 1, 2, 1000, 4095, 4096, 4097, 8192, 8193, 1 << 20, (1 << 20) + 1, 1 << 27,
+              (1 << 28) + 12345, 1 << 29]:
+        p = msort.ms_plan_query(n, kt, vb)
+        T = p["tile"]
+        assert T & (T - 1) == 0 and (2 * T) % p["merge_tile"] == 0
+        runs = max(1, math.ceil(n / T))
+        assert p["passes"] == math.ceil(math.log2(runs))
+        assert p["tile_sort_in_place"] == (p["passes"] % 2 == 0)
+        tb = msort.ms_temp_bytes(n, kt, vb)
+        if p["passes"] == 0:
+            assert tb == 0
+        else:
+            kb = 4 if kt in (0, 1) else 8
+            assert tb >= n * (kb + vb)
+    assert msort.ms_temp_bytes(100, 9, 0) == 0

@@ -1,0 +1,132 @@
+"""GPU parity of the plain merge sort (ms_sort, ms_sort_pairs) against the CPU
+oracle, element by element; full-size configurations via properties that
+determine the unique result plus oracle-sampled positions."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2211_16479_amd as msort
+import workloads
+from gpu_helpers import (as_i64, assert_equal_arrays, check_sampled_ranks,
+                         check_sorted_permutation_pairs, keys_fill, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 2, 3, 63, 64, 65, 1000, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193,
+         12289, 65537, 131071, 300_007, 1_000_003]
+DTYPES = [np.uint32, np.int32, np.uint64, np.int64]
+
+
+def gpu_sort(a: np.ndarray, dev) -> np.ndarray:
+    t = to_dev(a, dev)
+    msort.ms_sort(t)
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def gpu_sort_pairs(k: np.ndarray, v: np.ndarray, dev):
+    tk, tv = to_dev(k, dev), to_dev(v, dev)
+    msort.ms_sort_pairs(tk, tv)
+    torch.cuda.synchronize()
+    return tk.cpu().numpy(), tv.cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=lambda d: np.dtype(d).name)
+def test_sort_sizes_uniform(gpu, dtype):
+    rng = np.random.default_rng(11)
+    for n in SIZES:
+        a = keys_fill(n, dtype, "uniform", rng)
+        assert_equal_arrays(gpu_sort(a, gpu), oracle.sort(a), f"{np.dtype(dtype).name} n={n}")
+
+
+@pytest.mark.parametrize("dist", ["few", "equal", "sorted", "reverse", "extremes"])
+@pytest.mark.parametrize("dtype", DTYPES, ids=lambda d: np.dtype(d).name)
+def test_sort_distributions(gpu, dtype, dist):
+    rng = np.random.default_rng(12)
+    for n in (4097, 70_001):
+        a = keys_fill(n, dtype, dist, rng)
+        assert_equal_arrays(gpu_sort(a, gpu), oracle.sort(a), f"{dist} n={n}")
+
+
+@pytest.mark.parametrize("kdt,vdt", [(np.uint32, np.uint32), (np.int32, np.uint32), (np.uint32, np.uint64),
+                                     (np.int64, np.uint32), (np.uint64, np.uint64), (np.int64, np.uint64)],
+                         ids=lambda d: np.dtype(d).name)
+def test_pairs_stable_with_ties(gpu, kdt, vdt):
+    rng = np.random.default_rng(13)
+    for n in (1, 5, 4096, 4097, 9000, 100_003):
+        for dist in ("few", "uniform", "equal"):
+            k = keys_fill(n, kdt, dist, rng)
+            v = np.arange(n, dtype=vdt) * 3 + 1
+            gk, gv = gpu_sort_pairs(k, v, gpu)
+            ek, ev = oracle.sort_pairs(k, v)
+            assert_equal_arrays(gk, ek, f"pairs keys {dist} n={n}")
+            assert_equal_arrays(gv, ev, f"pairs vals {dist} n={n}")
+
+
+def test_config_uniform_u32_2p20_seed0(gpu):
+    keys = workloads.uniform_u32(1 << 20, seed=0).numpy()
+    assert_equal_arrays(gpu_sort(keys, gpu), oracle.sort(keys), "2^20 uniform u32")
+
+
+def test_zipf_pairs_reduced(gpu):
+    k, v = workloads.zipf_pairs_u32(1 << 22, seed=0)
+    gk, gv = gpu_sort_pairs(k.numpy(), v.numpy(), gpu)
+    ek, ev = oracle.sort_pairs(k.numpy(), v.numpy())
+    assert_equal_arrays(gk, ek, "zipf keys")
+    assert_equal_arrays(gv, ev, "zipf vals")
+
+
+def test_normal_i64_and_nearly_sorted_reduced(gpu):
+    a = workloads.normal_i64(1 << 22, seed=0)
+    b = workloads.nearly_sorted(torch.sort(a).values, 0.01, seed=0)
+    ga, gb = gpu_sort(a.numpy(), gpu), gpu_sort(b.numpy(), gpu)
+    ea = oracle.sort(a.numpy())
+    assert_equal_arrays(ga, ea, "normal i64")
+    assert_equal_arrays(gb, ea, "nearly sorted i64 (same multiset)")
+
+
+def test_repeat_runs_identical(gpu):
+    k, v = workloads.zipf_pairs_u32(1 << 21, seed=3, distinct=5000)
+    outs = []
+    for _ in range(3):
+        tk, tv = k.to(gpu), v.to(gpu)
+        msort.ms_sort_pairs(tk, tv)
+        torch.cuda.synchronize()
+        outs.append((tk.cpu().numpy(), tv.cpu().numpy()))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
+def test_full_zipf_pairs_2p27(gpu):
+    """The benchmark workload at full size: 2^27 Zipf(1.1) pairs, value = index."""
+    k, v = workloads.zipf_pairs_u32(1 << 27, seed=0, device=gpu)
+    ok, ov = k.clone(), v.clone()
+    msort.ms_sort_pairs(ok, ov)
+    torch.cuda.synchronize()
+    check_sorted_permutation_pairs(k, ok, ov)
+    check_sampled_ranks(k.cpu().numpy(), ok.cpu().numpy(), samples=24, seed=1)
+
+
+def test_full_normal_i64_2p28_both_arrays(gpu):
+    a = workloads.normal_i64(1 << 28, seed=0, device=gpu)
+    ref = torch.sort(a).values                     # library cross-check on the GPU
+    b = workloads.nearly_sorted(ref, 0.01, seed=0)
+    oa, ob = a.clone(), b.clone()
+    msort.ms_sort(oa)
+    msort.ms_sort(ob)
+    torch.cuda.synchronize()
+    assert bool((oa == ref).all()), "random int64 array: differs from the sorted multiset"
+    assert bool((ob == oa).all()), "nearly sorted array: output differs from the random array's"
+    check_sampled_ranks(a.cpu().numpy(), oa.cpu().numpy(), samples=12, seed=2)
+
+
+def test_full_uniform_u32_2p27_keys(gpu):
+    """2^27 uint32 keys-only (the merge-pass bandwidth workload)."""
+    a = workloads.uniform_u32(1 << 27, seed=0, device=gpu)
+    o = a.clone()
+    msort.ms_sort(o)
+    torch.cuda.synchronize()
+    ref = torch.sort(as_i64(a)).values
+    assert bool((as_i64(o) == ref).all())
+    check_sampled_ranks(a.cpu().numpy(), o.cpu().numpy(), samples=12, seed=3)
