@@ -98,26 +98,29 @@ template <class IT, int WG, int N, class T>
 __device__ __forceinline__ void lds_merge_level(T (&v)[N], T* lds, int R) {
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int r = 0; r < N; ++r) lds[tid * N + r] = v[r];
+  for (int r = 0; r < N; ++r) lds[lds_pad(tid * N + r)] = v[r];
   __syncthreads();
   const int per_blk = (2 * R) / N;  // threads per merged run
   const int blk = tid / per_blk;
   const int d = (tid - blk * per_blk) * N;
-  const T* A = lds + blk * 2 * R;
-  const T* B = A + R;
+  const uint32_t a0 = blk * 2 * R, b0 = a0 + R;  // runs A and B (through lds_pad)
   int lo = d > R ? d - R : 0, hi = d < R ? d : R;
   while (lo < hi) {
     const int m = (lo + hi) >> 1;
-    if (IT::less(B[d - 1 - m], A[m])) hi = m; else lo = m + 1;
+    if (IT::less(lds[lds_pad(b0 + d - 1 - m)], lds[lds_pad(a0 + m)])) hi = m; else lo = m + 1;
   }
   int i = lo, j = d - lo;
-  T a = A[i < R ? i : R - 1], b = B[j < R ? j : R - 1];
+  T a = lds[lds_pad(a0 + (i < R ? i : R - 1))], b = lds[lds_pad(b0 + (j < R ? j : R - 1))];
 #pragma unroll
   for (int r = 0; r < N; ++r) {
     const bool take_b = (j < R) && (i >= R || IT::less(b, a));
     v[r] = take_b ? b : a;
-    if (take_b) { ++j; b = B[j < R ? j : R - 1]; }
-    else { ++i; a = A[i < R ? i : R - 1]; }
+    i += take_b ? 0 : 1;
+    j += take_b ? 1 : 0;
+    const uint32_t nx = take_b ? b0 + (j < R ? j : R - 1) : a0 + (i < R ? i : R - 1);
+    const T x = lds[lds_pad(nx)];
+    a = take_b ? a : x;
+    b = take_b ? x : b;
   }
   __syncthreads();
 }
@@ -131,7 +134,7 @@ struct TileSort {
   static constexpr int NW = WG / 64;
   static_assert(WG % 64 == 0 && (WG & (WG - 1)) == 0 && WG <= 1024, "WG");
   static_assert((IPT & (IPT - 1)) == 0 && IPT >= 2 && IPT <= 32, "IPT");
-  static constexpr size_t LDS_ITEMS = (NW > 1) ? sizeof(T) * TILE : 0;
+  static constexpr size_t LDS_ITEMS = (NW > 1) ? (sizeof(T) * lds_padded_size(TILE) + 15) / 16 * 16 : 0;
   static constexpr size_t LDS_VALS = PAIRS ? sizeof(typename std::conditional<PAIRS, V, int>::type) * TILE : 0;
   static constexpr size_t LDS_BYTES = LDS_ITEMS + LDS_VALS;
 
@@ -145,7 +148,17 @@ struct TileSort {
     T* lds = reinterpret_cast<T*>(smem);
     VV* lds_v = reinterpret_cast<VV*>(smem + LDS_ITEMS);
     if constexpr (PAIRS) {
-      for (uint32_t e = tid; e < len; e += WG) lds_v[e] = in_v[e];
+      VV vv[IPT];
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const uint32_t e = uint32_t(tid) + uint32_t(r) * WG;
+        if (e < len) vv[r] = in_v[e];
+      }
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const uint32_t e = uint32_t(tid) + uint32_t(r) * WG;
+        if (e < len) lds_v[e] = vv[r];
+      }
     }
     T v[IPT];
     const uint32_t e0 = uint32_t(tid) * IPT;

@@ -65,8 +65,9 @@ template <class K, class V, int WG, int IPT>
 struct MergeTile {
   static constexpr bool PAIRS = HasVal<V>::value;
   static constexpr int TM = WG * IPT;
-  static constexpr size_t LDS_KEYS = sizeof(K) * TM;
-  static constexpr size_t LDS_BYTES = LDS_KEYS + (PAIRS ? sizeof(typename std::conditional<PAIRS, V, int>::type) * TM : 0);
+  static constexpr size_t LDS_KEYS = (sizeof(K) * lds_padded_size(TM) + 15) / 16 * 16;
+  static constexpr size_t LDS_BYTES =
+      LDS_KEYS + (PAIRS ? sizeof(typename std::conditional<PAIRS, V, int>::type) * lds_padded_size(TM) : 0);
 
   // Merge A = src[a0, a0+la) and B = src[b0, b0+lb) (la + lb <= TM) into
   // dst[o0, o0+la+lb); A's elements win ties.
@@ -79,35 +80,73 @@ struct MergeTile {
     K* sk = reinterpret_cast<K*>(smem);
     VV* sv = reinterpret_cast<VV*>(smem + LDS_KEYS);
     const uint32_t total = la + lb;
-    // coalesced staging of both pieces, A then B
-    for (uint32_t e = tid; e < total; e += WG) {
-      const uint64_t g = e < la ? a0 + e : b0 + (e - la);
-      sk[e] = src_k[g];
-      if constexpr (PAIRS) sv[e] = src_v[g];
+    // coalesced staging of both pieces, A then B: all IPT loads of a thread
+    // are issued before any of them is waited on
+    if (total == uint32_t(TM)) {  // full tile (workgroup-uniform): no predicates
+      K kv[IPT];
+      VV vv[PAIRS ? IPT : 1];
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const uint32_t e = uint32_t(tid) + uint32_t(r) * WG;
+        const uint64_t g = e < la ? a0 + e : b0 + (e - la);
+        kv[r] = src_k[g];
+        if constexpr (PAIRS) vv[r] = src_v[g];
+      }
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const uint32_t e = uint32_t(tid) + uint32_t(r) * WG;
+        sk[lds_pad(e)] = kv[r];
+        if constexpr (PAIRS) sv[lds_pad(e)] = vv[r];
+      }
+    } else {
+      K kv[IPT];
+      VV vv[PAIRS ? IPT : 1];
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const uint32_t e = uint32_t(tid) + uint32_t(r) * WG;
+        if (e < total) {
+          const uint64_t g = e < la ? a0 + e : b0 + (e - la);
+          kv[r] = src_k[g];
+          if constexpr (PAIRS) vv[r] = src_v[g];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const uint32_t e = uint32_t(tid) + uint32_t(r) * WG;
+        if (e < total) {
+          sk[lds_pad(e)] = kv[r];
+          if constexpr (PAIRS) sv[lds_pad(e)] = vv[r];
+        }
+      }
     }
     __syncthreads();
     const uint32_t d = uint32_t(tid) * IPT;
     if (d >= total) return;
-    const K* A = sk;
-    const K* B = sk + la;
+    // A is sk[0, la), B is sk[la, total), both through lds_pad
     uint32_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
     while (lo < hi) {
       const uint32_t m = (lo + hi) >> 1;
-      if (B[d - 1 - m] < A[m]) hi = m; else lo = m + 1;
+      if (sk[lds_pad(la + d - 1 - m)] < sk[lds_pad(m)]) hi = m; else lo = m + 1;
     }
     uint32_t i = lo, j = d - lo;
     const uint32_t last = total - 1;
-    K a = sk[i < last ? i : last];
-    K b = sk[la + j < last ? la + j : last];
+    K a = sk[lds_pad(i < last ? i : last)];
+    K b = sk[lds_pad(la + j < last ? la + j : last)];
     K ko[IPT];
     uint32_t src_idx[IPT];
+    // branch-free serial merge: one LDS read per output, at the index of the
+    // side that was just consumed
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
       const bool take_b = (j < lb) && (i >= la || b < a);
       ko[r] = take_b ? b : a;
       src_idx[r] = take_b ? la + j : i;
-      if (take_b) { ++j; const uint32_t x = la + j; b = sk[x < last ? x : last]; }
-      else { ++i; a = sk[i < last ? i : last]; }
+      i += take_b ? 0u : 1u;
+      j += take_b ? 1u : 0u;
+      const uint32_t nx = take_b ? la + j : i;
+      const K x = sk[lds_pad(nx < last ? nx : last)];
+      a = take_b ? a : x;
+      b = take_b ? x : b;
     }
     const uint32_t cnt = total - d < uint32_t(IPT) ? total - d : uint32_t(IPT);
     K* out = dst_k + o0 + d;
@@ -121,7 +160,7 @@ struct MergeTile {
     if constexpr (PAIRS) {
       VV vo[IPT];
 #pragma unroll
-      for (int r = 0; r < IPT; ++r) vo[r] = sv[src_idx[r] < last ? src_idx[r] : last];
+      for (int r = 0; r < IPT; ++r) vo[r] = sv[lds_pad(src_idx[r] < last ? src_idx[r] : last)];
       VV* ov = dst_v + o0 + d;
       if (cnt == IPT && (reinterpret_cast<uintptr_t>(ov) & 15) == 0) {
         store_run<VV, IPT>(ov, vo);
