@@ -94,11 +94,11 @@ __device__ __forceinline__ void wave_merges(T (&v)[N], int lane) {
 
 // One LDS merge-path level: sorted runs of R items (blocked in registers
 // across the workgroup) become runs of 2R.  lds must hold WG*N items.
-template <class IT, int WG, int N, class T>
+template <class IT, int WG, int PAD, int N, class T>
 __device__ __forceinline__ void lds_merge_level(T (&v)[N], T* lds, int R) {
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int r = 0; r < N; ++r) lds[lds_pad(tid * N + r)] = v[r];
+  for (int r = 0; r < N; ++r) lds[lds_pad<PAD>(tid * N + r)] = v[r];
   __syncthreads();
   const int per_blk = (2 * R) / N;  // threads per merged run
   const int blk = tid / per_blk;
@@ -107,10 +107,10 @@ __device__ __forceinline__ void lds_merge_level(T (&v)[N], T* lds, int R) {
   int lo = d > R ? d - R : 0, hi = d < R ? d : R;
   while (lo < hi) {
     const int m = (lo + hi) >> 1;
-    if (IT::less(lds[lds_pad(b0 + d - 1 - m)], lds[lds_pad(a0 + m)])) hi = m; else lo = m + 1;
+    if (IT::less(lds[lds_pad<PAD>(b0 + d - 1 - m)], lds[lds_pad<PAD>(a0 + m)])) hi = m; else lo = m + 1;
   }
   int i = lo, j = d - lo;
-  T a = lds[lds_pad(a0 + (i < R ? i : R - 1))], b = lds[lds_pad(b0 + (j < R ? j : R - 1))];
+  T a = lds[lds_pad<PAD>(a0 + (i < R ? i : R - 1))], b = lds[lds_pad<PAD>(b0 + (j < R ? j : R - 1))];
 #pragma unroll
   for (int r = 0; r < N; ++r) {
     const bool take_b = (j < R) && (i >= R || IT::less(b, a));
@@ -118,14 +118,14 @@ __device__ __forceinline__ void lds_merge_level(T (&v)[N], T* lds, int R) {
     i += take_b ? 0 : 1;
     j += take_b ? 1 : 0;
     const uint32_t nx = take_b ? b0 + (j < R ? j : R - 1) : a0 + (i < R ? i : R - 1);
-    const T x = lds[lds_pad(nx)];
+    const T x = lds[lds_pad<PAD>(nx)];
     a = take_b ? a : x;
     b = take_b ? x : b;
   }
   __syncthreads();
 }
 
-template <class K, class V, int WG, int IPT>
+template <class K, class V, int WG, int IPT, int PAD>
 struct TileSort {
   static constexpr bool PAIRS = HasVal<V>::value;
   using IT = Item<K, PAIRS>;
@@ -134,7 +134,7 @@ struct TileSort {
   static constexpr int NW = WG / 64;
   static_assert(WG % 64 == 0 && (WG & (WG - 1)) == 0 && WG <= 1024, "WG");
   static_assert((IPT & (IPT - 1)) == 0 && IPT >= 2 && IPT <= 32, "IPT");
-  static constexpr size_t LDS_ITEMS = (NW > 1) ? (sizeof(T) * lds_padded_size(TILE) + 15) / 16 * 16 : 0;
+  static constexpr size_t LDS_ITEMS = (NW > 1) ? (sizeof(T) * lds_padded_size<PAD>(TILE) + 15) / 16 * 16 : 0;
   static constexpr size_t LDS_VALS = PAIRS ? sizeof(typename std::conditional<PAIRS, V, int>::type) * TILE : 0;
   static constexpr size_t LDS_BYTES = LDS_ITEMS + LDS_VALS;
 
@@ -182,7 +182,7 @@ struct TileSort {
       // all loads of this tile are done before the first barrier, so the
       // output may overwrite the input in place
 #pragma unroll
-      for (int R = 64 * IPT; R < TILE; R *= 2) lds_merge_level<IT, WG>(v, lds, R);
+      for (int R = 64 * IPT; R < TILE; R *= 2) lds_merge_level<IT, WG, PAD>(v, lds, R);
     } else {
       __syncthreads();
     }
@@ -219,10 +219,10 @@ struct TileSort {
 };
 
 // One workgroup per tile of the array: tiles [t*TILE, min(n, (t+1)*TILE)).
-template <class K, class V, int WG, int IPT>
+template <class K, class V, int WG, int IPT, int PAD>
 __global__ __launch_bounds__(WG) void block_sort_kernel(const K* in_k, const V* in_v, K* out_k, V* out_v,
                                                         uint64_t n_host, DevCtl ctl) {
-  using TS = TileSort<K, V, WG, IPT>;
+  using TS = TileSort<K, V, WG, IPT, PAD>;
   extern __shared__ __align__(16) unsigned char smem[];
   if (gated_off(ctl)) return;
   const uint64_t n = live_n(ctl, n_host);

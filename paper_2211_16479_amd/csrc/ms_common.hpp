@@ -137,8 +137,15 @@ __host__ __device__ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x
 // LDS index with one pad slot every 32 elements.  Merge-path threads read
 // positions about IPT/2 apart, and blocked writes are IPT apart; with power-of-
 // two strides those land in a few of the 64 LDS banks.  The pad spreads them.
-__host__ __device__ constexpr uint32_t lds_pad(uint32_t e) { return e + (e >> 5); }
-__host__ __device__ constexpr uint32_t lds_padded_size(uint32_t n) { return n + (n >> 5) + 1; }
+// LDS index with one pad slot every 2^S elements (S = 0: no padding).
+template <int S>
+__host__ __device__ constexpr uint32_t lds_pad(uint32_t e) {
+  return S ? e + (e >> S) : e;
+}
+template <int S>
+__host__ __device__ constexpr uint32_t lds_padded_size(uint32_t n) {
+  return S ? n + (n >> S) + 1 : n;
+}
 
 // Vector store of N consecutive 32- or 64-bit elements when the address is
 // aligned for it; element count N is a compile-time multiple of the vector.

@@ -46,28 +46,77 @@ __device__ __forceinline__ uint64_t merge_path_split(const K* A, uint64_t la, co
   return lo;
 }
 
-template <class K>
+// One search per merge tile.  G = 1: one thread runs the binary search.
+// G > 1: G lanes cooperate on one diagonal; each round they probe G evenly
+// spaced positions of the remaining interval [lo, hi) and a ballot picks the
+// sub-interval holding the split, so the interval shrinks by G + 1 per round
+// (fewer dependent global loads).  Both use the same predicate:
+// split <= m  iff  B[d-1-m] < A[m].
+template <class K, int G>
 __global__ __launch_bounds__(256) void partition_kernel(const K* __restrict__ src, uint64_t n_host, DevCtl ctl,
                                                         uint64_t W, uint32_t Tm, uint64_t num_tiles,
                                                         int64_t* __restrict__ part) {
+  static_assert(G >= 1 && G <= 64 && (64 % G) == 0, "group size");
   if (gated_off(ctl)) return;
   const uint64_t n = live_n(ctl, n_host);
-  const uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k >= num_tiles) return;
-  const uint64_t g = k * Tm;
-  if (g >= n) return;
-  const PassGeom q = pass_geom(g, n, W);
-  const uint64_t i = merge_path_split(src + q.pb, q.a_end - q.pb, src + q.a_end, q.b_end - q.a_end, g - q.pb);
-  part[k] = int64_t(q.pb + i);
+  const uint64_t gid = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const uint64_t k = gid / G;
+  if constexpr (G == 1) {
+    if (k >= num_tiles) return;
+    const uint64_t g = k * Tm;
+    if (g >= n) return;
+    const PassGeom q = pass_geom(g, n, W);
+    const uint64_t i = merge_path_split(src + q.pb, q.a_end - q.pb, src + q.a_end, q.b_end - q.a_end, g - q.pb);
+    part[k] = int64_t(q.pb + i);
+  } else {
+    const uint32_t q = uint32_t(gid % G);
+    const uint32_t gshift = (__lane_id() / G) * G;
+    const bool valid = k < num_tiles && k * Tm < n;
+    uint64_t lo = 0, hi = 0, d = 0;
+    const K* A = src;
+    const K* B = src;
+    PassGeom geo{0, 0, 0};
+    if (valid) {
+      geo = pass_geom(k * Tm, n, W);
+      const uint64_t la = geo.a_end - geo.pb, lb = geo.b_end - geo.a_end;
+      d = k * Tm - geo.pb;
+      A = src + geo.pb;
+      B = src + geo.a_end;
+      lo = d > lb ? d - lb : 0;
+      hi = d < la ? d : la;
+    }
+    while (true) {
+      const bool active = valid && lo < hi;
+      if (!__any(active)) break;
+      const uint64_t len = hi - lo;
+      const bool small = len <= G;
+      const uint64_t m = small ? lo + q : lo + ((q + 1) * len) / (G + 1);
+      const bool probe = active && (!small || q < len);
+      const bool pred = probe && (B[d - 1 - m] < A[m]);
+      const uint32_t gm = uint32_t((__ballot(pred) >> gshift) & ((G == 64) ? ~0ull : ((1ull << G) - 1)));
+      if (active) {
+        if (small) {
+          lo = hi = lo + (gm ? uint64_t(__builtin_ctz(gm)) : len);
+        } else if (gm == 0) {
+          lo = lo + (uint64_t(G) * len) / (G + 1) + 1;
+        } else {
+          const uint32_t f = __builtin_ctz(gm);
+          hi = lo + ((f + 1) * len) / (G + 1);
+          lo = f ? lo + (uint64_t(f) * len) / (G + 1) + 1 : lo;
+        }
+      }
+    }
+    if (valid && q == 0) part[k] = int64_t(geo.pb + lo);
+  }
 }
 
-template <class K, class V, int WG, int IPT>
+template <class K, class V, int WG, int IPT, int PAD>
 struct MergeTile {
   static constexpr bool PAIRS = HasVal<V>::value;
   static constexpr int TM = WG * IPT;
-  static constexpr size_t LDS_KEYS = (sizeof(K) * lds_padded_size(TM) + 15) / 16 * 16;
+  static constexpr size_t LDS_KEYS = (sizeof(K) * lds_padded_size<PAD>(TM) + 15) / 16 * 16;
   static constexpr size_t LDS_BYTES =
-      LDS_KEYS + (PAIRS ? sizeof(typename std::conditional<PAIRS, V, int>::type) * lds_padded_size(TM) : 0);
+      LDS_KEYS + (PAIRS ? sizeof(typename std::conditional<PAIRS, V, int>::type) * lds_padded_size<PAD>(TM) : 0);
 
   // Merge A = src[a0, a0+la) and B = src[b0, b0+lb) (la + lb <= TM) into
   // dst[o0, o0+la+lb); A's elements win ties.
@@ -95,8 +144,8 @@ struct MergeTile {
 #pragma unroll
       for (int r = 0; r < IPT; ++r) {
         const uint32_t e = uint32_t(tid) + uint32_t(r) * WG;
-        sk[lds_pad(e)] = kv[r];
-        if constexpr (PAIRS) sv[lds_pad(e)] = vv[r];
+        sk[lds_pad<PAD>(e)] = kv[r];
+        if constexpr (PAIRS) sv[lds_pad<PAD>(e)] = vv[r];
       }
     } else {
       K kv[IPT];
@@ -114,8 +163,8 @@ struct MergeTile {
       for (int r = 0; r < IPT; ++r) {
         const uint32_t e = uint32_t(tid) + uint32_t(r) * WG;
         if (e < total) {
-          sk[lds_pad(e)] = kv[r];
-          if constexpr (PAIRS) sv[lds_pad(e)] = vv[r];
+          sk[lds_pad<PAD>(e)] = kv[r];
+          if constexpr (PAIRS) sv[lds_pad<PAD>(e)] = vv[r];
         }
       }
     }
@@ -126,12 +175,12 @@ struct MergeTile {
     uint32_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
     while (lo < hi) {
       const uint32_t m = (lo + hi) >> 1;
-      if (sk[lds_pad(la + d - 1 - m)] < sk[lds_pad(m)]) hi = m; else lo = m + 1;
+      if (sk[lds_pad<PAD>(la + d - 1 - m)] < sk[lds_pad<PAD>(m)]) hi = m; else lo = m + 1;
     }
     uint32_t i = lo, j = d - lo;
     const uint32_t last = total - 1;
-    K a = sk[lds_pad(i < last ? i : last)];
-    K b = sk[lds_pad(la + j < last ? la + j : last)];
+    K a = sk[lds_pad<PAD>(i < last ? i : last)];
+    K b = sk[lds_pad<PAD>(la + j < last ? la + j : last)];
     K ko[IPT];
     uint32_t src_idx[IPT];
     // branch-free serial merge: one LDS read per output, at the index of the
@@ -144,7 +193,7 @@ struct MergeTile {
       i += take_b ? 0u : 1u;
       j += take_b ? 1u : 0u;
       const uint32_t nx = take_b ? la + j : i;
-      const K x = sk[lds_pad(nx < last ? nx : last)];
+      const K x = sk[lds_pad<PAD>(nx < last ? nx : last)];
       a = take_b ? a : x;
       b = take_b ? x : b;
     }
@@ -160,7 +209,7 @@ struct MergeTile {
     if constexpr (PAIRS) {
       VV vo[IPT];
 #pragma unroll
-      for (int r = 0; r < IPT; ++r) vo[r] = sv[lds_pad(src_idx[r] < last ? src_idx[r] : last)];
+      for (int r = 0; r < IPT; ++r) vo[r] = sv[lds_pad<PAD>(src_idx[r] < last ? src_idx[r] : last)];
       VV* ov = dst_v + o0 + d;
       if (cnt == IPT && (reinterpret_cast<uintptr_t>(ov) & 15) == 0) {
         store_run<VV, IPT>(ov, vo);
@@ -173,12 +222,12 @@ struct MergeTile {
   }
 };
 
-template <class K, class V, int WG, int IPT>
+template <class K, class V, int WG, int IPT, int PAD>
 __global__ __launch_bounds__(WG) void merge_kernel(const K* __restrict__ src_k, const V* __restrict__ src_v,
                                                    K* __restrict__ dst_k, V* __restrict__ dst_v,
                                                    uint64_t n_host, DevCtl ctl, uint64_t W,
                                                    const int64_t* __restrict__ part) {
-  using MT = MergeTile<K, V, WG, IPT>;
+  using MT = MergeTile<K, V, WG, IPT, PAD>;
   extern __shared__ __align__(16) unsigned char smem[];
   if (gated_off(ctl)) return;
   const uint64_t n = live_n(ctl, n_host);

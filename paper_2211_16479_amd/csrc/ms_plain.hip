@@ -6,6 +6,7 @@
 #include "ms_internal.hpp"
 #include "ms_merge.hpp"
 #include "ms_plan.hpp"
+#include "ms_plain_cfg.hpp"
 
 namespace ms {
 
@@ -16,20 +17,6 @@ static hipError_t allow_lds(F* kernel, size_t bytes) {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                              int(bytes));
 }
-
-// Tile and merge-tile geometry per (key width, value width).
-template <class K, class V>
-struct PlainCfg {
-  static constexpr bool PAIRS = HasVal<V>::value;
-  static constexpr bool WIDE = sizeof(K) == 8;
-  static constexpr int BS_WG = 256;
-  static constexpr int BS_IPT = (WIDE && PAIRS) ? 8 : 16;
-  static constexpr int MG_WG = 256;
-  static constexpr int MG_IPT = (WIDE || (PAIRS && sizeof(typename std::conditional<PAIRS, V, int>::type) == 8)) ? 8 : 16;
-  static constexpr int TILE = BS_WG * BS_IPT;
-  static constexpr int MTILE = MG_WG * MG_IPT;
-  static_assert((2 * TILE) % MTILE == 0, "a merge tile must never straddle two run pairs");
-};
 
 template <class K, class V>
 void plain_geometry(int* tile, int* merge_tile) {
@@ -48,8 +35,8 @@ size_t plain_temp_bytes(uint64_t n) {
 template <class K, class V>
 ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, void* ws) {
   using C = PlainCfg<K, V>;
-  using BS = TileSort<K, V, C::BS_WG, C::BS_IPT>;
-  using MT = MergeTile<K, V, C::MG_WG, C::MG_IPT>;
+  using BS = TileSort<K, V, C::BS_WG, C::BS_IPT, C::BS_PAD>;
+  using MT = MergeTile<K, V, C::MG_WG, C::MG_IPT, C::MG_PAD>;
   if (n == 0) return MS_OK;
   const int P = plan_passes(n, C::TILE);
   const size_t vb = C::PAIRS ? sizeof(typename std::conditional<C::PAIRS, V, int>::type) : 0;
@@ -63,14 +50,14 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
   V* cur_v = tile_sort_in_place(P) ? vals : tv;
   const uint64_t tiles = ceil_div(n, C::TILE);
   static const hipError_t lds_ok = [] {
-    hipError_t a = allow_lds(&block_sort_kernel<K, V, C::BS_WG, C::BS_IPT>, BS::LDS_BYTES);
-    hipError_t b = allow_lds(&merge_kernel<K, V, C::MG_WG, C::MG_IPT>, MT::LDS_BYTES);
+    hipError_t a = allow_lds(&block_sort_kernel<K, V, C::BS_WG, C::BS_IPT, C::BS_PAD>, BS::LDS_BYTES);
+    hipError_t b = allow_lds(&merge_kernel<K, V, C::MG_WG, C::MG_IPT, C::MG_PAD>, MT::LDS_BYTES);
     return a != hipSuccess ? a : b;
   }();
   if (lds_ok != hipSuccess) return hip_fail(lds_ok, "LDS size attribute");
   {
     ProfScope ps(PK_BLOCK_SORT, s);
-    block_sort_kernel<K, V, C::BS_WG, C::BS_IPT>
+    block_sort_kernel<K, V, C::BS_WG, C::BS_IPT, C::BS_PAD>
         <<<dim3(unsigned(tiles)), dim3(C::BS_WG), BS::LDS_BYTES, s>>>(keys, vals, cur_k, cur_v, n, ctl);
   }
   hipError_t e = hipGetLastError();
@@ -82,12 +69,12 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
     V* nxt_v = (cur_k == keys) ? tv : vals;
     {
       ProfScope ps(PK_PARTITION, s);
-      partition_kernel<K><<<dim3(unsigned(ceil_div(mtiles, 256))), dim3(256), 0, s>>>(cur_k, n, ctl, W, C::MTILE,
-                                                                                       mtiles, part);
+      partition_kernel<K, MS_PART_G><<<dim3(unsigned(ceil_div(mtiles * MS_PART_G, 256))), dim3(256), 0, s>>>(
+          cur_k, n, ctl, W, C::MTILE, mtiles, part);
     }
     {
       ProfScope ps(PK_MERGE, s);
-      merge_kernel<K, V, C::MG_WG, C::MG_IPT>
+      merge_kernel<K, V, C::MG_WG, C::MG_IPT, C::MG_PAD>
           <<<dim3(unsigned(mtiles)), dim3(C::MG_WG), MT::LDS_BYTES, s>>>(cur_k, cur_v, nxt_k, nxt_v, n, ctl, W, part);
     }
     e = hipGetLastError();

@@ -1,0 +1,84 @@
+// Tile shapes of the plain merge sort.
+#pragma once
+#include <type_traits>
+
+#include "ms_common.hpp"
+
+namespace ms {
+
+// Tile and merge-tile geometry per (key width, value width): workgroup size,
+// items per thread and LDS pad shift of the tile sort (BS_*) and of the
+// merge pass (MG_*).  Compile-time knobs, so that shapes can be swept by
+// building with -D overrides; the defaults are the fastest shapes measured
+// on MI355X.  Suffixes: K = 32-bit keys only, P = 32-bit keys with values,
+// W = 64-bit keys.
+#ifndef MS_PART_G
+#define MS_PART_G 1  // lanes per partition search (1 = binary search)
+#endif
+#ifndef MS_BS_WG_K
+#define MS_BS_WG_K 1024
+#endif
+#ifndef MS_BS_IPT_K
+#define MS_BS_IPT_K 16
+#endif
+#ifndef MS_BS_PAD_K
+#define MS_BS_PAD_K 0
+#endif
+#ifndef MS_MG_WG_K
+#define MS_MG_WG_K 256
+#endif
+#ifndef MS_MG_IPT_K
+#define MS_MG_IPT_K 8
+#endif
+#ifndef MS_MG_PAD_K
+#define MS_MG_PAD_K 0
+#endif
+#ifndef MS_BS_WG_P
+#define MS_BS_WG_P 256
+#endif
+#ifndef MS_BS_IPT_P
+#define MS_BS_IPT_P 16
+#endif
+#ifndef MS_BS_PAD_P
+#define MS_BS_PAD_P 5
+#endif
+#ifndef MS_MG_WG_P
+#define MS_MG_WG_P 512
+#endif
+#ifndef MS_MG_IPT_P
+#define MS_MG_IPT_P 8
+#endif
+#ifndef MS_MG_PAD_P
+#define MS_MG_PAD_P 5
+#endif
+#ifndef MS_BS_WG_W
+#define MS_BS_WG_W 256
+#endif
+#ifndef MS_BS_IPT_W
+#define MS_BS_IPT_W 16
+#endif
+#ifndef MS_MG_WG_W
+#define MS_MG_WG_W 256
+#endif
+#ifndef MS_MG_IPT_W
+#define MS_MG_IPT_W 8
+#endif
+#ifndef MS_PAD_W
+#define MS_PAD_W 5
+#endif
+template <class K, class V>
+struct PlainCfg {
+  static constexpr bool PAIRS = HasVal<V>::value;
+  static constexpr bool WIDE = sizeof(K) == 8;
+  static constexpr int BS_WG = WIDE ? MS_BS_WG_W : (PAIRS ? MS_BS_WG_P : MS_BS_WG_K);
+  static constexpr int BS_IPT = WIDE ? (PAIRS ? 8 : MS_BS_IPT_W) : (PAIRS ? MS_BS_IPT_P : MS_BS_IPT_K);
+  static constexpr int BS_PAD = WIDE ? MS_PAD_W : (PAIRS ? MS_BS_PAD_P : MS_BS_PAD_K);
+  static constexpr int MG_WG = WIDE ? MS_MG_WG_W : (PAIRS ? MS_MG_WG_P : MS_MG_WG_K);
+  static constexpr int MG_IPT = WIDE ? MS_MG_IPT_W : (PAIRS ? MS_MG_IPT_P : MS_MG_IPT_K);
+  static constexpr int MG_PAD = WIDE ? MS_PAD_W : (PAIRS ? MS_MG_PAD_P : MS_MG_PAD_K);
+  static constexpr int TILE = BS_WG * BS_IPT;
+  static constexpr int MTILE = MG_WG * MG_IPT;
+  static_assert((2 * TILE) % MTILE == 0, "a merge tile must never straddle two run pairs");
+};
+
+}  // namespace ms
