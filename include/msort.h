@@ -90,6 +90,63 @@ ms_status ms_sort_pairs(void* d_keys, void* d_vals, size_t n, ms_key_type kt, si
                         void* stream);
 
 /*
+ * ms_segmented_sort -- sort many independent arrays with one graph launch.
+ *   d_keys          : n_total keys of type kt; segment s is
+ *                     d_keys[d_offsets[s], d_offsets[s+1]) and is sorted in
+ *                     place, ascending and stable, independently of the others.
+ *   d_vals          : NULL when val_bytes == 0 (keys only), otherwise n_total
+ *                     values of val_bytes (4 or 8) bytes moved with their keys.
+ *   d_offsets       : device array of num_segments + 1 int64 offsets,
+ *                     non-decreasing, d_offsets[0] == 0 and
+ *                     d_offsets[num_segments] == n_total.  Empty segments are
+ *                     allowed.  The library does not check these conditions
+ *                     (they live on the device); violating them is undefined.
+ *   max_segment_len : an upper bound on every segment's length, or 0 if
+ *                     unknown (then n_total is used).  It only sets how many
+ *                     merge passes the captured graph contains; a bound that
+ *                     is too small gives unsorted output for longer segments.
+ * Segments are binned by length on the device into small classes, each sorted
+ * by a persistent kernel entirely in LDS (per-class workgroup size and items
+ * per thread from the tuning table), and a large class sorted by tiles plus
+ * merge passes that stay inside the segment.  The whole pipeline is captured
+ * once into a hipGraph (cached per device, stream, pointers, sizes and tuning
+ * table; up to 8 graphs, each owning its scratch) and replayed with one
+ * hipGraphLaunch on `stream`.  This is the batched form of the paper's
+ * chunk-parallel sort (section "Multiprocessing Merge Sort"), with each
+ * array a chunk.
+ */
+ms_status ms_segmented_sort(void* d_keys, void* d_vals, const int64_t* d_offsets, size_t num_segments,
+                            size_t n_total, size_t max_segment_len, ms_key_type kt, size_t val_bytes,
+                            void* stream);
+
+/*
+ * Size classes and the autotuned per-class shapes of ms_segmented_sort.
+ * A family is (kt, val_bytes with 0 = keys only).  Class c holds segments of
+ * length <= max_len (class bounds increase with c); longer segments form the
+ * large class.  Each small class has num_candidates compiled shapes
+ * (workgroup size wg, items per thread ipt, wg * ipt == max_len); the tuning
+ * table picks one per class (candidate 0 until set).  All host-only.
+ *   ms_seg_num_classes : number of small classes of the family.
+ *   ms_seg_class_info  : bound and candidate count of class cls.
+ *   ms_seg_candidate   : shape of candidate idx of class cls.
+ *   ms_tuning_set      : select the candidate with shape (wg, ipt) for cls;
+ *                        MS_ERR_UNSUPPORTED if no such shape is compiled.
+ *   ms_tuning_get      : the shape currently selected for cls.
+ *   ms_tuning_load     : apply a tuning file: lines "arch key_type value_bytes
+ *                        class wg ipt" (key_type u32|i32|u64|i64, '#' starts a
+ *                        comment line); only lines whose arch equals `arch`
+ *                        (NULL = the current device's, e.g. "gfx950") are
+ *                        applied; *applied (may be NULL) gets their count.
+ * Changing the table makes later calls capture new graphs.
+ */
+ms_status ms_seg_num_classes(ms_key_type kt, size_t val_bytes, int* num_classes);
+ms_status ms_seg_class_info(ms_key_type kt, size_t val_bytes, int cls, uint32_t* max_len, int* num_candidates);
+ms_status ms_seg_candidate(ms_key_type kt, size_t val_bytes, int cls, int idx, int* wg, int* ipt);
+ms_status ms_tuning_set(ms_key_type kt, size_t val_bytes, int cls, int wg, int ipt);
+ms_status ms_tuning_get(ms_key_type kt, size_t val_bytes, int cls, int* wg, int* ipt);
+ms_status ms_tuning_load(const char* path, const char* arch, int* applied);
+
+/*
  * ms_temp_bytes -- device scratch (bytes) that a plain sort of n keys with
  * values of val_bytes (0 = keys only) uses.  Host arithmetic only.
  * Returns 0 for an unsupported kt / val_bytes.
@@ -106,8 +163,8 @@ size_t ms_temp_bytes(size_t n, ms_key_type kt, size_t val_bytes);
 ms_status ms_plan_query(size_t n, ms_key_type kt, size_t val_bytes, int* tile, int* merge_tile,
                         int* passes, int* tile_sort_in_place);
 
-/* Free the library's scratch buffers of the current device (all streams).
- * Synchronises the device first. */
+/* Free the library's scratch buffers and cached segmented-sort graphs of the
+ * current device (all streams).  Synchronises the device first. */
 ms_status ms_release_workspace(void);
 
 /*

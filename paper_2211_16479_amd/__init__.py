@@ -49,6 +49,13 @@ def _declare(lib):
         "ms_plan_query": (i32, [sz, i32, sz, c.POINTER(i32), c.POINTER(i32), c.POINTER(i32),
                                 c.POINTER(i32)]),
         "ms_release_workspace": (i32, []),
+        "ms_segmented_sort": (i32, [vp, vp, vp, sz, sz, sz, i32, sz, vp]),
+        "ms_seg_num_classes": (i32, [i32, sz, c.POINTER(i32)]),
+        "ms_seg_class_info": (i32, [i32, sz, i32, c.POINTER(c.c_uint32), c.POINTER(i32)]),
+        "ms_seg_candidate": (i32, [i32, sz, i32, i32, c.POINTER(i32), c.POINTER(i32)]),
+        "ms_tuning_set": (i32, [i32, sz, i32, i32, i32]),
+        "ms_tuning_get": (i32, [i32, sz, i32, c.POINTER(i32), c.POINTER(i32)]),
+        "ms_tuning_load": (i32, [c.c_char_p, c.c_char_p, c.POINTER(i32)]),
         "ms_profile_enable": (i32, [i32]),
         "ms_profile_reset": (i32, []),
         "ms_profile_read": (i32, [i32, c.POINTER(c.c_uint64), c.POINTER(c.c_double)]),
@@ -115,6 +122,79 @@ def ms_sort_pairs(keys: torch.Tensor, vals: torch.Tensor, key_type=None):
                                keys.numel(), _key_type(keys, key_type), vals.element_size(),
                                _stream(keys)), "ms_sort_pairs")
     return keys, vals
+
+
+def ms_segmented_sort(keys: torch.Tensor, offsets: torch.Tensor, vals: torch.Tensor = None,
+                      max_segment_len: int = 0, key_type=None):
+    """Sort every segment keys[offsets[s]:offsets[s+1]] in place (stable).
+
+    ``offsets`` is an int64 GPU tensor of num_segments + 1 entries starting at
+    0 and ending at len(keys).  One cached hipGraph launch on the current
+    stream does all segments.  Returns (keys, vals)."""
+    _dev(keys, "keys")
+    _dev(offsets, "offsets")
+    if offsets.dtype != torch.int64:
+        raise TypeError("offsets must be int64")
+    vb = 0
+    vp = None
+    if vals is not None:
+        _dev(vals, "vals")
+        if vals.numel() != keys.numel():
+            raise ValueError("keys and vals differ in length")
+        vb = vals.element_size()
+        vp = ctypes.c_void_p(vals.data_ptr())
+    _check(lib().ms_segmented_sort(ctypes.c_void_p(keys.data_ptr()), vp, ctypes.c_void_p(offsets.data_ptr()),
+                                   max(0, offsets.numel() - 1), keys.numel(), int(max_segment_len),
+                                   _key_type(keys, key_type), vb, _stream(keys)), "ms_segmented_sort")
+    return keys, vals
+
+
+def ms_seg_classes(key_type: int, val_bytes: int = 0) -> list:
+    """[(max_len, [(wg, ipt), ...]), ...] for every small class of a family."""
+    L = lib()
+    nc = ctypes.c_int()
+    _check(L.ms_seg_num_classes(key_type, val_bytes, ctypes.byref(nc)), "ms_seg_num_classes")
+    out = []
+    for c in range(nc.value):
+        ml, ncand = ctypes.c_uint32(), ctypes.c_int()
+        _check(L.ms_seg_class_info(key_type, val_bytes, c, ctypes.byref(ml), ctypes.byref(ncand)),
+               "ms_seg_class_info")
+        shapes = []
+        for i in range(ncand.value):
+            wg, ipt = ctypes.c_int(), ctypes.c_int()
+            _check(L.ms_seg_candidate(key_type, val_bytes, c, i, ctypes.byref(wg), ctypes.byref(ipt)),
+                   "ms_seg_candidate")
+            shapes.append((wg.value, ipt.value))
+        out.append((ml.value, shapes))
+    return out
+
+
+def ms_tuning_set(key_type: int, val_bytes: int, cls: int, wg: int, ipt: int):
+    _check(lib().ms_tuning_set(key_type, val_bytes, cls, wg, ipt), "ms_tuning_set")
+
+
+def ms_tuning_get(key_type: int, val_bytes: int, cls: int) -> tuple:
+    wg, ipt = ctypes.c_int(), ctypes.c_int()
+    _check(lib().ms_tuning_get(key_type, val_bytes, cls, ctypes.byref(wg), ctypes.byref(ipt)), "ms_tuning_get")
+    return wg.value, ipt.value
+
+
+def ms_tuning_load(path: str, arch: str = None) -> int:
+    n = ctypes.c_int()
+    _check(lib().ms_tuning_load(path.encode(), None if arch is None else arch.encode(), ctypes.byref(n)),
+           "ms_tuning_load")
+    return n.value
+
+
+TUNING_DIR = os.path.join(_PKG, "tuning")
+
+
+def load_default_tuning(arch: str = None) -> int:
+    """Apply the committed tuning table for this GPU architecture, if present."""
+    path = os.path.join(TUNING_DIR, "tuning.txt")
+    if not os.path.exists(path):
+        return 0
+    return ms_tuning_load(path, arch)
 
 
 def ms_temp_bytes(n: int, key_type: int, val_bytes: int = 0) -> int:

@@ -2,15 +2,20 @@
 // management, error reporting and the event profiler.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
 #include "ms_internal.hpp"
 #include "ms_plan.hpp"
+#include "ms_segmented.hpp"
+#include "ms_tuning.hpp"
 
 namespace ms {
 
@@ -60,6 +65,37 @@ ms_status get_workspace(hipStream_t s, size_t bytes, void** out) {
   *out = b.ptr;
   return MS_OK;
 }
+
+// ------------------------------------------------------------- device info
+int device_cu_count() {
+  static std::mutex mu;
+  static std::map<int, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+  cache[dev] = cus;
+  return cus;
+}
+
+// --------------------------------------------------------- tuning table
+namespace {
+std::mutex g_tune_mu;
+int g_tune[4][3][SEG_MAX_CLASSES] = {};
+uint64_t g_tune_gen = 1;
+}  // namespace
+
+int* seg_tuning_row(ms_key_type kt, size_t vb) {
+  const int k = int(kt);
+  const int v = vb == 0 ? 0 : vb == 4 ? 1 : vb == 8 ? 2 : -1;
+  if (k < 0 || k > 3 || v < 0) return nullptr;
+  return g_tune[k][v];
+}
+uint64_t seg_tuning_generation() { return g_tune_gen; }
+void seg_tuning_bump() { ++g_tune_gen; }
 
 // ---------------------------------------------------------------- profiler
 namespace {
@@ -157,6 +193,120 @@ static ms_status sort_impl(void* d_keys, void* d_vals, size_t n, ms_key_type kt,
                               ws);
     });
   });
+}
+
+template <class F>
+static ms_status with_types(ms_key_type kt, size_t vb, F&& f) {
+  return with_key_type(kt, [&](auto kz) -> ms_status {
+    return with_val_type(vb, [&](auto vz) -> ms_status { return f(kz, vz); });
+  });
+}
+
+// ------------------------------------------------- segmented: graph cache
+namespace {
+struct GraphKey {
+  int dev;
+  void* stream;
+  int kt;
+  size_t vb;
+  void* keys;
+  void* vals;
+  const void* off;
+  uint64_t nseg, n_total, max_len, gen;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(dev, stream, kt, vb, keys, vals, off, nseg, n_total, max_len, gen) <
+           std::tie(o.dev, o.stream, o.kt, o.vb, o.keys, o.vals, o.off, o.nseg, o.n_total, o.max_len, o.gen);
+  }
+};
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  void* ws = nullptr;
+  uint64_t last_use = 0;
+};
+std::mutex g_graph_mu;
+std::map<GraphKey, GraphEntry> g_graphs;
+std::map<int, hipStream_t> g_capture_streams;
+uint64_t g_graph_clock = 0;
+constexpr size_t GRAPH_CACHE_MAX = 8;
+
+void drop_graph(GraphEntry& e) {
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  if (e.ws) (void)hipFree(e.ws);
+  e.exec = nullptr;
+  e.ws = nullptr;
+}
+}  // namespace
+
+static ms_status seg_run(void* d_keys, void* d_vals, const int64_t* d_off, uint64_t nseg, uint64_t n_total,
+                         uint64_t max_len, ms_key_type kt, size_t vb, hipStream_t s) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  const GraphKey key{dev, s, int(kt), vb, d_keys, d_vals, d_off, nseg, n_total, max_len, seg_tuning_generation()};
+  auto it = g_graphs.find(key);
+  if (it == g_graphs.end()) {
+    if (g_graphs.size() >= GRAPH_CACHE_MAX) {
+      auto lru = g_graphs.begin();
+      for (auto jt = g_graphs.begin(); jt != g_graphs.end(); ++jt)
+        if (jt->second.last_use < lru->second.last_use) lru = jt;
+      (void)hipDeviceSynchronize();  // the evicted graph may still be running
+      drop_graph(lru->second);
+      g_graphs.erase(lru);
+    }
+    GraphEntry ent;
+    size_t bytes = 0;
+    ms_status st = with_types(kt, vb, [&](auto kz, auto vz) -> ms_status {
+      using K = decltype(kz);
+      using V = decltype(vz);
+      bytes = seg_temp_bytes<K, V>(nseg, n_total);
+      return MS_OK;
+    });
+    if (st != MS_OK) return st;
+    e = hipMalloc(&ent.ws, bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (segmented scratch)");
+    hipStream_t& cs = g_capture_streams[dev];
+    if (!cs) {
+      e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+      if (e != hipSuccess) { drop_graph(ent); return hip_fail(e, "hipStreamCreate (capture)"); }
+    }
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) { drop_graph(ent); return hip_fail(e, "hipStreamBeginCapture"); }
+    const int* tune = seg_tuning_row(kt, vb);
+    st = with_types(kt, vb, [&](auto kz, auto vz) -> ms_status {
+      using K = decltype(kz);
+      using V = decltype(vz);
+      return seg_enqueue<K, V>(static_cast<K*>(d_keys), static_cast<V*>(d_vals), d_off, nseg, n_total, max_len,
+                               ent.ws, cs, tune);
+    });
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (st != MS_OK || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      drop_graph(ent);
+      return st != MS_OK ? st : hip_fail(e2, "hipStreamEndCapture");
+    }
+    e = hipGraphInstantiate(&ent.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) { drop_graph(ent); return hip_fail(e, "hipGraphInstantiate"); }
+    it = g_graphs.emplace(key, ent).first;
+  }
+  it->second.last_use = ++g_graph_clock;
+  e = hipGraphLaunch(it->second.exec, s);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return MS_OK;
+}
+
+static void release_graphs(int dev) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+    if (it->first.dev == dev) {
+      drop_graph(it->second);
+      it = g_graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
 }
 
 }  // namespace ms
@@ -258,6 +408,7 @@ ms_status ms_release_workspace(void) {
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  release_graphs(dev);
   std::lock_guard<std::mutex> lk(g_ws_mu);
   for (auto it = g_ws.begin(); it != g_ws.end();) {
     if (it->first.first == dev) {
@@ -270,6 +421,179 @@ ms_status ms_release_workspace(void) {
       ++it;
     }
   }
+  return MS_OK;
+}
+
+ms_status ms_segmented_sort(void* d_keys, void* d_vals, const int64_t* d_offsets, size_t num_segments,
+                            size_t n_total, size_t max_segment_len, ms_key_type kt, size_t val_bytes,
+                            void* stream) {
+  ms_status st = check_common(d_keys, n_total, kt);
+  if (st != MS_OK) return st;
+  if (val_bytes != 0 && val_bytes != 4 && val_bytes != 8) {
+    set_error("value width must be 0 (keys only), 4 or 8 bytes");
+    return MS_ERR_UNSUPPORTED;
+  }
+  if (num_segments == 0 || n_total == 0) return MS_OK;
+  if (d_offsets == nullptr) {
+    set_error("d_offsets is NULL with num_segments > 0");
+    return MS_ERR_INVALID_ARG;
+  }
+  if (val_bytes != 0 && d_vals == nullptr) {
+    set_error("d_vals is NULL with val_bytes > 0");
+    return MS_ERR_INVALID_ARG;
+  }
+  if (val_bytes != 0 && d_vals == d_keys) {
+    set_error("key and value buffers overlap");
+    return MS_ERR_INVALID_ARG;
+  }
+  if (num_segments >= (size_t(1) << 31)) {
+    set_error("too many segments");
+    return MS_ERR_INVALID_ARG;
+  }
+  const uint64_t max_len = (max_segment_len == 0 || max_segment_len > n_total) ? n_total : max_segment_len;
+  try {
+    return seg_run(d_keys, val_bytes ? d_vals : nullptr, d_offsets, num_segments, n_total, max_len, kt, val_bytes,
+                   static_cast<hipStream_t>(stream));
+  } catch (...) {
+    set_error("unexpected exception");
+    return MS_ERR_INTERNAL;
+  }
+}
+
+ms_status ms_seg_num_classes(ms_key_type kt, size_t val_bytes, int* num_classes) {
+  int nc = 0;
+  ms_status st = with_types(kt, val_bytes, [&](auto kz, auto vz) -> ms_status {
+    nc = seg_num_classes<decltype(kz), decltype(vz)>();
+    return MS_OK;
+  });
+  if (st == MS_OK && num_classes) *num_classes = nc;
+  return st;
+}
+
+ms_status ms_seg_class_info(ms_key_type kt, size_t val_bytes, int cls, uint32_t* max_len, int* num_candidates) {
+  int nc = 0;
+  ms_status st = ms_seg_num_classes(kt, val_bytes, &nc);
+  if (st != MS_OK) return st;
+  if (cls < 0 || cls >= nc) {
+    set_error("size class out of range");
+    return MS_ERR_INVALID_ARG;
+  }
+  uint32_t b = 0;
+  int c = 0;
+  with_types(kt, val_bytes, [&](auto kz, auto vz) -> ms_status {
+    seg_class_info<decltype(kz), decltype(vz)>(cls, &b, &c);
+    return MS_OK;
+  });
+  if (max_len) *max_len = b;
+  if (num_candidates) *num_candidates = c;
+  return MS_OK;
+}
+
+ms_status ms_seg_candidate(ms_key_type kt, size_t val_bytes, int cls, int idx, int* wg, int* ipt) {
+  int nc = 0;
+  ms_status st = ms_seg_class_info(kt, val_bytes, cls, nullptr, &nc);
+  if (st != MS_OK) return st;
+  if (idx < 0 || idx >= nc) {
+    set_error("candidate index out of range");
+    return MS_ERR_INVALID_ARG;
+  }
+  int w = 0, p = 0;
+  with_types(kt, val_bytes, [&](auto kz, auto vz) -> ms_status {
+    seg_candidate<decltype(kz), decltype(vz)>(cls, idx, &w, &p);
+    return MS_OK;
+  });
+  if (wg) *wg = w;
+  if (ipt) *ipt = p;
+  return MS_OK;
+}
+
+ms_status ms_tuning_set(ms_key_type kt, size_t val_bytes, int cls, int wg, int ipt) {
+  int nc = 0;
+  ms_status st = ms_seg_class_info(kt, val_bytes, cls, nullptr, &nc);
+  if (st != MS_OK) return st;
+  for (int i = 0; i < nc; ++i) {
+    int w = 0, p = 0;
+    ms_seg_candidate(kt, val_bytes, cls, i, &w, &p);
+    if (w == wg && p == ipt) {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      seg_tuning_row(kt, val_bytes)[cls] = i;
+      seg_tuning_bump();
+      return MS_OK;
+    }
+  }
+  set_error("no compiled variant with that workgroup size and items per thread");
+  return MS_ERR_UNSUPPORTED;
+}
+
+ms_status ms_tuning_get(ms_key_type kt, size_t val_bytes, int cls, int* wg, int* ipt) {
+  int nc = 0;
+  ms_status st = ms_seg_class_info(kt, val_bytes, cls, nullptr, &nc);
+  if (st != MS_OK) return st;
+  int idx = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    idx = seg_tuning_row(kt, val_bytes)[cls];
+  }
+  return ms_seg_candidate(kt, val_bytes, cls, idx, wg, ipt);
+}
+
+ms_status ms_tuning_load(const char* path, const char* arch, int* applied) {
+  if (applied) *applied = 0;
+  if (!path) {
+    set_error("path is NULL");
+    return MS_ERR_INVALID_ARG;
+  }
+  std::string want;
+  if (arch) {
+    want = arch;
+  } else {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "device properties");
+    want = prop.gcnArchName;
+    want = want.substr(0, want.find(':'));
+  }
+  FILE* f = std::fopen(path, "r");
+  if (!f) {
+    set_error(std::string("cannot open ") + path);
+    return MS_ERR_INVALID_ARG;
+  }
+  char line[512];
+  int n = 0;
+  int lineno = 0;
+  while (std::fgets(line, sizeof line, f)) {
+    ++lineno;
+    char a[64], k[16];
+    size_t vb = 0;
+    int cls = 0, wg = 0, ipt = 0;
+    if (line[0] == '#' || line[0] == '\n') continue;
+    if (std::sscanf(line, "%63s %15s %zu %d %d %d", a, k, &vb, &cls, &wg, &ipt) != 6) {
+      std::fclose(f);
+      set_error("malformed tuning line " + std::to_string(lineno));
+      return MS_ERR_INVALID_ARG;
+    }
+    if (want != a) continue;
+    ms_key_type kt;
+    if (!std::strcmp(k, "u32")) kt = MS_KEY_U32;
+    else if (!std::strcmp(k, "i32")) kt = MS_KEY_I32;
+    else if (!std::strcmp(k, "u64")) kt = MS_KEY_U64;
+    else if (!std::strcmp(k, "i64")) kt = MS_KEY_I64;
+    else {
+      std::fclose(f);
+      set_error("unknown key type on tuning line " + std::to_string(lineno));
+      return MS_ERR_INVALID_ARG;
+    }
+    ms_status st = ms_tuning_set(kt, vb, cls, wg, ipt);
+    if (st != MS_OK) {
+      std::fclose(f);
+      return st;
+    }
+    ++n;
+  }
+  std::fclose(f);
+  if (applied) *applied = n;
   return MS_OK;
 }
 

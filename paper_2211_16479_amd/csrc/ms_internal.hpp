@@ -50,4 +50,19 @@ size_t plain_temp_bytes(uint64_t n);
 template <class K, class V>
 void plain_geometry(int* tile, int* merge_tile);
 
+// Segmented sort (ms_seg_launch.hpp): enqueue the whole pipeline on s.
+template <class K, class V>
+ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint64_t n_total, uint64_t max_len,
+                      void* ws, hipStream_t s, const int* tune);
+template <class K, class V>
+size_t seg_temp_bytes(uint64_t nseg, uint64_t n_total);
+template <class K, class V>
+int seg_num_classes();
+template <class K, class V>
+void seg_class_info(int cls, uint32_t* bound, int* ncand);
+template <class K, class V>
+void seg_candidate(int cls, int idx, int* wg, int* ipt);
+
+int device_cu_count();
+
 }  // namespace ms

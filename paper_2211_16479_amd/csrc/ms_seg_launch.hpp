@@ -1,0 +1,210 @@
+// Host side of the segmented sort: scratch layout, per-class variant choice
+// (autotuned), the launch sequence, and its capture into one hipGraph.
+#pragma once
+#include <algorithm>
+
+#include "ms_internal.hpp"
+#include "ms_plan.hpp"
+#include "ms_segmented.hpp"
+#include "ms_tuning.hpp"
+
+namespace ms {
+
+template <class F>
+static hipError_t seg_allow_lds(F* kernel, size_t bytes) {
+  if (bytes <= 48 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             int(bytes));
+}
+
+int device_cu_count();
+
+template <class K, class V, int WG, int IPT>
+static hipError_t launch_small(K* keys, V* vals, const int64_t* off, SegState st, int cls, uint64_t nseg,
+                               hipStream_t s) {
+  constexpr int PAD = PlainCfg<K, V>::BS_PAD;
+  using TS = TileSort<K, V, WG, IPT, PAD>;
+  static const hipError_t ok = seg_allow_lds(&seg_small_kernel<K, V, WG, IPT, PAD>, TS::LDS_BYTES);
+  if (ok != hipSuccess) return ok;
+  const uint64_t per_cu = std::max(1, 2048 / WG);
+  const uint64_t grid = std::min<uint64_t>(nseg, uint64_t(device_cu_count()) * per_cu);
+  seg_small_kernel<K, V, WG, IPT, PAD><<<dim3(unsigned(grid)), dim3(WG), TS::LDS_BYTES, s>>>(keys, vals, off, st, cls,
+                                                                                            nseg);
+  return hipGetLastError();
+}
+
+// Candidate (WG, IPT) shapes per class bound; index 0 is the default.
+// 32-bit keys (keys only or 4-byte values) get every candidate, other
+// families the default only, to bound compile time.
+template <class K, class V>
+struct SegCands {
+  static constexpr bool FULL = sizeof(K) == 4 && (!HasVal<V>::value || sizeof(typename std::conditional<
+                                                                           HasVal<V>::value, V, int>::type) == 4);
+  static int count(uint32_t bound) {
+    if (!FULL) return 1;
+    switch (bound) {
+      case 256: return 2;
+      case 1024: return 3;
+      case 2048: return 2;
+      case 4096: return 3;
+      case 16384: return 2;
+    }
+    return 1;
+  }
+  static void shape(uint32_t bound, int idx, int* wg, int* ipt) {
+    static const int t256[2][2] = {{64, 4}, {128, 2}};
+    static const int t1k[3][2] = {{128, 8}, {64, 16}, {256, 4}};
+    static const int t2k[2][2] = {{256, 8}, {128, 16}};
+    static const int t4k[3][2] = {{256, 16}, {512, 8}, {1024, 4}};
+    static const int t16k[2][2] = {{1024, 16}, {512, 32}};
+    const int(*t)[2] = bound == 256 ? t256 : bound == 1024 ? t1k : bound == 2048 ? t2k : bound == 4096 ? t4k : t16k;
+    *wg = t[idx][0];
+    *ipt = t[idx][1];
+  }
+  static hipError_t launch(uint32_t bound, int idx, K* keys, V* vals, const int64_t* off, SegState st, int cls,
+                           uint64_t nseg, hipStream_t s) {
+    switch (bound) {
+      case 256:
+        if constexpr (FULL) if (idx == 1) return launch_small<K, V, 128, 2>(keys, vals, off, st, cls, nseg, s);
+        return launch_small<K, V, 64, 4>(keys, vals, off, st, cls, nseg, s);
+      case 1024:
+        if constexpr (FULL) {
+          if (idx == 1) return launch_small<K, V, 64, 16>(keys, vals, off, st, cls, nseg, s);
+          if (idx == 2) return launch_small<K, V, 256, 4>(keys, vals, off, st, cls, nseg, s);
+        }
+        return launch_small<K, V, 128, 8>(keys, vals, off, st, cls, nseg, s);
+      case 2048:
+        if constexpr (FULL) if (idx == 1) return launch_small<K, V, 128, 16>(keys, vals, off, st, cls, nseg, s);
+        return launch_small<K, V, 256, 8>(keys, vals, off, st, cls, nseg, s);
+      case 4096:
+        if constexpr (FULL) {
+          if (idx == 1) return launch_small<K, V, 512, 8>(keys, vals, off, st, cls, nseg, s);
+          if (idx == 2) return launch_small<K, V, 1024, 4>(keys, vals, off, st, cls, nseg, s);
+        }
+        return launch_small<K, V, 256, 16>(keys, vals, off, st, cls, nseg, s);
+      case 16384:
+        if constexpr (sizeof(K) == 4 && !HasVal<V>::value) {
+          if (idx == 1) return launch_small<K, V, 512, 32>(keys, vals, off, st, cls, nseg, s);
+          return launch_small<K, V, 1024, 16>(keys, vals, off, st, cls, nseg, s);
+        }
+        break;
+    }
+    return hipErrorInvalidValue;
+  }
+};
+
+struct SegLayout {
+  size_t cls_count, cls_work, large_ctr, queues, large_seg, large_mbase, owner, part, tk, tv, bytes;
+  uint64_t mt_cap;
+};
+
+template <class K, class V>
+SegLayout seg_layout(uint64_t nseg, uint64_t n_total) {
+  using S = SegCfg<K, V>;
+  const size_t vb = HasVal<V>::value ? sizeof(typename std::conditional<HasVal<V>::value, V, int>::type) : 0;
+  SegLayout L{};
+  L.mt_cap = (n_total / S::TILE + nseg + 1) * S::C;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes, 256); return at; };
+  L.cls_count = take(sizeof(uint32_t) * SEG_MAX_CLASSES);
+  L.cls_work = take(sizeof(uint32_t) * SEG_MAX_CLASSES);
+  L.large_ctr = take(sizeof(unsigned long long));
+  L.queues = take(sizeof(int32_t) * SEG_MAX_CLASSES * nseg);
+  L.large_seg = take(sizeof(int32_t) * nseg);
+  L.large_mbase = take(sizeof(int64_t) * nseg);
+  L.owner = take(sizeof(int32_t) * L.mt_cap);
+  L.part = take(sizeof(int64_t) * L.mt_cap);
+  L.tk = take(sizeof(K) * n_total);
+  L.tv = take(vb * n_total);
+  L.bytes = o;
+  return L;
+}
+
+// Enqueue the whole segmented pipeline on stream s (possibly capturing).
+template <class K, class V>
+ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint64_t n_total, uint64_t max_len,
+                      void* ws, hipStream_t s, const int* tune) {
+  using S = SegCfg<K, V>;
+  using P = PlainCfg<K, V>;
+  const SegLayout L = seg_layout<K, V>(nseg, n_total);
+  char* w = static_cast<char*>(ws);
+  SegState st;
+  st.cls_count = reinterpret_cast<uint32_t*>(w + L.cls_count);
+  st.cls_work = reinterpret_cast<uint32_t*>(w + L.cls_work);
+  st.large_ctr = reinterpret_cast<unsigned long long*>(w + L.large_ctr);
+  st.queues = reinterpret_cast<int32_t*>(w + L.queues);
+  st.large_seg = reinterpret_cast<int32_t*>(w + L.large_seg);
+  st.large_mbase = reinterpret_cast<int64_t*>(w + L.large_mbase);
+  st.owner = reinterpret_cast<int32_t*>(w + L.owner);
+  st.part = reinterpret_cast<int64_t*>(w + L.part);
+  K* tk = reinterpret_cast<K*>(w + L.tk);
+  V* tv = reinterpret_cast<V*>(w + L.tv);
+  const uint64_t cus = uint64_t(device_cu_count());
+
+  seg_init_kernel<<<1, 64, 0, s>>>(st);
+  seg_classify_kernel<K, V><<<dim3(unsigned(ceil_div(nseg, 256))), dim3(256), 0, s>>>(off, nseg, st);
+  seg_owner_kernel<K, V><<<dim3(unsigned(std::min<uint64_t>(nseg, cus * 4))), dim3(256), 0, s>>>(off, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "segment classification launch");
+  for (int c = 0; c < S::NCLS; ++c) {
+    e = SegCands<K, V>::launch(S::cls_max(c), tune[c], keys, vals, off, st, c, nseg, s);
+    if (e != hipSuccess) return hip_fail(e, "small-segment sort launch");
+  }
+  if (max_len > uint64_t(S::TILE)) {
+    using TS = TileSort<K, V, P::BS_WG, P::BS_IPT, P::BS_PAD>;
+    using MT = MergeTile<K, V, P::MG_WG, P::MG_IPT, P::MG_PAD>;
+    static const hipError_t lds_ok = [] {
+      hipError_t a = seg_allow_lds(&seg_large_tile_kernel<K, V, P::BS_WG, P::BS_IPT, P::BS_PAD>, TS::LDS_BYTES);
+      hipError_t b = seg_allow_lds(&seg_merge_kernel<K, V, P::MG_WG, P::MG_IPT, P::MG_PAD>, MT::LDS_BYTES);
+      return a != hipSuccess ? a : b;
+    }();
+    if (lds_ok != hipSuccess) return hip_fail(lds_ok, "LDS size attribute");
+    const uint64_t tiles_cap = L.mt_cap / S::C;
+    const uint64_t tgrid = std::min<uint64_t>(tiles_cap, cus * std::max(1, 2048 / P::BS_WG));
+    seg_large_tile_kernel<K, V, P::BS_WG, P::BS_IPT, P::BS_PAD>
+        <<<dim3(unsigned(tgrid)), dim3(P::BS_WG), TS::LDS_BYTES, s>>>(keys, vals, tk, tv, off, st);
+    const int passes = plan_passes(max_len, S::TILE);
+    const uint64_t pgrid = std::min<uint64_t>(ceil_div(L.mt_cap, 256), cus * 8);
+    const uint64_t mgrid = std::min<uint64_t>(L.mt_cap, cus * std::max(1, 2048 / P::MG_WG));
+    for (int p = 0; p < passes; ++p) {
+      seg_partition_kernel<K, V><<<dim3(unsigned(pgrid)), dim3(256), 0, s>>>(keys, tk, off, st, p);
+      seg_merge_kernel<K, V, P::MG_WG, P::MG_IPT, P::MG_PAD>
+          <<<dim3(unsigned(mgrid)), dim3(P::MG_WG), MT::LDS_BYTES, s>>>(keys, vals, tk, tv, off, st, p);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "large-segment launch");
+  }
+  return MS_OK;
+}
+
+template <class K, class V>
+size_t seg_temp_bytes(uint64_t nseg, uint64_t n_total) {
+  return seg_layout<K, V>(nseg, n_total).bytes;
+}
+
+template <class K, class V>
+int seg_num_classes() {
+  return SegCfg<K, V>::NCLS;
+}
+
+template <class K, class V>
+void seg_class_info(int cls, uint32_t* bound, int* ncand) {
+  using S = SegCfg<K, V>;
+  *bound = S::cls_max(cls);
+  *ncand = SegCands<K, V>::count(*bound);
+}
+
+template <class K, class V>
+void seg_candidate(int cls, int idx, int* wg, int* ipt) {
+  SegCands<K, V>::shape(SegCfg<K, V>::cls_max(cls), idx, wg, ipt);
+}
+
+#define MS_SEG_INSTANTIATE(K, V)                                                                              \
+  template ms_status seg_enqueue<K, V>(K*, V*, const int64_t*, uint64_t, uint64_t, uint64_t, void*, hipStream_t, \
+                                       const int*);                                                           \
+  template size_t seg_temp_bytes<K, V>(uint64_t, uint64_t);                                                   \
+  template int seg_num_classes<K, V>();                                                                       \
+  template void seg_class_info<K, V>(int, uint32_t*, int*);                                                   \
+  template void seg_candidate<K, V>(int, int, int*, int*);
+
+}  // namespace ms

@@ -1,0 +1,250 @@
+// Segmented sort: many independent arrays, one call, one graph launch.
+//
+// Every segment [off[s], off[s+1]) is sorted on its own (stable, in place).
+// The pipeline is shape-independent on the host -- the split of segments into
+// size classes happens on the device -- so it can be captured once into a
+// hipGraph and replayed:
+//   1. init      : clear the class counters (a fill kernel, no memset nodes);
+//   2. classify  : one thread per segment bins it by length into a small class
+//                  queue, or reserves merge tiles for it in the large list;
+//   3. owner     : writes, for every reserved merge tile, which large segment
+//                  it belongs to;
+//   4. per small class c, a persistent kernel whose workgroups take segments
+//      from the class queue through an atomic work counter and sort each one
+//      entirely in LDS (the tile sort of ms_block_sort.hpp with the class's
+//      workgroup size and items per thread, picked by the autotuner);
+//   5. large segments: the tile sort on each tile, then merge passes bounded
+//      to the segment (runs never cross a segment end).  Segments finish after
+//      different numbers of passes, so each one picks its own buffer parity
+//      so that its last pass lands in the caller's buffer.
+#pragma once
+#include "ms_block_sort.hpp"
+#include "ms_merge.hpp"
+#include "ms_plain_cfg.hpp"
+
+namespace ms {
+
+constexpr int SEG_MAX_CLASSES = 5;
+constexpr int SEG_MAX_CANDIDATES = 3;
+
+// Device-side state of one segmented sort (all in library scratch).
+struct SegState {
+  uint32_t* cls_count;   // [SEG_MAX_CLASSES] segments per small class
+  uint32_t* cls_work;    // [SEG_MAX_CLASSES] atomic work counters
+  unsigned long long* large_ctr;  // (large segment count << 40) | reserved merge tiles
+  int32_t* queues;       // [SEG_MAX_CLASSES][nseg] segment ids per small class
+  int32_t* large_seg;    // [nseg] segment id per large slot
+  int64_t* large_mbase;  // [nseg] first reserved merge tile per large slot
+  int32_t* owner;        // [mt_cap] large slot owning each merge tile
+  int64_t* part;         // [mt_cap] merge-path splits of the current pass
+};
+
+constexpr unsigned long long SEG_SLOT_SHIFT = 40;
+constexpr unsigned long long SEG_TILE_MASK = (1ull << SEG_SLOT_SHIFT) - 1;
+
+__device__ __forceinline__ int seg_passes(uint64_t L, uint64_t T) {
+  if (L <= T) return 0;
+  const uint64_t runs = (L + T - 1) / T;
+  return 64 - __builtin_clzll(runs - 1);
+}
+
+// Size classes of one (key, value) family: small classes have upper bounds
+// 256, 1024, 4096, 16384 (capped at the large-segment tile), larger segments
+// go through the tile sort + merge passes.
+template <class K, class V>
+struct SegCfg {
+  using P = PlainCfg<K, V>;
+  static constexpr int TILE = P::TILE;    // large segments: tile-sort tile
+  static constexpr int MTILE = P::MTILE;  // large segments: merge tile
+  static constexpr int C = TILE / MTILE;  // merge tiles per tile
+  static constexpr int NCLS = TILE >= 16384 ? 4 : (TILE >= 4096 ? 3 : (TILE >= 2048 ? 3 : 2));
+  static __host__ __device__ constexpr uint32_t cls_max(int c) {
+    return c == 0 ? 256u : c == 1 ? 1024u : c == 2 ? (TILE >= 4096 ? 4096u : uint32_t(TILE)) : 16384u;
+  }
+  static_assert(TILE % MTILE == 0, "tile must be a whole number of merge tiles");
+};
+
+template <class K, class V>
+__device__ __forceinline__ int seg_class(uint64_t L) {
+  using S = SegCfg<K, V>;
+#pragma unroll
+  for (int c = 0; c < S::NCLS; ++c)
+    if (L <= S::cls_max(c)) return c;
+  return S::NCLS;  // large
+}
+
+static __global__ void seg_init_kernel(SegState st) {
+  const int t = threadIdx.x;
+  if (t < SEG_MAX_CLASSES) {
+    st.cls_count[t] = 0;
+    st.cls_work[t] = 0;
+  }
+  if (t == 0) *st.large_ctr = 0;
+}
+
+template <class K, class V>
+__global__ __launch_bounds__(256) void seg_classify_kernel(const int64_t* __restrict__ off, uint64_t nseg,
+                                                           SegState st) {
+  using S = SegCfg<K, V>;
+  const uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  const int64_t b = off[s], e = off[s + 1];
+  if (e - b <= 1) return;  // nothing to sort
+  const uint64_t L = uint64_t(e - b);
+  const int c = seg_class<K, V>(L);
+  if (c < S::NCLS) {
+    const uint32_t slot = atomicAdd(&st.cls_count[c], 1u);
+    st.queues[uint64_t(c) * nseg + slot] = int32_t(s);
+  } else {
+    const unsigned long long mt = ((L + S::TILE - 1) / S::TILE) * S::C;
+    const unsigned long long old = atomicAdd(st.large_ctr, (1ull << SEG_SLOT_SHIFT) | mt);
+    const uint64_t slot = old >> SEG_SLOT_SHIFT;
+    st.large_seg[slot] = int32_t(s);
+    st.large_mbase[slot] = int64_t(old & SEG_TILE_MASK);
+  }
+}
+
+template <class K, class V>
+__global__ __launch_bounds__(256) void seg_owner_kernel(const int64_t* __restrict__ off, SegState st) {
+  using S = SegCfg<K, V>;
+  const uint64_t nlarge = (*st.large_ctr) >> SEG_SLOT_SHIFT;
+  for (uint64_t slot = blockIdx.x; slot < nlarge; slot += gridDim.x) {
+    const int32_t s = st.large_seg[slot];
+    const uint64_t L = uint64_t(off[s + 1] - off[s]);
+    const uint64_t mt = ((L + S::TILE - 1) / S::TILE) * S::C;
+    const int64_t mb = st.large_mbase[slot];
+    for (uint64_t t = threadIdx.x; t < mt; t += blockDim.x) st.owner[mb + t] = int32_t(slot);
+  }
+}
+
+// Small class: workgroups fetch segments from the class queue until it is
+// drained; each segment is sorted in place in LDS.
+template <class K, class V, int WG, int IPT, int PAD>
+__global__ __launch_bounds__(WG) void seg_small_kernel(K* __restrict__ keys, V* __restrict__ vals,
+                                                       const int64_t* __restrict__ off, SegState st, int cls,
+                                                       uint64_t nseg) {
+  using TS = TileSort<K, V, WG, IPT, PAD>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ uint32_t cur;
+  const uint32_t count = st.cls_count[cls];
+  const int32_t* q = st.queues + uint64_t(cls) * nseg;
+  for (;;) {
+    if (threadIdx.x == 0) cur = atomicAdd(&st.cls_work[cls], 1u);
+    __syncthreads();
+    const uint32_t i = cur;
+    __syncthreads();
+    if (i >= count) break;
+    const int32_t s = q[i];
+    const int64_t b = off[s];
+    const uint32_t L = uint32_t(off[s + 1] - b);
+    if constexpr (TS::PAIRS) {
+      TS::run(keys + b, vals + b, keys + b, vals + b, L, smem);
+    } else {
+      TS::template run<int>(keys + b, nullptr, keys + b, nullptr, L, smem);
+    }
+    __syncthreads();
+  }
+}
+
+// Large segments, step 1: tile sort of every tile of every large segment.
+template <class K, class V, int WG, int IPT, int PAD>
+__global__ __launch_bounds__(WG) void seg_large_tile_kernel(K* __restrict__ keys, V* __restrict__ vals,
+                                                            K* __restrict__ tk, V* __restrict__ tv,
+                                                            const int64_t* __restrict__ off, SegState st) {
+  using S = SegCfg<K, V>;
+  using TS = TileSort<K, V, WG, IPT, PAD>;
+  static_assert(TS::TILE == S::TILE, "large-segment tile");
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint64_t tiles = ((*st.large_ctr) & SEG_TILE_MASK) / S::C;
+  for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    const int32_t slot = st.owner[t * S::C];
+    const int32_t s = st.large_seg[slot];
+    const int64_t b = off[s];
+    const uint64_t L = uint64_t(off[s + 1] - b);
+    const uint64_t j = t - uint64_t(st.large_mbase[slot]) / S::C;
+    if (j * S::TILE >= L) continue;  // reserved but past the segment end (uniform)
+    const uint64_t rem = L - j * S::TILE;
+    const uint32_t len = rem < uint64_t(S::TILE) ? uint32_t(rem) : uint32_t(S::TILE);
+    const bool to_caller = (seg_passes(L, S::TILE) & 1) == 0;
+    const uint64_t o = uint64_t(b) + j * S::TILE;
+    if constexpr (TS::PAIRS) {
+      TS::run(keys + o, vals + o, (to_caller ? keys : tk) + o, (to_caller ? vals : tv) + o, len, smem);
+    } else {
+      TS::template run<int>(keys + o, nullptr, (to_caller ? keys : tk) + o, nullptr, len, smem);
+    }
+    __syncthreads();
+  }
+}
+
+// Large segments, pass p: partition (one thread per reserved merge tile).
+template <class K, class V>
+__global__ __launch_bounds__(256) void seg_partition_kernel(const K* __restrict__ keys, const K* __restrict__ tk,
+                                                            const int64_t* __restrict__ off, SegState st, int p) {
+  using S = SegCfg<K, V>;
+  const uint64_t mt = (*st.large_ctr) & SEG_TILE_MASK;
+  for (uint64_t g = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < mt; g += uint64_t(gridDim.x) * blockDim.x) {
+    const int32_t slot = st.owner[g];
+    const int32_t s = st.large_seg[slot];
+    const int64_t b = off[s];
+    const uint64_t L = uint64_t(off[s + 1] - b);
+    const int P = seg_passes(L, S::TILE);
+    if (p >= P) continue;
+    const uint64_t lt = g - uint64_t(st.large_mbase[slot]);
+    const uint64_t g0 = lt * S::MTILE;
+    if (g0 >= L) continue;
+    const K* src = (((P - p) & 1) == 0 ? keys : tk) + b;
+    const uint64_t W = uint64_t(S::TILE) << p;
+    const PassGeom q = pass_geom(g0, L, W);
+    st.part[g] = int64_t(q.pb + merge_path_split(src + q.pb, q.a_end - q.pb, src + q.a_end, q.b_end - q.a_end,
+                                                  g0 - q.pb));
+  }
+}
+
+// Large segments, pass p: merge (workgroups loop over reserved merge tiles).
+template <class K, class V, int WG, int IPT, int PAD>
+__global__ __launch_bounds__(WG) void seg_merge_kernel(K* __restrict__ keys, V* __restrict__ vals,
+                                                       K* __restrict__ tk, V* __restrict__ tv,
+                                                       const int64_t* __restrict__ off, SegState st, int p) {
+  using S = SegCfg<K, V>;
+  using MT = MergeTile<K, V, WG, IPT, PAD>;
+  static_assert(MT::TM == S::MTILE, "large-segment merge tile");
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint64_t mt = (*st.large_ctr) & SEG_TILE_MASK;
+  for (uint64_t g = blockIdx.x; g < mt; g += gridDim.x) {
+    const int32_t slot = st.owner[g];
+    const int32_t s = st.large_seg[slot];
+    const int64_t b = off[s];
+    const uint64_t L = uint64_t(off[s + 1] - b);
+    const int P = seg_passes(L, S::TILE);
+    if (p >= P) continue;  // workgroup-uniform
+    const uint64_t lt = g - uint64_t(st.large_mbase[slot]);
+    const uint64_t g0 = lt * S::MTILE;
+    if (g0 >= L) continue;
+    const bool from_caller = ((P - p) & 1) == 0;
+    K* sk = (from_caller ? keys : tk) + b;
+    K* dk = (from_caller ? tk : keys) + b;
+    const uint64_t g1 = g0 + S::MTILE < L ? g0 + S::MTILE : L;
+    const uint64_t W = uint64_t(S::TILE) << p;
+    const PassGeom q = pass_geom(g0, L, W);
+    const uint64_t i0 = uint64_t(st.part[g]);
+    const uint64_t j0 = q.a_end + (g0 - q.pb) - (i0 - q.pb);
+    uint64_t i1, j1;
+    if (g1 == q.b_end) {
+      i1 = q.a_end;
+      j1 = q.b_end;
+    } else {
+      i1 = uint64_t(st.part[g + 1]);
+      j1 = q.a_end + (g1 - q.pb) - (i1 - q.pb);
+    }
+    if constexpr (MT::PAIRS) {
+      V* sv = (from_caller ? vals : tv) + b;
+      V* dv = (from_caller ? tv : vals) + b;
+      MT::run(sk, sv, dk, dv, i0, uint32_t(i1 - i0), j0, uint32_t(j1 - j0), g0, smem);
+    } else {
+      MT::template run<int>(sk, nullptr, dk, nullptr, i0, uint32_t(i1 - i0), j0, uint32_t(j1 - j0), g0, smem);
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace ms

@@ -74,3 +74,54 @@ def test_plan_arithmetic(kt, vb):
             kb = 4 if kt in (0, 1) else 8
             assert tb >= n * (kb + vb)
     assert msort.ms_temp_bytes(100, 9, 0) == 0
+
+
+def test_segmented_argument_checks():
+    L = msort.lib()
+    # nothing to do
+    assert L.ms_segmented_sort(None, None, None, 0, 0, 0, 0, 0, None) == 0
+    assert L.ms_segmented_sort(ctypes.c_void_p(64), None, None, 0, 10, 0, 0, 0, None) == 0
+    # missing offsets / values, bad widths, bad key type
+    assert L.ms_segmented_sort(ctypes.c_void_p(64), None, None, 3, 10, 0, 0, 0, None) == 1
+    assert L.ms_segmented_sort(ctypes.c_void_p(64), None, ctypes.c_void_p(128), 3, 10, 0, 0, 4, None) == 1
+    assert L.ms_segmented_sort(ctypes.c_void_p(64), None, ctypes.c_void_p(128), 3, 10, 0, 0, 3, None) == 2
+    assert L.ms_segmented_sort(ctypes.c_void_p(64), None, ctypes.c_void_p(128), 3, 10, 0, 9, 0, None) == 2
+    assert L.ms_segmented_sort(None, None, ctypes.c_void_p(128), 3, 10, 0, 0, 0, None) == 1
+
+
+@pytest.mark.parametrize("kt,vb", [(0, 0), (0, 4), (1, 8), (2, 0), (3, 4), (3, 8)])
+def test_size_classes_and_candidates(kt, vb):
+    classes = msort.ms_seg_classes(kt, vb)
+    assert 2 <= len(classes) <= 5
+    bounds = [b for b, _ in classes]
+    assert bounds == sorted(bounds) and bounds[0] == 256
+    tile = msort.ms_plan_query(1 << 20, kt, vb)["tile"]
+    assert bounds[-1] == tile          # the last small class is one tile
+    for b, shapes in classes:
+        assert shapes, b
+        for wg, ipt in shapes:
+            assert wg * ipt == b and wg % 64 == 0 and ipt >= 2
+
+
+def test_tuning_set_get_load(tmp_path):
+    classes = msort.ms_seg_classes(0, 0)
+    for c, (b, shapes) in enumerate(classes):
+        for wg, ipt in shapes:
+            msort.ms_tuning_set(0, 0, c, wg, ipt)
+            assert msort.ms_tuning_get(0, 0, c) == (wg, ipt)
+        msort.ms_tuning_set(0, 0, c, *shapes[0])
+    with pytest.raises(msort.MSortError):
+        msort.ms_tuning_set(0, 0, 0, 64, 8)          # 512 != class bound
+    with pytest.raises(msort.MSortError):
+        msort.ms_tuning_set(0, 0, 99, 64, 4)
+    b, shapes = classes[1]
+    alt = shapes[-1]
+    f = tmp_path / "t.txt"
+    f.write_text(f"# comment\ngfx950 u32 0 1 {alt[0]} {alt[1]}\ngfx942 u32 0 1 {shapes[0][0]} {shapes[0][1]}\n")
+    assert msort.ms_tuning_load(str(f), "gfx950") == 1
+    assert msort.ms_tuning_get(0, 0, 1) == alt
+    msort.ms_tuning_set(0, 0, 1, *shapes[0])
+    bad = tmp_path / "bad.txt"
+    bad.write_text("gfx950 u32 zero\n")
+    with pytest.raises(msort.MSortError):
+        msort.ms_tuning_load(str(bad), "gfx950")
