@@ -105,6 +105,8 @@ ms_status ms_sort_pairs(void* d_keys, void* d_vals, size_t n, ms_key_type kt, si
  *                     unknown (then n_total is used).  It only sets how many
  *                     merge passes the captured graph contains; a bound that
  *                     is too small gives unsorted output for longer segments.
+ * Limits: fewer than 2^26 segments and n_total < 2^32 per call, otherwise
+ * MS_ERR_UNSUPPORTED.
  * Segments are binned by length on the device into small classes, each sorted
  * by a persistent kernel entirely in LDS (per-class workgroup size and items
  * per thread from the tuning table), and a large class sorted by tiles plus

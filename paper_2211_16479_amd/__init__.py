@@ -133,6 +133,7 @@ def ms_segmented_sort(keys: torch.Tensor, offsets: torch.Tensor, vals: torch.Ten
     stream does all segments.  Returns (keys, vals)."""
     _dev(keys, "keys")
     _dev(offsets, "offsets")
+    _ensure_tuning()
     if offsets.dtype != torch.int64:
         raise TypeError("offsets must be int64")
     vb = 0
@@ -187,6 +188,15 @@ def ms_tuning_load(path: str, arch: str = None) -> int:
 
 
 TUNING_DIR = os.path.join(_PKG, "tuning")
+_tuning_loaded = False
+
+
+def _ensure_tuning():
+    """Apply the committed per-class shape table once per process (GPU runs)."""
+    global _tuning_loaded
+    if not _tuning_loaded:
+        _tuning_loaded = True
+        load_default_tuning()
 
 
 def load_default_tuning(arch: str = None) -> int:

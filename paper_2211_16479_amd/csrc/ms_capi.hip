@@ -225,7 +225,11 @@ struct GraphEntry {
 };
 std::mutex g_graph_mu;
 std::map<GraphKey, GraphEntry> g_graphs;
-std::map<int, hipStream_t> g_capture_streams;
+struct CaptureStreams {
+  hipStream_t main = nullptr, side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+};
+std::map<int, CaptureStreams> g_capture_streams;
 uint64_t g_graph_clock = 0;
 constexpr size_t GRAPH_CACHE_MAX = 8;
 
@@ -265,11 +269,15 @@ static ms_status seg_run(void* d_keys, void* d_vals, const int64_t* d_off, uint6
     if (st != MS_OK) return st;
     e = hipMalloc(&ent.ws, bytes);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc (segmented scratch)");
-    hipStream_t& cs = g_capture_streams[dev];
-    if (!cs) {
-      e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-      if (e != hipSuccess) { drop_graph(ent); return hip_fail(e, "hipStreamCreate (capture)"); }
+    CaptureStreams& cap = g_capture_streams[dev];
+    if (!cap.main) {
+      e = hipStreamCreateWithFlags(&cap.main, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap.side, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&cap.ev_fork, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&cap.ev_join, hipEventDisableTiming);
+      if (e != hipSuccess) { drop_graph(ent); return hip_fail(e, "capture streams"); }
     }
+    hipStream_t cs = cap.main;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) { drop_graph(ent); return hip_fail(e, "hipStreamBeginCapture"); }
     const int* tune = seg_tuning_row(kt, vb);
@@ -277,7 +285,7 @@ static ms_status seg_run(void* d_keys, void* d_vals, const int64_t* d_off, uint6
       using K = decltype(kz);
       using V = decltype(vz);
       return seg_enqueue<K, V>(static_cast<K*>(d_keys), static_cast<V*>(d_vals), d_off, nseg, n_total, max_len,
-                               ent.ws, cs, tune);
+                               ent.ws, cs, tune, SegFork{cap.side, cap.ev_fork, cap.ev_join});
     });
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &graph);
@@ -446,9 +454,9 @@ ms_status ms_segmented_sort(void* d_keys, void* d_vals, const int64_t* d_offsets
     set_error("key and value buffers overlap");
     return MS_ERR_INVALID_ARG;
   }
-  if (num_segments >= (size_t(1) << 31)) {
-    set_error("too many segments");
-    return MS_ERR_INVALID_ARG;
+  if (num_segments >= (size_t(1) << 26) || n_total >= (size_t(1) << 32)) {
+    set_error("segmented sort supports fewer than 2^26 segments and 2^32 keys per call");
+    return MS_ERR_UNSUPPORTED;
   }
   const uint64_t max_len = (max_segment_len == 0 || max_segment_len > n_total) ? n_total : max_segment_len;
   try {

@@ -50,10 +50,16 @@ size_t plain_temp_bytes(uint64_t n);
 template <class K, class V>
 void plain_geometry(int* tile, int* merge_tile);
 
-// Segmented sort (ms_seg_launch.hpp): enqueue the whole pipeline on s.
+// Segmented sort (ms_seg_launch.hpp): enqueue the whole pipeline on s.  If
+// fork.side is set, the small classes go to that stream between a fork and a
+// join event (used while capturing, so the graph gets two branches).
+struct SegFork {
+  hipStream_t side;
+  hipEvent_t ev_fork, ev_join;
+};
 template <class K, class V>
 ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint64_t n_total, uint64_t max_len,
-                      void* ws, hipStream_t s, const int* tune);
+                      void* ws, hipStream_t s, const int* tune, SegFork fork);
 template <class K, class V>
 size_t seg_temp_bytes(uint64_t nseg, uint64_t n_total);
 template <class K, class V>

@@ -27,9 +27,13 @@ static hipError_t launch_small(K* keys, V* vals, const int64_t* off, SegState st
   static const hipError_t ok = seg_allow_lds(&seg_small_kernel<K, V, WG, IPT, PAD>, TS::LDS_BYTES);
   if (ok != hipSuccess) return ok;
   const uint64_t per_cu = std::max(1, 2048 / WG);
-  const uint64_t grid = std::min<uint64_t>(nseg, uint64_t(device_cu_count()) * per_cu);
+  const uint64_t slots = uint64_t(device_cu_count()) * per_cu;
+  // segments per work grab: enough that every resident workgroup gets a few
+  // grabs when the whole batch sits in this class
+  const uint32_t chunk = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(64, nseg / (slots * 4))));
+  const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(nseg, chunk), slots));
   seg_small_kernel<K, V, WG, IPT, PAD><<<dim3(unsigned(grid)), dim3(WG), TS::LDS_BYTES, s>>>(keys, vals, off, st, cls,
-                                                                                            nseg);
+                                                                                            nseg, chunk);
   return hipGetLastError();
 }
 
@@ -94,7 +98,7 @@ struct SegCands {
 };
 
 struct SegLayout {
-  size_t cls_count, cls_work, large_ctr, queues, large_seg, large_mbase, owner, part, tk, tv, bytes;
+  size_t cls_count, cls_work, large_ctr, queues, large_seg, large_mbase, desc, part, tk, tv, bytes;
   uint64_t mt_cap;
 };
 
@@ -112,7 +116,7 @@ SegLayout seg_layout(uint64_t nseg, uint64_t n_total) {
   L.queues = take(sizeof(int32_t) * SEG_MAX_CLASSES * nseg);
   L.large_seg = take(sizeof(int32_t) * nseg);
   L.large_mbase = take(sizeof(int64_t) * nseg);
-  L.owner = take(sizeof(int32_t) * L.mt_cap);
+  L.desc = take(sizeof(int4) * L.mt_cap);
   L.part = take(sizeof(int64_t) * L.mt_cap);
   L.tk = take(sizeof(K) * n_total);
   L.tv = take(vb * n_total);
@@ -123,7 +127,7 @@ SegLayout seg_layout(uint64_t nseg, uint64_t n_total) {
 // Enqueue the whole segmented pipeline on stream s (possibly capturing).
 template <class K, class V>
 ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint64_t n_total, uint64_t max_len,
-                      void* ws, hipStream_t s, const int* tune) {
+                      void* ws, hipStream_t s, const int* tune, SegFork fork) {
   using S = SegCfg<K, V>;
   using P = PlainCfg<K, V>;
   const SegLayout L = seg_layout<K, V>(nseg, n_total);
@@ -135,7 +139,7 @@ ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint6
   st.queues = reinterpret_cast<int32_t*>(w + L.queues);
   st.large_seg = reinterpret_cast<int32_t*>(w + L.large_seg);
   st.large_mbase = reinterpret_cast<int64_t*>(w + L.large_mbase);
-  st.owner = reinterpret_cast<int32_t*>(w + L.owner);
+  st.desc = reinterpret_cast<int4*>(w + L.desc);
   st.part = reinterpret_cast<int64_t*>(w + L.part);
   K* tk = reinterpret_cast<K*>(w + L.tk);
   V* tv = reinterpret_cast<V*>(w + L.tv);
@@ -146,8 +150,16 @@ ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint6
   seg_owner_kernel<K, V><<<dim3(unsigned(std::min<uint64_t>(nseg, cus * 4))), dim3(256), 0, s>>>(off, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "segment classification launch");
+  // small classes run on a side branch (fork/join through events) so that
+  // they overlap the large-segment passes
+  hipStream_t side = fork.side ? fork.side : s;
+  if (fork.side) {
+    e = hipEventRecord(fork.ev_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, fork.ev_fork, 0);
+    if (e != hipSuccess) return hip_fail(e, "graph fork");
+  }
   for (int c = 0; c < S::NCLS; ++c) {
-    e = SegCands<K, V>::launch(S::cls_max(c), tune[c], keys, vals, off, st, c, nseg, s);
+    e = SegCands<K, V>::launch(S::cls_max(c), tune[c], keys, vals, off, st, c, nseg, side);
     if (e != hipSuccess) return hip_fail(e, "small-segment sort launch");
   }
   if (max_len > uint64_t(S::TILE)) {
@@ -159,20 +171,23 @@ ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint6
       return a != hipSuccess ? a : b;
     }();
     if (lds_ok != hipSuccess) return hip_fail(lds_ok, "LDS size attribute");
+    // one workgroup per reserved (merge) tile up to the host-side bound
     const uint64_t tiles_cap = L.mt_cap / S::C;
-    const uint64_t tgrid = std::min<uint64_t>(tiles_cap, cus * std::max(1, 2048 / P::BS_WG));
     seg_large_tile_kernel<K, V, P::BS_WG, P::BS_IPT, P::BS_PAD>
-        <<<dim3(unsigned(tgrid)), dim3(P::BS_WG), TS::LDS_BYTES, s>>>(keys, vals, tk, tv, off, st);
+        <<<dim3(unsigned(tiles_cap)), dim3(P::BS_WG), TS::LDS_BYTES, s>>>(keys, vals, tk, tv, st);
     const int passes = plan_passes(max_len, S::TILE);
-    const uint64_t pgrid = std::min<uint64_t>(ceil_div(L.mt_cap, 256), cus * 8);
-    const uint64_t mgrid = std::min<uint64_t>(L.mt_cap, cus * std::max(1, 2048 / P::MG_WG));
     for (int p = 0; p < passes; ++p) {
-      seg_partition_kernel<K, V><<<dim3(unsigned(pgrid)), dim3(256), 0, s>>>(keys, tk, off, st, p);
+      seg_partition_kernel<K, V><<<dim3(unsigned(ceil_div(L.mt_cap, 256))), dim3(256), 0, s>>>(keys, tk, st, p);
       seg_merge_kernel<K, V, P::MG_WG, P::MG_IPT, P::MG_PAD>
-          <<<dim3(unsigned(mgrid)), dim3(P::MG_WG), MT::LDS_BYTES, s>>>(keys, vals, tk, tv, off, st, p);
+          <<<dim3(unsigned(L.mt_cap)), dim3(P::MG_WG), MT::LDS_BYTES, s>>>(keys, vals, tk, tv, st, p);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "large-segment launch");
+  }
+  if (fork.side) {
+    e = hipEventRecord(fork.ev_join, side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, fork.ev_join, 0);
+    if (e != hipSuccess) return hip_fail(e, "graph join");
   }
   return MS_OK;
 }
@@ -201,7 +216,7 @@ void seg_candidate(int cls, int idx, int* wg, int* ipt) {
 
 #define MS_SEG_INSTANTIATE(K, V)                                                                              \
   template ms_status seg_enqueue<K, V>(K*, V*, const int64_t*, uint64_t, uint64_t, uint64_t, void*, hipStream_t, \
-                                       const int*);                                                           \
+                                       const int*, SegFork);                                                  \
   template size_t seg_temp_bytes<K, V>(uint64_t, uint64_t);                                                   \
   template int seg_num_classes<K, V>();                                                                       \
   template void seg_class_info<K, V>(int, uint32_t*, int*);                                                   \

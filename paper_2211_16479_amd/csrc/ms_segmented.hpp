@@ -7,8 +7,9 @@
 //   1. init      : clear the class counters (a fill kernel, no memset nodes);
 //   2. classify  : one thread per segment bins it by length into a small class
 //                  queue, or reserves merge tiles for it in the large list;
-//   3. owner     : writes, for every reserved merge tile, which large segment
-//                  it belongs to;
+//   3. owner     : writes, for every reserved merge tile, a descriptor (segment
+//                  start, length, tile index) so that the large-segment kernels
+//                  need one dependent load before touching keys;
 //   4. per small class c, a persistent kernel whose workgroups take segments
 //      from the class queue through an atomic work counter and sort each one
 //      entirely in LDS (the tile sort of ms_block_sort.hpp with the class's
@@ -35,9 +36,25 @@ struct SegState {
   int32_t* queues;       // [SEG_MAX_CLASSES][nseg] segment ids per small class
   int32_t* large_seg;    // [nseg] segment id per large slot
   int64_t* large_mbase;  // [nseg] first reserved merge tile per large slot
-  int32_t* owner;        // [mt_cap] large slot owning each merge tile
+  int4* desc;            // [mt_cap] per reserved merge tile: segment base (lo, hi), length, tile index
   int64_t* part;         // [mt_cap] merge-path splits of the current pass
 };
+
+// A reserved merge tile of a large segment, unpacked from its descriptor.
+struct SegTile {
+  int64_t base;  // segment start in the key array
+  uint64_t L;    // segment length
+  uint64_t lt;   // merge-tile index inside the segment
+};
+
+__device__ __forceinline__ SegTile seg_tile(const int4* desc, uint64_t g) {
+  const int4 d = desc[g];
+  SegTile t;
+  t.base = int64_t(uint64_t(uint32_t(d.x)) | (uint64_t(uint32_t(d.y)) << 32));
+  t.L = uint32_t(d.z);
+  t.lt = uint32_t(d.w);
+  return t;
+}
 
 constexpr unsigned long long SEG_SLOT_SHIFT = 40;
 constexpr unsigned long long SEG_TILE_MASK = (1ull << SEG_SLOT_SHIFT) - 1;
@@ -82,168 +99,196 @@ static __global__ void seg_init_kernel(SegState st) {
   if (t == 0) *st.large_ctr = 0;
 }
 
+// One thread per segment.  Slots are reserved in two steps so that a batch
+// of many small segments does not serialise on one global counter: threads
+// first count into workgroup-local LDS counters, then one thread per class
+// adds the workgroup's total to the global counter, and every thread's slot
+// is the global base plus its local offset.  (Order inside a class queue is
+// arbitrary; each segment is sorted independently, so results do not depend
+// on it.)  The large class uses one packed counter (segments << 40 | merge
+// tiles) so that slot order and merge-tile order agree.
 template <class K, class V>
 __global__ __launch_bounds__(256) void seg_classify_kernel(const int64_t* __restrict__ off, uint64_t nseg,
                                                            SegState st) {
   using S = SegCfg<K, V>;
+  __shared__ uint32_t l_cnt[SEG_MAX_CLASSES];
+  __shared__ uint32_t g_base[SEG_MAX_CLASSES];
+  __shared__ unsigned long long l_large, g_large;
   const uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (s >= nseg) return;
-  const int64_t b = off[s], e = off[s + 1];
-  if (e - b <= 1) return;  // nothing to sort
-  const uint64_t L = uint64_t(e - b);
-  const int c = seg_class<K, V>(L);
+  if (threadIdx.x < SEG_MAX_CLASSES) l_cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) l_large = 0;
+  __syncthreads();
+  int c = -1;
+  uint64_t L = 0;
+  uint32_t local = 0;
+  unsigned long long llocal = 0;
+  if (s < nseg) {
+    const int64_t b = off[s], e = off[s + 1];
+    if (e - b > 1) {
+      L = uint64_t(e - b);
+      c = seg_class<K, V>(L);
+      if (c < S::NCLS) {
+        local = atomicAdd(&l_cnt[c], 1u);
+      } else {
+        const unsigned long long mt = ((L + S::TILE - 1) / S::TILE) * S::C;
+        llocal = atomicAdd(&l_large, (1ull << SEG_SLOT_SHIFT) | mt);
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < S::NCLS && l_cnt[threadIdx.x] != 0)
+    g_base[threadIdx.x] = atomicAdd(&st.cls_count[threadIdx.x], l_cnt[threadIdx.x]);
+  if (threadIdx.x == 0 && l_large != 0) g_large = atomicAdd(st.large_ctr, l_large);
+  __syncthreads();
+  if (c < 0) return;
   if (c < S::NCLS) {
-    const uint32_t slot = atomicAdd(&st.cls_count[c], 1u);
-    st.queues[uint64_t(c) * nseg + slot] = int32_t(s);
+    st.queues[uint64_t(c) * nseg + g_base[c] + local] = int32_t(s);
   } else {
-    const unsigned long long mt = ((L + S::TILE - 1) / S::TILE) * S::C;
-    const unsigned long long old = atomicAdd(st.large_ctr, (1ull << SEG_SLOT_SHIFT) | mt);
-    const uint64_t slot = old >> SEG_SLOT_SHIFT;
+    const unsigned long long at = g_large + llocal;
+    const uint64_t slot = at >> SEG_SLOT_SHIFT;
     st.large_seg[slot] = int32_t(s);
-    st.large_mbase[slot] = int64_t(old & SEG_TILE_MASK);
+    st.large_mbase[slot] = int64_t(at & SEG_TILE_MASK);
   }
 }
 
+// Writes the descriptor of every reserved merge tile of every large segment.
 template <class K, class V>
 __global__ __launch_bounds__(256) void seg_owner_kernel(const int64_t* __restrict__ off, SegState st) {
   using S = SegCfg<K, V>;
   const uint64_t nlarge = (*st.large_ctr) >> SEG_SLOT_SHIFT;
   for (uint64_t slot = blockIdx.x; slot < nlarge; slot += gridDim.x) {
     const int32_t s = st.large_seg[slot];
-    const uint64_t L = uint64_t(off[s + 1] - off[s]);
+    const int64_t b = off[s];
+    const uint64_t L = uint64_t(off[s + 1] - b);
     const uint64_t mt = ((L + S::TILE - 1) / S::TILE) * S::C;
     const int64_t mb = st.large_mbase[slot];
-    for (uint64_t t = threadIdx.x; t < mt; t += blockDim.x) st.owner[mb + t] = int32_t(slot);
+    for (uint64_t t = threadIdx.x; t < mt; t += blockDim.x)
+      st.desc[mb + t] = make_int4(int(uint32_t(uint64_t(b))), int(uint32_t(uint64_t(b) >> 32)), int(uint32_t(L)),
+                                  int(uint32_t(t)));
   }
 }
 
-// Small class: workgroups fetch segments from the class queue until it is
-// drained; each segment is sorted in place in LDS.
+// Small class: workgroup b first takes queue chunk b (static), then grabs
+// further chunks of `chunk` consecutive queue entries from the class's atomic
+// work counter (which starts at gridDim.x chunks) until the queue is
+// drained.  Chunks cut the number of atomics on the one counter, which
+// otherwise serialises classes with hundreds of thousands of tiny segments.
+// Each segment is sorted in place in LDS.
 template <class K, class V, int WG, int IPT, int PAD>
 __global__ __launch_bounds__(WG) void seg_small_kernel(K* __restrict__ keys, V* __restrict__ vals,
                                                        const int64_t* __restrict__ off, SegState st, int cls,
-                                                       uint64_t nseg) {
+                                                       uint64_t nseg, uint32_t chunk) {
   using TS = TileSort<K, V, WG, IPT, PAD>;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t cur;
   const uint32_t count = st.cls_count[cls];
   const int32_t* q = st.queues + uint64_t(cls) * nseg;
-  for (;;) {
-    if (threadIdx.x == 0) cur = atomicAdd(&st.cls_work[cls], 1u);
-    __syncthreads();
-    const uint32_t i = cur;
-    __syncthreads();
-    if (i >= count) break;
-    const int32_t s = q[i];
-    const int64_t b = off[s];
-    const uint32_t L = uint32_t(off[s + 1] - b);
-    if constexpr (TS::PAIRS) {
-      TS::run(keys + b, vals + b, keys + b, vals + b, L, smem);
-    } else {
-      TS::template run<int>(keys + b, nullptr, keys + b, nullptr, L, smem);
+  uint32_t c0 = blockIdx.x * chunk;
+  while (c0 < count) {
+    const uint32_t c1 = c0 + chunk < count ? c0 + chunk : count;
+    for (uint32_t i = c0; i < c1; ++i) {
+      const int32_t s = q[i];
+      const int64_t b = off[s];
+      const uint32_t L = uint32_t(off[s + 1] - b);
+      if constexpr (TS::PAIRS) {
+        TS::run(keys + b, vals + b, keys + b, vals + b, L, smem);
+      } else {
+        TS::template run<int>(keys + b, nullptr, keys + b, nullptr, L, smem);
+      }
+      __syncthreads();
     }
+    if (threadIdx.x == 0) cur = (gridDim.x + atomicAdd(&st.cls_work[cls], 1u)) * chunk;
+    __syncthreads();
+    c0 = cur;
     __syncthreads();
   }
 }
 
-// Large segments, step 1: tile sort of every tile of every large segment.
+// Large segments, step 1: one workgroup per reserved tile (the grid covers
+// the host-side bound; workgroups past the device-side count return).
 template <class K, class V, int WG, int IPT, int PAD>
 __global__ __launch_bounds__(WG) void seg_large_tile_kernel(K* __restrict__ keys, V* __restrict__ vals,
-                                                            K* __restrict__ tk, V* __restrict__ tv,
-                                                            const int64_t* __restrict__ off, SegState st) {
+                                                            K* __restrict__ tk, V* __restrict__ tv, SegState st) {
   using S = SegCfg<K, V>;
   using TS = TileSort<K, V, WG, IPT, PAD>;
   static_assert(TS::TILE == S::TILE, "large-segment tile");
   extern __shared__ __align__(16) unsigned char smem[];
-  const uint64_t tiles = ((*st.large_ctr) & SEG_TILE_MASK) / S::C;
-  for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-    const int32_t slot = st.owner[t * S::C];
-    const int32_t s = st.large_seg[slot];
-    const int64_t b = off[s];
-    const uint64_t L = uint64_t(off[s + 1] - b);
-    const uint64_t j = t - uint64_t(st.large_mbase[slot]) / S::C;
-    if (j * S::TILE >= L) continue;  // reserved but past the segment end (uniform)
-    const uint64_t rem = L - j * S::TILE;
-    const uint32_t len = rem < uint64_t(S::TILE) ? uint32_t(rem) : uint32_t(S::TILE);
-    const bool to_caller = (seg_passes(L, S::TILE) & 1) == 0;
-    const uint64_t o = uint64_t(b) + j * S::TILE;
-    if constexpr (TS::PAIRS) {
-      TS::run(keys + o, vals + o, (to_caller ? keys : tk) + o, (to_caller ? vals : tv) + o, len, smem);
-    } else {
-      TS::template run<int>(keys + o, nullptr, (to_caller ? keys : tk) + o, nullptr, len, smem);
-    }
-    __syncthreads();
+  const uint64_t t = blockIdx.x;
+  if (t >= ((*st.large_ctr) & SEG_TILE_MASK) / S::C) return;
+  const SegTile d = seg_tile(st.desc, t * S::C);
+  const uint64_t j = d.lt / S::C;
+  if (j * S::TILE >= d.L) return;  // reserved but past the segment end
+  const uint64_t rem = d.L - j * S::TILE;
+  const uint32_t len = rem < uint64_t(S::TILE) ? uint32_t(rem) : uint32_t(S::TILE);
+  const bool to_caller = (seg_passes(d.L, S::TILE) & 1) == 0;
+  const uint64_t o = uint64_t(d.base) + j * S::TILE;
+  if constexpr (TS::PAIRS) {
+    TS::run(keys + o, vals + o, (to_caller ? keys : tk) + o, (to_caller ? vals : tv) + o, len, smem);
+  } else {
+    TS::template run<int>(keys + o, nullptr, (to_caller ? keys : tk) + o, nullptr, len, smem);
   }
 }
 
 // Large segments, pass p: partition (one thread per reserved merge tile).
 template <class K, class V>
 __global__ __launch_bounds__(256) void seg_partition_kernel(const K* __restrict__ keys, const K* __restrict__ tk,
-                                                            const int64_t* __restrict__ off, SegState st, int p) {
+                                                            SegState st, int p) {
   using S = SegCfg<K, V>;
-  const uint64_t mt = (*st.large_ctr) & SEG_TILE_MASK;
-  for (uint64_t g = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < mt; g += uint64_t(gridDim.x) * blockDim.x) {
-    const int32_t slot = st.owner[g];
-    const int32_t s = st.large_seg[slot];
-    const int64_t b = off[s];
-    const uint64_t L = uint64_t(off[s + 1] - b);
-    const int P = seg_passes(L, S::TILE);
-    if (p >= P) continue;
-    const uint64_t lt = g - uint64_t(st.large_mbase[slot]);
-    const uint64_t g0 = lt * S::MTILE;
-    if (g0 >= L) continue;
-    const K* src = (((P - p) & 1) == 0 ? keys : tk) + b;
-    const uint64_t W = uint64_t(S::TILE) << p;
-    const PassGeom q = pass_geom(g0, L, W);
-    st.part[g] = int64_t(q.pb + merge_path_split(src + q.pb, q.a_end - q.pb, src + q.a_end, q.b_end - q.a_end,
-                                                  g0 - q.pb));
-  }
+  const uint64_t g = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= ((*st.large_ctr) & SEG_TILE_MASK)) return;
+  const SegTile d = seg_tile(st.desc, g);
+  const int P = seg_passes(d.L, S::TILE);
+  if (p >= P) return;
+  const uint64_t g0 = d.lt * S::MTILE;
+  if (g0 >= d.L) return;
+  const K* src = (((P - p) & 1) == 0 ? keys : tk) + d.base;
+  const uint64_t W = uint64_t(S::TILE) << p;
+  const PassGeom q = pass_geom(g0, d.L, W);
+  st.part[g] = int64_t(q.pb + merge_path_split(src + q.pb, q.a_end - q.pb, src + q.a_end, q.b_end - q.a_end,
+                                                g0 - q.pb));
 }
 
-// Large segments, pass p: merge (workgroups loop over reserved merge tiles).
+// Large segments, pass p: merge (one workgroup per reserved merge tile).
 template <class K, class V, int WG, int IPT, int PAD>
 __global__ __launch_bounds__(WG) void seg_merge_kernel(K* __restrict__ keys, V* __restrict__ vals,
-                                                       K* __restrict__ tk, V* __restrict__ tv,
-                                                       const int64_t* __restrict__ off, SegState st, int p) {
+                                                       K* __restrict__ tk, V* __restrict__ tv, SegState st, int p) {
   using S = SegCfg<K, V>;
   using MT = MergeTile<K, V, WG, IPT, PAD>;
   static_assert(MT::TM == S::MTILE, "large-segment merge tile");
   extern __shared__ __align__(16) unsigned char smem[];
-  const uint64_t mt = (*st.large_ctr) & SEG_TILE_MASK;
-  for (uint64_t g = blockIdx.x; g < mt; g += gridDim.x) {
-    const int32_t slot = st.owner[g];
-    const int32_t s = st.large_seg[slot];
-    const int64_t b = off[s];
-    const uint64_t L = uint64_t(off[s + 1] - b);
-    const int P = seg_passes(L, S::TILE);
-    if (p >= P) continue;  // workgroup-uniform
-    const uint64_t lt = g - uint64_t(st.large_mbase[slot]);
-    const uint64_t g0 = lt * S::MTILE;
-    if (g0 >= L) continue;
-    const bool from_caller = ((P - p) & 1) == 0;
-    K* sk = (from_caller ? keys : tk) + b;
-    K* dk = (from_caller ? tk : keys) + b;
-    const uint64_t g1 = g0 + S::MTILE < L ? g0 + S::MTILE : L;
-    const uint64_t W = uint64_t(S::TILE) << p;
-    const PassGeom q = pass_geom(g0, L, W);
-    const uint64_t i0 = uint64_t(st.part[g]);
-    const uint64_t j0 = q.a_end + (g0 - q.pb) - (i0 - q.pb);
-    uint64_t i1, j1;
-    if (g1 == q.b_end) {
-      i1 = q.a_end;
-      j1 = q.b_end;
-    } else {
-      i1 = uint64_t(st.part[g + 1]);
-      j1 = q.a_end + (g1 - q.pb) - (i1 - q.pb);
-    }
-    if constexpr (MT::PAIRS) {
-      V* sv = (from_caller ? vals : tv) + b;
-      V* dv = (from_caller ? tv : vals) + b;
-      MT::run(sk, sv, dk, dv, i0, uint32_t(i1 - i0), j0, uint32_t(j1 - j0), g0, smem);
-    } else {
-      MT::template run<int>(sk, nullptr, dk, nullptr, i0, uint32_t(i1 - i0), j0, uint32_t(j1 - j0), g0, smem);
-    }
-    __syncthreads();
+  const uint64_t g = blockIdx.x;
+  if (g >= ((*st.large_ctr) & SEG_TILE_MASK)) return;
+  // the splits are loaded together with the descriptor (both indices are
+  // inside the scratch arrays: g + 1 < reserved tiles + C <= mt_cap); values
+  // that turn out not to be needed are ignored
+  const int64_t part0 = st.part[g], part1 = st.part[g + 1];
+  const SegTile d = seg_tile(st.desc, g);
+  const int P = seg_passes(d.L, S::TILE);
+  if (p >= P) return;
+  const uint64_t g0 = d.lt * S::MTILE;
+  if (g0 >= d.L) return;
+  const bool from_caller = ((P - p) & 1) == 0;
+  K* sk = (from_caller ? keys : tk) + d.base;
+  K* dk = (from_caller ? tk : keys) + d.base;
+  const uint64_t g1 = g0 + S::MTILE < d.L ? g0 + S::MTILE : d.L;
+  const uint64_t W = uint64_t(S::TILE) << p;
+  const PassGeom q = pass_geom(g0, d.L, W);
+  const uint64_t i0 = uint64_t(part0);
+  const uint64_t j0 = q.a_end + (g0 - q.pb) - (i0 - q.pb);
+  uint64_t i1, j1;
+  if (g1 == q.b_end) {
+    i1 = q.a_end;
+    j1 = q.b_end;
+  } else {
+    i1 = uint64_t(part1);
+    j1 = q.a_end + (g1 - q.pb) - (i1 - q.pb);
+  }
+  if constexpr (MT::PAIRS) {
+    V* sv = (from_caller ? vals : tv) + d.base;
+    V* dv = (from_caller ? tv : vals) + d.base;
+    MT::run(sk, sv, dk, dv, i0, uint32_t(i1 - i0), j0, uint32_t(j1 - j0), g0, smem);
+  } else {
+    MT::template run<int>(sk, nullptr, dk, nullptr, i0, uint32_t(i1 - i0), j0, uint32_t(j1 - j0), g0, smem);
   }
 }
 
