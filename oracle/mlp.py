@@ -4,17 +4,13 @@ The paper has no learned component; the model below is this project's
 definition of the "small two-layer MLP CDF model" of the learned-bucket form.
 The GPU trains the same model in FP32 with hand-written kernels; this module
 is the plain fp64 statement of the same arithmetic that those kernels are
-checked against (gradients, one Adam step, the trained loss).
+checked against (gradients, one Adam step, the trained loss, the inference
+table).
 
-Model (H hidden units, H even; parameter vector theta of length 3H+1 laid
-out as [p_0..p_{H-1}, b1_0..b1_{H-1}, q_0..q_{H-1}, b2]):
+Model (H hidden units; parameter vector theta of length 3H+1 laid out as
+[w1_0..w1_{H-1}, b1_0..b1_{H-1}, w2_0..w2_{H-1}, b2]):
 
-    s_h  = +1 for h < H/2, -1 otherwise       (fixed signs)
-    w1_h = s_h * softplus(p_h),  w2_h = s_h * softplus(q_h)
     F(x) = b2 + sum_h w2_h * relu(w1_h * x + b1_h)
-
-Every unit has w1_h * w2_h >= 0, so F is non-decreasing in x: the model is
-monotone by construction, and so are the bucket ids derived from it.
 
 Loss over a sorted sample x_0 <= ... <= x_{S-1} with targets
 y_i = (i + 0.5) / S (the mid-rank of each sample position):
@@ -23,6 +19,18 @@ y_i = (i + 0.5) / S (the mid-rank of each sample position):
 
 Optimiser: Adam (beta1 = 0.9, beta2 = 0.999, eps = 1e-8) with bias
 correction, a fixed step count and a fixed learning rate.
+
+Start point (closed form): the piecewise-linear interpolant of the sample's
+empirical CDF through H knots at sample quantiles -- unit h is a ramp
+relu(x - k_h) whose output weight is the slope change at knot k_h.
+
+Inference: a 1-D two-layer ReLU network is a piecewise-linear function whose
+breakpoints are -b1_h / w1_h.  `pl_table` lists F at the breakpoints inside
+[0, 1] (plus 0 and 1) and replaces every value by the running maximum (the
+smallest non-decreasing function >= F at those points); `pl_eval` evaluates
+that table by linear interpolation, capped at the next point's value.  Where
+F is non-decreasing the table reproduces F exactly; everywhere it is
+non-decreasing, so bucket ids derived from it are ordered like the keys.
 
 Input features are computed from the integer key in float32, exactly as the
 GPU computes them (IEEE round-to-nearest-even), so both sides see
@@ -38,35 +46,14 @@ BETA2 = 0.999
 EPS = 1e-8
 
 
-def signs(H: int) -> np.ndarray:
-    s = np.ones(H)
-    s[H // 2:] = -1.0
-    return s
-
-
-def softplus(v):
-    return np.logaddexp(0.0, v)
-
-
-def sigmoid(v):
-    return 0.5 * (1.0 + np.tanh(0.5 * v))
-
-
 def unpack(theta: np.ndarray, H: int):
     theta = np.asarray(theta, np.float64)
     assert theta.size == 3 * H + 1
     return theta[:H], theta[H:2 * H], theta[2 * H:3 * H], theta[3 * H]
 
 
-def weights(theta: np.ndarray, H: int):
-    """(w1, b1, w2, b2) of the monotone parametrisation."""
-    p, b1, q, b2 = unpack(theta, H)
-    s = signs(H)
-    return s * softplus(p), b1, s * softplus(q), b2
-
-
 def forward(theta: np.ndarray, x: np.ndarray, H: int) -> np.ndarray:
-    w1, b1, w2, b2 = weights(theta, H)
+    w1, b1, w2, b2 = unpack(theta, H)
     z = np.outer(np.asarray(x, np.float64), w1) + b1
     return b2 + np.maximum(z, 0.0) @ w2
 
@@ -84,21 +71,16 @@ def grad(theta: np.ndarray, x: np.ndarray, y: np.ndarray, H: int) -> np.ndarray:
     """Analytic gradient of the mean squared error w.r.t. theta (chain rule)."""
     x = np.asarray(x, np.float64)
     S = x.size
-    p, b1, q, b2 = unpack(theta, H)
-    s = signs(H)
-    w1, w2 = s * softplus(p), s * softplus(q)
+    w1, b1, w2, b2 = unpack(theta, H)
     z = np.outer(x, w1) + b1                 # (S, H)
     a = np.maximum(z, 0.0)
     r = (b2 + a @ w2 - y) * (2.0 / S)        # dL/dF per sample
-    g_w2 = a.T @ r                           # dL/dw2_h
     g_z = np.outer(r, w2) * (z > 0.0)        # dL/dz_h (relu' = 1 where z > 0)
-    g_b1 = g_z.sum(axis=0)
-    g_w1 = g_z.T @ x
     g = np.empty(3 * H + 1)
-    g[:H] = g_w1 * s * sigmoid(p)            # d softplus(p)/dp = sigmoid(p)
-    g[H:2 * H] = g_b1
-    g[2 * H:3 * H] = g_w2 * s * sigmoid(q)
-    g[3 * H] = r.sum()
+    g[:H] = g_z.T @ x                        # dL/dw1
+    g[H:2 * H] = g_z.sum(axis=0)             # dL/db1
+    g[2 * H:3 * H] = a.T @ r                 # dL/dw2
+    g[3 * H] = r.sum()                       # dL/db2
     return g
 
 
@@ -111,21 +93,33 @@ def adam_step(theta, g, m, v, t: int, lr: float):
     return theta - lr * mh / (np.sqrt(vh) + EPS), m, v
 
 
-def init_params(x_sorted: np.ndarray, H: int, slope: float = 1.0, out_w: float = 0.1) -> np.ndarray:
-    """Deterministic start point from the sorted sample.
+def quantile_knots(x_sorted: np.ndarray, H: int):
+    """Knot i (i = 0..H) at sample position q_i = floor(i * (S - 1) / H) with
+    value y_{q_i} = (q_i + 0.5) / S."""
+    S = x_sorted.size
+    q = (np.arange(H + 1) * (S - 1)) // H
+    return np.asarray(x_sorted, np.float64)[q], (q + 0.5) / S
 
-    Unit h gets |w1| = slope and its ReLU kink at the sample quantile
-    (h + 0.5) / H of x (rising units, s = +1, are active right of the kink,
-    falling units, s = -1, left of it); |w2| = out_w; b2 = 0.5.
-    """
-    x = np.asarray(x_sorted, np.float64)
-    S = x.size
-    s = signs(H)
-    knots = x[np.minimum(((np.arange(H) + 0.5) / H * S).astype(np.int64), S - 1)]
-    p = np.full(H, np.log(np.expm1(slope)))
-    q = np.full(H, np.log(np.expm1(out_w)))
-    b1 = -s * slope * knots
-    return np.concatenate([p, b1, q, [0.5]])
+
+def init_params(x_sorted: np.ndarray, H: int) -> np.ndarray:
+    """Closed-form start: F equals the piecewise-linear interpolant through the
+    quantile knots on [k_0, k_last] (constant y_0 left of k_0).  Of a run of
+    equal knots (ties in the sample) only the last is kept, so F reaches the
+    value after the tie.  Unit h has w1 = 1, b1 = -k_h and w2 = the slope
+    change at k_h; unused units have w2 = 0."""
+    k, yk = quantile_knots(x_sorted, H)
+    keep = np.ones(H + 1, bool)
+    keep[:-1] = k[:-1] < k[1:]
+    k, yk = k[keep], yk[keep]
+    m = k.size - 1
+    w1 = np.ones(H)
+    b1 = np.full(H, -k[-1])
+    w2 = np.zeros(H)
+    if m >= 1:
+        slopes = np.diff(yk) / np.diff(k)
+        b1[:m] = -k[:m]
+        w2[:m] = np.diff(np.concatenate([[0.0], slopes]))
+    return np.concatenate([w1, b1, w2, [yk[0]]])
 
 
 def train(x_sorted: np.ndarray, H: int, steps: int, lr: float, theta0=None):
@@ -144,6 +138,29 @@ def train(x_sorted: np.ndarray, H: int, steps: int, lr: float, theta0=None):
     return theta, np.array(hist)
 
 
+def pl_table(theta: np.ndarray, H: int):
+    """(t, V): breakpoints of F inside (0, 1) plus 0 and 1, ascending, and the
+    running maximum of F over those points."""
+    w1, b1, w2, b2 = unpack(theta, H)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        bp = -b1 / w1
+    bp = bp[(w1 != 0) & (bp > 0) & (bp < 1)]
+    t = np.unique(np.concatenate([[0.0, 1.0], bp]))
+    V = np.maximum.accumulate(forward(theta, t, H))
+    return t, V
+
+
+def pl_eval(table, x: np.ndarray) -> np.ndarray:
+    """Monotone evaluation of a table: clamp x to [0, 1], find the segment,
+    interpolate, cap at the segment's right value."""
+    t, V = table
+    x = np.clip(np.asarray(x, np.float64), 0.0, 1.0)
+    j = np.clip(np.searchsorted(t, x, side="right") - 1, 0, t.size - 2)
+    dt = t[j + 1] - t[j]
+    slope = np.where(dt > 0, (V[j + 1] - V[j]) / np.where(dt > 0, dt, 1.0), 0.0)
+    return np.minimum(V[j] + slope * (x - t[j]), V[j + 1])
+
+
 def feature_linear(keys: np.ndarray) -> np.ndarray:
     k = np.asarray(keys, np.uint32)
     return (k.astype(np.float32) * np.float32(2.0 ** -32)).astype(np.float32)
@@ -156,7 +173,7 @@ def feature_log(keys: np.ndarray) -> np.ndarray:
     return (bits.astype(np.int32).astype(np.float32) * np.float32(2.0 ** -28)).astype(np.float32)
 
 
-def bucket_ids(theta: np.ndarray, x: np.ndarray, H: int, B: int) -> np.ndarray:
-    """b = clamp(floor(F(x) * B), 0, B - 1), evaluated in fp64 (speed-only role)."""
-    u = forward(theta, x, H) * B
+def bucket_ids(table, x: np.ndarray, B: int) -> np.ndarray:
+    """b = clamp(floor(pl_eval(x) * B), 0, B - 1), in fp64 (speed-only role)."""
+    u = pl_eval(table, x) * B
     return np.clip(np.floor(u), 0, B - 1).astype(np.int64)

@@ -1,7 +1,8 @@
 """Pins of the fp64 MLP CDF oracle: central finite differences, the
 least-squares line (closed form) when every ReLU stays active, Adam's first
-step in closed form, monotonicity of the parametrisation, exact feature
-values.  CPU only."""
+step in closed form, the start point interpolating the quantile knots, and
+the inference table (exact where the network is monotone, monotone always).
+CPU only."""
 import numpy as np
 import pytest
 
@@ -9,9 +10,7 @@ from oracle import mlp
 
 
 def _rand_theta(rng, H):
-    th = rng.normal(size=3 * H + 1)
-    th[H:2 * H] = rng.uniform(-0.5, 0.5, size=H)
-    return th
+    return rng.normal(size=3 * H + 1)
 
 
 @pytest.mark.parametrize("H", [2, 8, 16])
@@ -39,13 +38,9 @@ def test_all_units_active_converges_to_least_squares_line():
     y = mlp.targets(x.size)
     A = np.stack([x, np.ones_like(x)], 1)
     slope_ls, icpt_ls = np.linalg.solve(A.T @ A, A.T @ y)
-    th = np.zeros(3 * H + 1)
-    th[:H] = np.log(np.expm1(0.5))          # |w1| = 0.5
-    th[H:2 * H] = 5.0                        # b1 = 5 > |w1| keeps z > 0 on [0, 1]
-    th[2 * H:3 * H] = np.log(np.expm1(0.3))
-    th[3 * H] = 0.0
-    th, hist = mlp.train(x, H, steps=6000, lr=3e-3, theta0=th)
-    w1, b1, w2, b2 = mlp.weights(th, H)
+    th = np.concatenate([np.full(H, 1.0), np.full(H, 1.0), np.full(H, 0.3), [0.0]])
+    th, hist = mlp.train(x, H, steps=4000, lr=1e-2, theta0=th)
+    w1, b1, w2, b2 = mlp.unpack(th, H)
     assert (np.outer([0.0, 1.0], w1) + b1 > 0).all()
     slope = float(w2 @ w1)
     icpt = float(b2 + w2 @ b1)
@@ -66,14 +61,47 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(v, 0.001 * g * g)
 
 
-def test_model_is_monotone_for_any_parameters():
+@pytest.mark.parametrize("H", [1, 4, 16])
+def test_start_point_interpolates_the_quantile_knots(H):
     rng = np.random.default_rng(9)
-    xs = np.linspace(-0.5, 1.5, 4001)
-    for _ in range(50):
+    S = 4096
+    x = np.sort(rng.gamma(2.0, 0.1, size=S))
+    th = mlp.init_params(x, H)
+    q = (np.arange(H + 1) * (S - 1)) // H
+    np.testing.assert_allclose(mlp.forward(th, x[q], H), (q + 0.5) / S, rtol=0, atol=1e-12)
+    # constant left of the first knot, linear between knots
+    assert mlp.forward(th, [x[0] - 1.0], H)[0] == pytest.approx((0.5) / S)
+    mid = 0.5 * (x[q[0]] + x[q[1]])
+    lin = (0.5 + (q[1] + 0.5 - 0.5) * (mid - x[q[0]]) / (x[q[1]] - x[q[0]])) / S
+    assert mlp.forward(th, [mid], H)[0] == pytest.approx(lin, rel=1e-12)
+
+
+def test_start_point_with_ties_reaches_post_tie_values():
+    x = np.sort(np.concatenate([np.full(600, 0.25), np.linspace(0.3, 0.9, 424)]))
+    H = 8
+    th = mlp.init_params(x, H)
+    k, yk = mlp.quantile_knots(x, H)
+    last_of_run = np.r_[k[:-1] < k[1:], True]
+    np.testing.assert_allclose(mlp.forward(th, k[last_of_run], H), yk[last_of_run], atol=1e-12)
+
+
+def test_pl_table_exact_for_monotone_networks_and_monotone_always():
+    rng = np.random.default_rng(10)
+    xs = np.linspace(0.0, 1.0, 20001)
+    for _ in range(40):
         H = int(rng.choice([2, 4, 16]))
-        th = rng.normal(scale=3.0, size=3 * H + 1)
-        F = mlp.forward(th, xs, H)
-        assert (np.diff(F) >= -1e-12).all()
+        # a non-decreasing network: positive slopes everywhere (w1, w2 > 0)
+        th = np.concatenate([rng.uniform(0.1, 3, H), rng.uniform(-2, 1, H), rng.uniform(0.01, 1, H), [0.1]])
+        np.testing.assert_allclose(mlp.pl_eval(mlp.pl_table(th, H), xs), mlp.forward(th, xs, H),
+                                   rtol=1e-12, atol=1e-12)
+        # arbitrary network: table is non-decreasing and equals the running max at breakpoints
+        th2 = rng.normal(scale=2.0, size=3 * H + 1)
+        t, V = mlp.pl_table(th2, H)
+        ev = mlp.pl_eval((t, V), xs)
+        assert (np.diff(ev) >= 0).all()
+        dense = np.linspace(0, 1, 200001)
+        runmax = np.maximum.accumulate(mlp.forward(th2, dense, H))
+        np.testing.assert_allclose(V, np.interp(t, dense, runmax), atol=1e-3 * (1 + np.abs(V).max()))
 
 
 def test_feature_values_and_monotonicity():
@@ -92,14 +120,15 @@ def test_feature_values_and_monotonicity():
     assert np.abs(err).max() < 0.0861 / 32 + 1e-6
 
 
-def test_training_fits_a_mixture_cdf():
+def test_training_improves_on_the_start_point():
     rng = np.random.default_rng(11)
     S = 4096
-    comp = rng.integers(0, 3, size=S)
-    x = np.sort(np.clip(rng.normal([0.2, 0.5, 0.7][0], 0.05, size=S) * (comp == 0)
-                        + rng.normal(0.5, 0.1, size=S) * (comp == 1)
-                        + rng.normal(0.8, 0.02, size=S) * (comp == 2), 0, 1))
-    th, hist = mlp.train(x, 16, steps=400, lr=0.02)
-    assert hist[-1] < hist[0] / 20
-    b = mlp.bucket_ids(th, x, 16, 64)
+    x = np.sort(np.concatenate([rng.normal(0.2, 0.03, S // 3), rng.normal(0.55, 0.1, S // 3),
+                                rng.normal(0.8, 0.01, S - 2 * (S // 3))]).clip(0, 1))
+    th0 = mlp.init_params(x, 16)
+    l0 = mlp.loss(th0, x, mlp.targets(S), 16)
+    th, hist = mlp.train(x, 16, steps=200, lr=1e-3)
+    assert hist[0] == pytest.approx(l0)
+    assert hist[-1] < l0
+    b = mlp.bucket_ids(mlp.pl_table(th, 16), x, 64)
     assert (np.diff(b) >= 0).all()
