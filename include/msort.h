@@ -148,6 +148,99 @@ ms_status ms_tuning_set(ms_key_type kt, size_t val_bytes, int cls, int wg, int i
 ms_status ms_tuning_get(ms_key_type kt, size_t val_bytes, int cls, int* wg, int* ipt);
 ms_status ms_tuning_load(const char* path, const char* arch, int* applied);
 
+/* ------------------------------------------------------------------------
+ * Learned-bucket form (uint32 keys).  A small two-layer ReLU MLP
+ *   F(x) = b2 + sum_h w2_h * relu(w1_h * x + b1_h),   H = 16 hidden units,
+ * of a feature x of the key (MS_FEATURE_LOG: a monotone piecewise-linear
+ * log2(1 + key) / 32 computed from the float bits; MS_FEATURE_LINEAR:
+ * key * 2^-32) is trained on the GPU to map keys to normalised ranks, on a
+ * sample of 2^sample_log2 keys that the plain merge sort ranks: closed-form
+ * start at the piecewise-linear interpolant through 16 sample quantiles,
+ * then full-batch Adam on the mean squared rank error.  The trained network
+ * is evaluated as the piecewise-linear function it is, through a running-max
+ * envelope, so bucket ids floor(F(x) * B) are non-decreasing in the key.
+ * Keys are scattered (two levels) into B ~ n / bucket_fill buckets; buckets
+ * of at most bucket_capacity keys are sorted in LDS; larger ones spill.  The
+ * spill is sorted by the plain merge sort and merged back with one exact
+ * merge-path pass.  If more than spill_threshold * n keys spill, or the order
+ * check of the buckets fails, the plain merge sort sorts the input instead
+ * (decided on the device).  The output is the same bytes as ms_sort's.
+ * ------------------------------------------------------------------------ */
+typedef enum ms_algo {
+  MS_ALGO_AUTO = 0,            /* learned for uint32 and n >= 2^22, else merge path */
+  MS_ALGO_MERGE_PATH = 1,
+  MS_ALGO_LEARNED_BUCKET = 2
+} ms_algo;
+
+typedef enum ms_feature { MS_FEATURE_LOG = 0, MS_FEATURE_LINEAR = 1 } ms_feature;
+
+typedef struct ms_options {
+  int algo;                  /* ms_algo */
+  float spill_threshold;     /* fall back when spilled keys > this * n; [0, 0.5], default 0.05 */
+  uint32_t bucket_capacity;  /* keys sorted per LDS bucket: 4096 or 16384 (default) */
+  uint32_t bucket_fill;      /* target mean keys per bucket, 64..capacity, default 2048 */
+  uint32_t train_steps;      /* Adam steps, default 128 */
+  float learning_rate;       /* default 1e-3 */
+  uint32_t sample_log2;      /* log2 of the sample size, 10..20, default 16 */
+  uint64_t seed;             /* sample positions, default 0 */
+  int feature;               /* ms_feature, default MS_FEATURE_LOG */
+  int use_network;           /* 1 (default); 0: bucket = floor(x * B) with no network */
+  int force_fallback;        /* 1: always take the plain merge sort (testing) */
+  int use_graph;             /* 1 (default): replay a cached hipGraph of the pipeline */
+} ms_options;
+
+/* Written on the device when the sort completes (valid after the stream). */
+typedef struct ms_stats {
+  int32_t algo_used;         /* MS_ALGO_MERGE_PATH or MS_ALGO_LEARNED_BUCKET */
+  int32_t fallback_taken;    /* the learned path handed over to the plain sort */
+  int32_t misordered;        /* the bucket order check failed */
+  int32_t repaired;          /* a spill was sorted and merged back */
+  uint64_t spilled;          /* keys in over-full buckets */
+  uint64_t max_bucket;       /* largest bucket */
+  uint64_t buckets;          /* number of buckets B */
+  float loss_initial;        /* training loss at the start point */
+  float loss_final;          /* training loss before the last step */
+} ms_stats;
+
+/* Default options (as documented above). */
+void ms_options_default(ms_options* opt);
+
+/*
+ * ms_sort_ex -- ms_sort with a choice of algorithm.  opt may be NULL
+ * (defaults); d_stats may be NULL, otherwise a device pointer to one
+ * ms_stats.  MS_ALGO_LEARNED_BUCKET requires MS_KEY_U32,
+ * n >= 4 * 2^sample_log2 and n < 2^32 (else MS_ERR_UNSUPPORTED); invalid
+ * options give MS_ERR_INVALID_ARG.  The learned pipeline is replayed from a
+ * cached hipGraph (use_graph = 1) keyed by pointers, n and options.
+ */
+ms_status ms_sort_ex(void* d_keys, size_t n, ms_key_type kt, const ms_options* opt, ms_stats* d_stats,
+                     void* stream);
+
+/*
+ * Steps of the learned form, for tests and inspection (all device pointers;
+ * parameters theta are 49 floats laid out [w1 x16, b1 x16, w2 x16, b2]):
+ *   ms_learned_grad   : at theta, over the sorted sample (S keys, target of
+ *                       position i = (i + 0.5) / S), write the gradient of the
+ *                       mean squared error (49 floats) and the sum of squared
+ *                       errors (1 float) to d_out[50].
+ *   ms_learned_train  : from d_theta0 (NULL: the quantile start point) run
+ *                       `steps` Adam steps; write the parameters to
+ *                       d_theta_out[49] and, if d_loss_hist is not NULL, the
+ *                       loss before each step to d_loss_hist[steps].
+ *   ms_learned_table  : the inference table of theta: breakpoints d_t[32]
+ *                       (ascending, +inf padded), running-max values d_v[32],
+ *                       count d_count[1].
+ *   ms_learned_bucket_ids : bucket id in [0, 2^log2_buckets) of each of n
+ *                       keys under theta (use_network = 0: floor(x * B)).
+ */
+ms_status ms_learned_grad(const uint32_t* d_sample, uint32_t S, int feature, const float* d_theta, float* d_out,
+                          void* stream);
+ms_status ms_learned_train(const uint32_t* d_sample, uint32_t S, int feature, uint32_t steps, float learning_rate,
+                           const float* d_theta0, float* d_theta_out, float* d_loss_hist, void* stream);
+ms_status ms_learned_table(const float* d_theta, float* d_t, float* d_v, int* d_count, void* stream);
+ms_status ms_learned_bucket_ids(const uint32_t* d_keys, size_t n, const float* d_theta, int feature, int use_network,
+                                uint32_t log2_buckets, uint32_t* d_out, void* stream);
+
 /*
  * ms_temp_bytes -- device scratch (bytes) that a plain sort of n keys with
  * values of val_bytes (0 = keys only) uses.  Host arithmetic only.

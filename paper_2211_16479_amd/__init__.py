@@ -27,6 +27,29 @@ PROFILE_KERNELS = {"tile_sort": 0, "partition": 1, "merge": 2, "seg_classify": 3
                    "seg_small": 4, "seg_large": 5, "mlp_train": 6, "learned_hist": 7,
                    "learned_scatter": 8, "bucket_sort": 9, "learned_other": 10}
 
+MS_ALGO_AUTO, MS_ALGO_MERGE_PATH, MS_ALGO_LEARNED_BUCKET = 0, 1, 2
+MS_FEATURE_LOG, MS_FEATURE_LINEAR = 0, 1
+MLP_HIDDEN = 16
+MLP_PARAMS = 3 * MLP_HIDDEN + 1
+
+
+class MsOptions(ctypes.Structure):
+    """ms_options of include/msort.h."""
+    _fields_ = [("algo", ctypes.c_int), ("spill_threshold", ctypes.c_float),
+                ("bucket_capacity", ctypes.c_uint32), ("bucket_fill", ctypes.c_uint32),
+                ("train_steps", ctypes.c_uint32), ("learning_rate", ctypes.c_float),
+                ("sample_log2", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("feature", ctypes.c_int),
+                ("use_network", ctypes.c_int), ("force_fallback", ctypes.c_int), ("use_graph", ctypes.c_int)]
+
+
+class MsStats(ctypes.Structure):
+    """ms_stats of include/msort.h."""
+    _fields_ = [("algo_used", ctypes.c_int32), ("fallback_taken", ctypes.c_int32),
+                ("misordered", ctypes.c_int32), ("repaired", ctypes.c_int32), ("spilled", ctypes.c_uint64),
+                ("max_bucket", ctypes.c_uint64), ("buckets", ctypes.c_uint64), ("loss_initial", ctypes.c_float),
+                ("loss_final", ctypes.c_float)]
+
+
 _lib = None
 
 
@@ -56,6 +79,12 @@ def _declare(lib):
         "ms_tuning_set": (i32, [i32, sz, i32, i32, i32]),
         "ms_tuning_get": (i32, [i32, sz, i32, c.POINTER(i32), c.POINTER(i32)]),
         "ms_tuning_load": (i32, [c.c_char_p, c.c_char_p, c.POINTER(i32)]),
+        "ms_options_default": (None, [c.POINTER(MsOptions)]),
+        "ms_sort_ex": (i32, [vp, sz, i32, c.POINTER(MsOptions), vp, vp]),
+        "ms_learned_grad": (i32, [vp, c.c_uint32, i32, vp, vp, vp]),
+        "ms_learned_train": (i32, [vp, c.c_uint32, i32, c.c_uint32, c.c_float, vp, vp, vp, vp]),
+        "ms_learned_table": (i32, [vp, vp, vp, vp, vp]),
+        "ms_learned_bucket_ids": (i32, [vp, sz, vp, i32, i32, c.c_uint32, vp, vp]),
         "ms_profile_enable": (i32, [i32]),
         "ms_profile_reset": (i32, []),
         "ms_profile_read": (i32, [i32, c.POINTER(c.c_uint64), c.POINTER(c.c_double)]),
@@ -205,6 +234,92 @@ def load_default_tuning(arch: str = None) -> int:
     if not os.path.exists(path):
         return 0
     return ms_tuning_load(path, arch)
+
+
+def ms_options_default() -> MsOptions:
+    o = MsOptions()
+    lib().ms_options_default(ctypes.byref(o))
+    return o
+
+
+def ms_sort_ex(keys: torch.Tensor, key_type=None, stats: bool = True, **options):
+    """ms_sort with an algorithm choice; keyword arguments set ms_options
+    fields (algo, spill_threshold, bucket_capacity, ...).  Returns
+    (keys, stats dict or None); stats are read after a stream sync."""
+    _dev(keys, "keys")
+    o = ms_options_default()
+    for k, v in options.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    st = torch.zeros(ctypes.sizeof(MsStats), dtype=torch.uint8, device=keys.device) if stats else None
+    _check(lib().ms_sort_ex(ctypes.c_void_p(keys.data_ptr()), keys.numel(), _key_type(keys, key_type),
+                            ctypes.byref(o), None if st is None else ctypes.c_void_p(st.data_ptr()),
+                            _stream(keys)), "ms_sort_ex")
+    if st is None:
+        return keys, None
+    torch.cuda.current_stream(keys.device).synchronize()
+    raw = MsStats.from_buffer_copy(bytes(st.cpu().numpy()))
+    return keys, {f: getattr(raw, f) for f, _ in MsStats._fields_}
+
+
+def _f32(t: torch.Tensor, n: int, name: str):
+    _dev(t, name)
+    if t.dtype != torch.float32 or t.numel() < n:
+        raise ValueError(f"{name} must be float32 with at least {n} elements")
+
+
+def ms_learned_grad(sample_sorted: torch.Tensor, theta: torch.Tensor, feature: int = MS_FEATURE_LOG):
+    """Gradient (49) and squared-error sum (1) of the MLP at theta on a sorted
+    uint32 sample; returns a float32 tensor of 50."""
+    _dev(sample_sorted, "sample")
+    _f32(theta, MLP_PARAMS, "theta")
+    out = torch.empty(MLP_PARAMS + 1, dtype=torch.float32, device=theta.device)
+    _check(lib().ms_learned_grad(ctypes.c_void_p(sample_sorted.data_ptr()), sample_sorted.numel(), feature,
+                                 ctypes.c_void_p(theta.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                 _stream(theta)), "ms_learned_grad")
+    return out
+
+
+def ms_learned_train(sample_sorted: torch.Tensor, steps: int, learning_rate: float, theta0: torch.Tensor = None,
+                     feature: int = MS_FEATURE_LOG):
+    """(theta after `steps` Adam steps, loss before each step)."""
+    _dev(sample_sorted, "sample")
+    dev = sample_sorted.device
+    th = torch.empty(MLP_PARAMS, dtype=torch.float32, device=dev)
+    hist = torch.empty(max(1, steps), dtype=torch.float32, device=dev)
+    if theta0 is not None:
+        _f32(theta0, MLP_PARAMS, "theta0")
+    _check(lib().ms_learned_train(ctypes.c_void_p(sample_sorted.data_ptr()), sample_sorted.numel(), feature, steps,
+                                  learning_rate, None if theta0 is None else ctypes.c_void_p(theta0.data_ptr()),
+                                  ctypes.c_void_p(th.data_ptr()), ctypes.c_void_p(hist.data_ptr()),
+                                  _stream(sample_sorted)), "ms_learned_train")
+    return th, hist[:steps]
+
+
+def ms_learned_table(theta: torch.Tensor):
+    """(breakpoints, running-max values, count) of theta's inference table."""
+    _f32(theta, MLP_PARAMS, "theta")
+    t = torch.empty(32, dtype=torch.float32, device=theta.device)
+    v = torch.empty(32, dtype=torch.float32, device=theta.device)
+    c = torch.empty(1, dtype=torch.int32, device=theta.device)
+    _check(lib().ms_learned_table(ctypes.c_void_p(theta.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                  ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(c.data_ptr()), _stream(theta)),
+           "ms_learned_table")
+    n = int(c.item())
+    return t[:n], v[:n], n
+
+
+def ms_learned_bucket_ids(keys: torch.Tensor, theta: torch.Tensor, log2_buckets: int,
+                          feature: int = MS_FEATURE_LOG, use_network: bool = True):
+    _dev(keys, "keys")
+    _f32(theta, MLP_PARAMS, "theta")
+    out = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
+    _check(lib().ms_learned_bucket_ids(ctypes.c_void_p(keys.data_ptr()), keys.numel(),
+                                       ctypes.c_void_p(theta.data_ptr()), feature, 1 if use_network else 0,
+                                       log2_buckets, ctypes.c_void_p(out.data_ptr()), _stream(keys)),
+           "ms_learned_bucket_ids")
+    return out
 
 
 def ms_temp_bytes(n: int, key_type: int, val_bytes: int = 0) -> int:

@@ -218,7 +218,8 @@ struct TileSort {
   }
 };
 
-// One workgroup per tile of the array: tiles [t*TILE, min(n, (t+1)*TILE)).
+// Tiles [t*TILE, min(n, (t+1)*TILE)); workgroup b takes tiles b, b + grid, ...
+// (one tile each when the grid covers them all).
 template <class K, class V, int WG, int IPT, int PAD>
 __global__ __launch_bounds__(WG) void block_sort_kernel(const K* in_k, const V* in_v, K* out_k, V* out_v,
                                                         uint64_t n_host, DevCtl ctl) {
@@ -226,14 +227,15 @@ __global__ __launch_bounds__(WG) void block_sort_kernel(const K* in_k, const V* 
   extern __shared__ __align__(16) unsigned char smem[];
   if (gated_off(ctl)) return;
   const uint64_t n = live_n(ctl, n_host);
-  const uint64_t base = uint64_t(blockIdx.x) * TS::TILE;
-  if (base >= n) return;
-  const uint64_t rem = n - base;
-  const uint32_t len = rem < uint64_t(TS::TILE) ? uint32_t(rem) : uint32_t(TS::TILE);
-  if constexpr (TS::PAIRS) {
-    TS::run(in_k + base, in_v + base, out_k + base, out_v + base, len, smem);
-  } else {
-    TS::template run<int>(in_k + base, nullptr, out_k + base, nullptr, len, smem);
+  for (uint64_t base = uint64_t(blockIdx.x) * TS::TILE; base < n; base += uint64_t(gridDim.x) * TS::TILE) {
+    const uint64_t rem = n - base;
+    const uint32_t len = rem < uint64_t(TS::TILE) ? uint32_t(rem) : uint32_t(TS::TILE);
+    if constexpr (TS::PAIRS) {
+      TS::run(in_k + base, in_v + base, out_k + base, out_v + base, len, smem);
+    } else {
+      TS::template run<int>(in_k + base, nullptr, out_k + base, nullptr, len, smem);
+    }
+    __syncthreads();
   }
 }
 

@@ -4,6 +4,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
@@ -189,7 +190,7 @@ static ms_status sort_impl(void* d_keys, void* d_vals, size_t n, ms_key_type kt,
       void* ws = nullptr;
       ms_status st = get_workspace(s, plain_temp_bytes<K, V>(n), &ws);
       if (st != MS_OK) return st;
-      return plain_sort<K, V>(static_cast<K*>(d_keys), static_cast<V*>(d_vals), n, DevCtl{nullptr, nullptr}, s,
+      return plain_sort<K, V>(static_cast<K*>(d_keys), static_cast<V*>(d_vals), n, DevCtl{nullptr, nullptr, nullptr}, s,
                               ws);
     });
   });
@@ -202,29 +203,18 @@ static ms_status with_types(ms_key_type kt, size_t vb, F&& f) {
   });
 }
 
-// ------------------------------------------------- segmented: graph cache
+// ------------------------------------------------------------ graph cache
+// Pipelines whose launch sequence is fixed on the host are captured once into
+// a hipGraph (per device, stream, pointers, sizes and options) that owns its
+// scratch, and replayed with one hipGraphLaunch.
 namespace {
-struct GraphKey {
-  int dev;
-  void* stream;
-  int kt;
-  size_t vb;
-  void* keys;
-  void* vals;
-  const void* off;
-  uint64_t nseg, n_total, max_len, gen;
-  bool operator<(const GraphKey& o) const {
-    return std::tie(dev, stream, kt, vb, keys, vals, off, nseg, n_total, max_len, gen) <
-           std::tie(o.dev, o.stream, o.kt, o.vb, o.keys, o.vals, o.off, o.nseg, o.n_total, o.max_len, o.gen);
-  }
-};
 struct GraphEntry {
   hipGraphExec_t exec = nullptr;
   void* ws = nullptr;
   uint64_t last_use = 0;
 };
 std::mutex g_graph_mu;
-std::map<GraphKey, GraphEntry> g_graphs;
+std::map<std::vector<uint64_t>, GraphEntry> g_graphs;
 struct CaptureStreams {
   hipStream_t main = nullptr, side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -241,13 +231,15 @@ void drop_graph(GraphEntry& e) {
 }
 }  // namespace
 
-static ms_status seg_run(void* d_keys, void* d_vals, const int64_t* d_off, uint64_t nseg, uint64_t n_total,
-                         uint64_t max_len, ms_key_type kt, size_t vb, hipStream_t s) {
+ms_status cached_graph_launch(std::vector<uint64_t> key, size_t ws_bytes,
+                              const std::function<ms_status(void* ws, hipStream_t cs, SegFork fork)>& enqueue,
+                              hipStream_t s) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  key.push_back(uint64_t(dev));
+  key.push_back(reinterpret_cast<uint64_t>(s));
   std::lock_guard<std::mutex> lk(g_graph_mu);
-  const GraphKey key{dev, s, int(kt), vb, d_keys, d_vals, d_off, nseg, n_total, max_len, seg_tuning_generation()};
   auto it = g_graphs.find(key);
   if (it == g_graphs.end()) {
     if (g_graphs.size() >= GRAPH_CACHE_MAX) {
@@ -259,16 +251,8 @@ static ms_status seg_run(void* d_keys, void* d_vals, const int64_t* d_off, uint6
       g_graphs.erase(lru);
     }
     GraphEntry ent;
-    size_t bytes = 0;
-    ms_status st = with_types(kt, vb, [&](auto kz, auto vz) -> ms_status {
-      using K = decltype(kz);
-      using V = decltype(vz);
-      bytes = seg_temp_bytes<K, V>(nseg, n_total);
-      return MS_OK;
-    });
-    if (st != MS_OK) return st;
-    e = hipMalloc(&ent.ws, bytes);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc (segmented scratch)");
+    e = hipMalloc(&ent.ws, ws_bytes ? ws_bytes : 256);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (graph scratch)");
     CaptureStreams& cap = g_capture_streams[dev];
     if (!cap.main) {
       e = hipStreamCreateWithFlags(&cap.main, hipStreamNonBlocking);
@@ -277,18 +261,11 @@ static ms_status seg_run(void* d_keys, void* d_vals, const int64_t* d_off, uint6
       if (e == hipSuccess) e = hipEventCreateWithFlags(&cap.ev_join, hipEventDisableTiming);
       if (e != hipSuccess) { drop_graph(ent); return hip_fail(e, "capture streams"); }
     }
-    hipStream_t cs = cap.main;
-    e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    e = hipStreamBeginCapture(cap.main, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) { drop_graph(ent); return hip_fail(e, "hipStreamBeginCapture"); }
-    const int* tune = seg_tuning_row(kt, vb);
-    st = with_types(kt, vb, [&](auto kz, auto vz) -> ms_status {
-      using K = decltype(kz);
-      using V = decltype(vz);
-      return seg_enqueue<K, V>(static_cast<K*>(d_keys), static_cast<V*>(d_vals), d_off, nseg, n_total, max_len,
-                               ent.ws, cs, tune, SegFork{cap.side, cap.ev_fork, cap.ev_join});
-    });
+    ms_status st = enqueue(ent.ws, cap.main, SegFork{cap.side, cap.ev_fork, cap.ev_join});
     hipGraph_t graph = nullptr;
-    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    hipError_t e2 = hipStreamEndCapture(cap.main, &graph);
     if (st != MS_OK || e2 != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
       drop_graph(ent);
@@ -305,10 +282,35 @@ static ms_status seg_run(void* d_keys, void* d_vals, const int64_t* d_off, uint6
   return MS_OK;
 }
 
+static ms_status seg_run(void* d_keys, void* d_vals, const int64_t* d_off, uint64_t nseg, uint64_t n_total,
+                         uint64_t max_len, ms_key_type kt, size_t vb, hipStream_t s) {
+  size_t bytes = 0;
+  ms_status st = with_types(kt, vb, [&](auto kz, auto vz) -> ms_status {
+    bytes = seg_temp_bytes<decltype(kz), decltype(vz)>(nseg, n_total);
+    return MS_OK;
+  });
+  if (st != MS_OK) return st;
+  std::vector<uint64_t> key = {1, uint64_t(kt), vb, reinterpret_cast<uint64_t>(d_keys),
+                               reinterpret_cast<uint64_t>(d_vals), reinterpret_cast<uint64_t>(d_off), nseg, n_total,
+                               max_len, seg_tuning_generation()};
+  const int* tune = seg_tuning_row(kt, vb);
+  return cached_graph_launch(
+      key, bytes,
+      [&](void* ws, hipStream_t cs, SegFork fork) -> ms_status {
+        return with_types(kt, vb, [&](auto kz, auto vz) -> ms_status {
+          using K = decltype(kz);
+          using V = decltype(vz);
+          return seg_enqueue<K, V>(static_cast<K*>(d_keys), static_cast<V*>(d_vals), d_off, nseg, n_total, max_len,
+                                   ws, cs, tune, fork);
+        });
+      },
+      s);
+}
+
 static void release_graphs(int dev) {
   std::lock_guard<std::mutex> lk(g_graph_mu);
   for (auto it = g_graphs.begin(); it != g_graphs.end();) {
-    if (it->first.dev == dev) {
+    if (it->first[it->first.size() - 2] == uint64_t(dev)) {
       drop_graph(it->second);
       it = g_graphs.erase(it);
     } else {

@@ -201,8 +201,9 @@ __device__ __forceinline__ void load_run(const E* __restrict__ src, E (&v)[N]) {
 // that lives in device memory (set by an earlier kernel) and a gate flag that
 // lets a kernel return at once when its stage is not needed.
 struct DevCtl {
-  const uint64_t* n_dev;  // if non-null, the element count (<= the host bound)
-  const int* gate;        // if non-null and *gate == 0, the kernel does nothing
+  const uint64_t* n_dev;      // if non-null, the element count (<= the host bound)
+  const int* gate;            // if non-null and *gate == 0, the kernel does nothing
+  const uint64_t* split_dev;  // if non-null: one merge of run [0, split) with [split, n)
 };
 
 __device__ __forceinline__ bool gated_off(const DevCtl& c) { return c.gate && *c.gate == 0; }

@@ -2,7 +2,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <string>
+#include <vector>
 
 #include "../../include/msort.h"
 #include "ms_common.hpp"
@@ -43,12 +45,19 @@ ms_status get_workspace(hipStream_t s, size_t bytes, void** out);
 
 // Plain merge sort of n keys (and values) already resident on the device.
 // ctl may carry a device-side count (n is then an upper bound) and a gate.
+// max_grid > 0 caps every launch's grid (workgroups then loop over tiles);
+// gated uses pass a small cap so that skipped stages cost little.
 template <class K, class V>
-ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, void* ws);
+ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, void* ws, uint64_t max_grid = 0);
 template <class K, class V>
 size_t plain_temp_bytes(uint64_t n);
 template <class K, class V>
 void plain_geometry(int* tile, int* merge_tile);
+// One merge of src[0, split) with src[split, n) into dst (split on the device),
+// as the plain sort's partition + merge kernels; part needs ceil(n/merge tile).
+template <class K, class V>
+ms_status merge_two_runs(const K* src, K* dst, uint64_t n, DevCtl ctl, int64_t* part, hipStream_t s,
+                         uint64_t max_grid = 0);
 
 // Segmented sort (ms_seg_launch.hpp): enqueue the whole pipeline on s.  If
 // fork.side is set, the small classes go to that stream between a fork and a
@@ -59,7 +68,7 @@ struct SegFork {
 };
 template <class K, class V>
 ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint64_t n_total, uint64_t max_len,
-                      void* ws, hipStream_t s, const int* tune, SegFork fork);
+                      void* ws, hipStream_t s, const int* tune, SegFork fork, void* const* keys_sel = nullptr);
 template <class K, class V>
 size_t seg_temp_bytes(uint64_t nseg, uint64_t n_total);
 template <class K, class V>
@@ -70,5 +79,11 @@ template <class K, class V>
 void seg_candidate(int cls, int idx, int* wg, int* ipt);
 
 int device_cu_count();
+
+// Capture `enqueue` once per key into a hipGraph that owns ws_bytes of
+// scratch, then launch it on s (cache of 8 graphs, least recently used out).
+ms_status cached_graph_launch(std::vector<uint64_t> key, size_t ws_bytes,
+                              const std::function<ms_status(void* ws, hipStream_t cs, SegFork fork)>& enqueue,
+                              hipStream_t s);
 
 }  // namespace ms

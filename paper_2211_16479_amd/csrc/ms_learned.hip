@@ -1,0 +1,412 @@
+// Learned-bucket sort: host side (plan, scratch layout, launch sequence) and
+// its C ABI (ms_sort_ex and the step-level entry points used by tests).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "ms_internal.hpp"
+#include "ms_learned.hpp"
+#include "ms_plan.hpp"
+#include "ms_tuning.hpp"
+
+namespace ms {
+
+__global__ void ls_setup_kernel(LsModel* md, int log_feature, int use_table, int coarse_bits, int fine_bits) {
+  if (threadIdx.x != 0) return;
+  md->log_feature = log_feature;
+  md->use_table = use_table;
+  md->coarse_bits = coarse_bits;
+  md->fine_bits = fine_bits;
+  md->nbins_c = 1u << coarse_bits;
+  md->nbins_f = 1u << fine_bits;
+  md->fallback = 0;
+  md->do_learned = 0;
+  md->do_repair = 0;
+  md->misordered = 0;
+  md->spilled = 0;
+  md->kept = 0;
+  md->max_bucket = 0;
+  md->loss0 = 0.f;
+  md->loss_last = 0.f;
+}
+
+__global__ void ls_set_theta_kernel(LsModel* md, const float* theta) {
+  const int p = threadIdx.x;
+  if (p < LS_P) {
+    md->theta[0][p] = theta[p];
+    md->m[0][p] = 0.f;
+    md->v[0][p] = 0.f;
+  }
+}
+
+__global__ void ls_get_theta_kernel(const LsModel* md, int parity, float* theta) {
+  const int p = threadIdx.x;
+  if (p < LS_P) theta[p] = md->theta[parity][p];
+}
+
+__global__ void ls_get_table_kernel(const LsModel* md, float* t, float* v, int* nt) {
+  const int i = threadIdx.x;
+  if (i < LS_TAB) {
+    t[i] = md->tab_t[i];
+    v[i] = md->tab_v[i];
+  }
+  if (i == 0) *nt = md->tab_n;
+}
+
+__global__ __launch_bounds__(256) void ls_bucket_ids_kernel(const uint32_t* __restrict__ keys, uint64_t n,
+                                                            const LsModel* md, uint32_t* __restrict__ out) {
+  __shared__ LsTable tb;
+  ls_load_table(md, &tb);
+  __syncthreads();
+  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = ls_bucket(&tb, keys[i]);
+}
+
+__global__ void ls_plain_stats_kernel(ms_stats* st) {
+  if (threadIdx.x != 0) return;
+  *st = ms_stats{};
+  st->algo_used = MS_ALGO_MERGE_PATH;
+}
+
+__global__ void ls_stats_kernel(const LsModel* md, ms_stats* st, uint64_t buckets) {
+  if (threadIdx.x != 0) return;
+  st->algo_used = md->fallback ? MS_ALGO_MERGE_PATH : MS_ALGO_LEARNED_BUCKET;
+  st->fallback_taken = md->fallback;
+  st->misordered = md->misordered;
+  st->repaired = md->do_repair;
+  st->spilled = md->spilled;
+  st->max_bucket = md->max_bucket;
+  st->buckets = buckets;
+  st->loss_initial = md->loss0;
+  st->loss_final = md->loss_last;
+}
+
+// Sizes of one learned sort.
+struct LsPlan {
+  uint32_t S;          // sample size
+  int cb, fb;          // coarse / fine bits
+  uint32_t nbc, nbf;   // coarse / fine bins
+  uint64_t B;          // buckets
+  uint64_t spill_cap;  // spill that still takes the learned path
+  uint64_t chunk_cap;  // bound on level-2 chunks
+  // scratch offsets
+  size_t md, sample, sample_tmp, partial, loss, bins, coarse, xr, part, seg, bytes;
+  size_t bins_c_off[12], bins_f_off[5];
+};
+
+static LsPlan ls_plan(uint64_t n, const ms_options& o) {
+  LsPlan P{};
+  P.S = 1u << o.sample_log2;
+  const uint64_t want = std::max<uint64_t>(1, (n + o.bucket_fill - 1) / o.bucket_fill);
+  int tb = 0;
+  while ((uint64_t(1) << tb) < want && tb < 20) ++tb;
+  P.cb = std::min(tb, 10);
+  P.fb = tb - P.cb;
+  P.nbc = 1u << P.cb;
+  P.nbf = 1u << P.fb;
+  P.B = uint64_t(1) << tb;
+  P.spill_cap = std::min<uint64_t>(n, uint64_t(std::ceil(double(o.spill_threshold) * double(n))));
+  P.chunk_cap = ceil_div(n, LS_CHK) + P.nbc;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t at = off; off = align_up(off + bytes, 256); return at; };
+  P.md = take(sizeof(LsModel));
+  P.sample = take(sizeof(uint32_t) * P.S);
+  P.sample_tmp = take(plain_temp_bytes<uint32_t, NoVal>(P.S));
+  P.partial = take(sizeof(float) * 2 * LS_TRAIN_G * LS_PS);
+  P.loss = take(sizeof(float) * (o.train_steps + 1));
+  for (int i = 0; i < 12; ++i) P.bins_c_off[i] = take(sizeof(uint32_t) * (P.nbc + 1));
+  for (int i = 0; i < 4; ++i) P.bins_f_off[i] = take(sizeof(uint32_t) * P.B);
+  P.bins_f_off[4] = take(sizeof(int64_t) * (P.B + 1));
+  P.coarse = take(std::max<size_t>(sizeof(uint32_t) * n, plain_temp_bytes<uint32_t, NoVal>(n)));
+  P.xr = take(sizeof(uint32_t) * n);
+  P.part = take(sizeof(int64_t) * (ceil_div(n, 2048) + 2));
+  P.seg = take(seg_temp_bytes<uint32_t, NoVal>(P.B, o.bucket_capacity));
+  P.bytes = off;
+  return P;
+}
+
+static LsBins ls_bins(char* w, const LsPlan& P) {
+  LsBins b;
+  uint32_t** c[12] = {&b.cnt_c, &b.off_c, &b.cursor_c, &b.chunk_start, &b.kept_tot, &b.spill_tot,
+                      &b.cmin, &b.cmax, &b.cbad, &b.cmaxb, &b.kept_base, &b.spill_base};
+  for (int i = 0; i < 12; ++i) *c[i] = reinterpret_cast<uint32_t*>(w + P.bins_c_off[i]);
+  b.cnt_f = reinterpret_cast<uint32_t*>(w + P.bins_f_off[0]);
+  b.fmin = reinterpret_cast<uint32_t*>(w + P.bins_f_off[1]);
+  b.fmax = reinterpret_cast<uint32_t*>(w + P.bins_f_off[2]);
+  b.cursor_f = reinterpret_cast<uint32_t*>(w + P.bins_f_off[3]);
+  b.seg_off = reinterpret_cast<int64_t*>(w + P.bins_f_off[4]);
+  return b;
+}
+
+// Model training on an already sorted sample: start point, then T Adam steps.
+static ms_status ls_train_enqueue(const uint32_t* sample, uint32_t S, LsModel* md, float* partial, int T, float lr,
+                                  float* loss_hist, bool init, hipStream_t s) {
+  if (init) ls_init_kernel<<<1, 64, 0, s>>>(sample, S, md);
+  for (int t = 0; t <= T; ++t) {
+    ProfScope ps(PK_LEARN_TRAIN, s);
+    ls_train_kernel<<<LS_TRAIN_G, LS_TRAIN_WG, 0, s>>>(sample, S, md, partial, t, T, lr, loss_hist, nullptr, nullptr);
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MS_OK : hip_fail(e, "training launch");
+}
+
+static ms_status learned_enqueue(uint32_t* keys, uint64_t n, const ms_options& o, ms_stats* d_stats, void* ws,
+                                 hipStream_t s) {
+  const LsPlan P = ls_plan(n, o);
+  char* w = static_cast<char*>(ws);
+  LsModel* md = reinterpret_cast<LsModel*>(w + P.md);
+  uint32_t* sample = reinterpret_cast<uint32_t*>(w + P.sample);
+  float* partial = reinterpret_cast<float*>(w + P.partial);
+  float* loss = reinterpret_cast<float*>(w + P.loss);
+  uint32_t* coarse = reinterpret_cast<uint32_t*>(w + P.coarse);
+  uint32_t* xr = reinterpret_cast<uint32_t*>(w + P.xr);
+  int64_t* part = reinterpret_cast<int64_t*>(w + P.part);
+  const LsBins bn = ls_bins(w, P);
+  const DevCtl none{nullptr, nullptr, nullptr};
+
+  ls_setup_kernel<<<1, 64, 0, s>>>(md, o.feature == MS_FEATURE_LOG ? 1 : 0, o.use_network ? 1 : 0, P.cb, P.fb);
+  // sample, ranked by the plain merge sort
+  ls_sample_kernel<<<dim3(unsigned(ceil_div(P.S, 256))), 256, 0, s>>>(keys, n, P.S, o.seed, sample);
+  ms_status st = plain_sort<uint32_t, NoVal>(sample, nullptr, P.S, none, s, w + P.sample_tmp);
+  if (st != MS_OK) return st;
+  // train and compile the network
+  st = ls_train_enqueue(sample, P.S, md, partial, int(o.train_steps), o.learning_rate, loss, true, s);
+  if (st != MS_OK) return st;
+  ls_compile_kernel<<<1, 64, 0, s>>>(md, int(o.train_steps) & 1, nullptr);
+  // level 1
+  ls_clear_kernel<<<dim3(unsigned(ceil_div(std::max<uint64_t>(P.B, P.nbc), 256))), 256, 0, s>>>(bn, P.nbc,
+                                                                                                 uint32_t(P.B));
+  const unsigned chunks1 = unsigned(ceil_div(n, LS_CHK));
+  {
+    ProfScope ps(PK_LEARN_HIST, s);
+    ls_hist1_kernel<<<chunks1, LS_WG, 0, s>>>(keys, n, md, bn);
+  }
+  ls_plan1_kernel<<<1, LS_WG, 0, s>>>(md, bn);
+  {
+    ProfScope ps(PK_LEARN_SCATTER, s);
+    ls_scatter1_kernel<<<chunks1, LS_WG, 0, s>>>(keys, n, md, bn, coarse);
+  }
+  // level 2
+  {
+    ProfScope ps(PK_LEARN_HIST, s);
+    ls_hist2_kernel<<<unsigned(P.chunk_cap), LS_WG, 0, s>>>(coarse, md, bn);
+  }
+  ls_totals_kernel<<<P.nbc, LS_WG, 0, s>>>(md, bn, o.bucket_capacity);
+  ls_plan2_kernel<<<1, LS_WG, 0, s>>>(md, bn, n, P.spill_cap, o.force_fallback, keys, xr);
+  ls_offsets_kernel<<<P.nbc, LS_WG, 0, s>>>(md, bn, o.bucket_capacity);
+  {
+    ProfScope ps(PK_LEARN_SCATTER, s);
+    ls_scatter2_kernel<<<unsigned(P.chunk_cap), LS_WG, 0, s>>>(coarse, md, bn, o.bucket_capacity, xr);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "learned bucketing launch");
+  // kept buckets: sorted in LDS by the segmented small-class kernels, in the
+  // array chosen on the device (*md->r_keys)
+  {
+    ProfScope ps(PK_LEARN_BUCKET, s);
+    st = seg_enqueue<uint32_t, NoVal>(keys, nullptr, bn.seg_off, P.B, o.bucket_capacity, o.bucket_capacity, w + P.seg,
+                                      s, seg_tuning_row(MS_KEY_U32, 0), SegFork{nullptr, nullptr, nullptr},
+                                      reinterpret_cast<void* const*>(&md->r_keys));
+  }
+  if (st != MS_OK) return st;
+  // repair: spill sorted by the plain merge sort, then merged with the kept keys
+  // (gated stages run with a bounded grid: when skipped they cost little)
+  const uint64_t gated_grid = uint64_t(device_cu_count()) * 4;
+  const uint64_t* spilled = reinterpret_cast<const uint64_t*>(&md->spilled);
+  if (P.spill_cap > 0) {
+    st = plain_sort<uint32_t, NoVal>(xr, nullptr, P.spill_cap, DevCtl{spilled, &md->do_repair, nullptr}, s, coarse,
+                                     gated_grid);
+    if (st != MS_OK) return st;
+    st = merge_two_runs<uint32_t, NoVal>(xr, keys, n, DevCtl{nullptr, &md->do_repair, spilled}, part, s,
+                                         gated_grid);
+    if (st != MS_OK) return st;
+  }
+  // fallback: the plain merge sort of the untouched input
+  st = plain_sort<uint32_t, NoVal>(keys, nullptr, n, DevCtl{nullptr, &md->fallback, nullptr}, s, coarse,
+                                   gated_grid);
+  if (st != MS_OK) return st;
+  if (d_stats) ls_stats_kernel<<<1, 64, 0, s>>>(md, d_stats, P.B);
+  e = hipGetLastError();
+  return e == hipSuccess ? MS_OK : hip_fail(e, "learned sort launch");
+}
+
+static ms_status check_options(const ms_options& o) {
+  if (o.algo < MS_ALGO_AUTO || o.algo > MS_ALGO_LEARNED_BUCKET) return MS_ERR_INVALID_ARG;
+  if (!(o.spill_threshold >= 0.f && o.spill_threshold <= 0.5f)) return MS_ERR_INVALID_ARG;
+  if (o.bucket_capacity != 4096 && o.bucket_capacity != 16384) return MS_ERR_INVALID_ARG;
+  if (o.bucket_fill < 64 || o.bucket_fill > o.bucket_capacity) return MS_ERR_INVALID_ARG;
+  if (o.train_steps > 100000) return MS_ERR_INVALID_ARG;
+  if (!(o.learning_rate >= 0.f && o.learning_rate < 1.f)) return MS_ERR_INVALID_ARG;
+  if (o.sample_log2 < 10 || o.sample_log2 > 20) return MS_ERR_INVALID_ARG;
+  if (o.feature != MS_FEATURE_LOG && o.feature != MS_FEATURE_LINEAR) return MS_ERR_INVALID_ARG;
+  return MS_OK;
+}
+
+// A scratch LsModel for the step-level entry points (per device, stream).
+static ms_status step_scratch(hipStream_t s, size_t extra, char** w) {
+  void* p = nullptr;
+  ms_status st = get_workspace(s, align_up(sizeof(LsModel), 256) + align_up(extra, 256), &p);
+  *w = static_cast<char*>(p);
+  return st;
+}
+
+}  // namespace ms
+
+using namespace ms;
+
+extern "C" {
+
+void ms_options_default(ms_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->algo = MS_ALGO_AUTO;
+  o->spill_threshold = 0.05f;
+  o->bucket_capacity = 16384;
+  o->bucket_fill = 2048;
+  o->train_steps = 128;
+  o->learning_rate = 1e-3f;
+  o->sample_log2 = 16;
+  o->seed = 0;
+  o->feature = MS_FEATURE_LOG;
+  o->use_network = 1;
+  o->force_fallback = 0;
+  o->use_graph = 1;
+}
+
+ms_status ms_sort_ex(void* d_keys, size_t n, ms_key_type kt, const ms_options* opt, ms_stats* d_stats, void* stream) {
+  ms_options o;
+  ms_options_default(&o);
+  if (opt) o = *opt;
+  if (check_options(o) != MS_OK) {
+    set_error("invalid ms_options");
+    return MS_ERR_INVALID_ARG;
+  }
+  if (n > 0 && d_keys == nullptr) {
+    set_error("d_keys is NULL with n > 0");
+    return MS_ERR_INVALID_ARG;
+  }
+  if (kt < MS_KEY_U32 || kt > MS_KEY_I64) {
+    set_error("unknown key type");
+    return MS_ERR_UNSUPPORTED;
+  }
+  if (n == 0) return MS_OK;
+  const bool learned_ok = kt == MS_KEY_U32 && n >= (uint64_t(4) << o.sample_log2) && n < (uint64_t(1) << 32);
+  if (o.algo == MS_ALGO_LEARNED_BUCKET && !learned_ok) {
+    set_error("the learned-bucket form needs uint32 keys, n >= 4 * sample size and n < 2^32");
+    return MS_ERR_UNSUPPORTED;
+  }
+  const bool learned = learned_ok && o.algo != MS_ALGO_MERGE_PATH && (o.algo == MS_ALGO_LEARNED_BUCKET || n >= (1u << 22));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!learned) {
+    ms_status st = ms_sort(d_keys, n, kt, stream);
+    if (st != MS_OK || !d_stats) return st;
+    ls_plain_stats_kernel<<<1, 64, 0, s>>>(d_stats);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MS_OK : hip_fail(e, "stats launch");
+  }
+  try {
+    const LsPlan P = ls_plan(n, o);
+    uint32_t* keys = static_cast<uint32_t*>(d_keys);
+    if (!o.use_graph) {
+      void* ws = nullptr;
+      ms_status st = get_workspace(s, P.bytes, &ws);
+      if (st != MS_OK) return st;
+      return learned_enqueue(keys, n, o, d_stats, ws, s);
+    }
+    uint32_t lr_bits, th_bits;
+    std::memcpy(&lr_bits, &o.learning_rate, 4);
+    std::memcpy(&th_bits, &o.spill_threshold, 4);
+    std::vector<uint64_t> key = {2, reinterpret_cast<uint64_t>(d_keys), n, reinterpret_cast<uint64_t>(d_stats),
+                                 th_bits, o.bucket_capacity, o.bucket_fill, o.train_steps, lr_bits, o.sample_log2,
+                                 o.seed, uint64_t(o.feature), uint64_t(o.use_network), uint64_t(o.force_fallback),
+                                 seg_tuning_generation()};
+    return cached_graph_launch(
+        key, P.bytes, [&](void* ws, hipStream_t cs, SegFork) { return learned_enqueue(keys, n, o, d_stats, ws, cs); },
+        s);
+  } catch (...) {
+    set_error("unexpected exception");
+    return MS_ERR_INTERNAL;
+  }
+}
+
+ms_status ms_learned_grad(const uint32_t* d_sample, uint32_t S, int feature, const float* d_theta, float* d_out,
+                          void* stream) {
+  if (!d_sample || !d_theta || !d_out || S == 0) {
+    set_error("NULL pointer or empty sample");
+    return MS_ERR_INVALID_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = nullptr;
+  ms_status st = step_scratch(s, sizeof(float) * 2 * LS_TRAIN_G * LS_PS, &w);
+  if (st != MS_OK) return st;
+  LsModel* md = reinterpret_cast<LsModel*>(w);
+  float* partial = reinterpret_cast<float*>(w + align_up(sizeof(LsModel), 256));
+  ls_setup_kernel<<<1, 64, 0, s>>>(md, feature == MS_FEATURE_LOG ? 1 : 0, 1, 0, 0);
+  ls_set_theta_kernel<<<1, 64, 0, s>>>(md, d_theta);
+  ls_train_kernel<<<LS_TRAIN_G, LS_TRAIN_WG, 0, s>>>(d_sample, S, md, partial, 0, 1, 0.f, nullptr, nullptr, nullptr);
+  ls_train_kernel<<<LS_TRAIN_G, LS_TRAIN_WG, 0, s>>>(d_sample, S, md, partial, 1, 1, 0.f, nullptr, d_out, nullptr);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MS_OK : hip_fail(e, "gradient launch");
+}
+
+ms_status ms_learned_train(const uint32_t* d_sample, uint32_t S, int feature, uint32_t steps, float learning_rate,
+                           const float* d_theta0, float* d_theta_out, float* d_loss_hist, void* stream) {
+  if (!d_sample || !d_theta_out || S == 0 || steps > 100000) {
+    set_error("NULL pointer, empty sample or too many steps");
+    return MS_ERR_INVALID_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = nullptr;
+  ms_status st = step_scratch(s, sizeof(float) * 2 * LS_TRAIN_G * LS_PS, &w);
+  if (st != MS_OK) return st;
+  LsModel* md = reinterpret_cast<LsModel*>(w);
+  float* partial = reinterpret_cast<float*>(w + align_up(sizeof(LsModel), 256));
+  ls_setup_kernel<<<1, 64, 0, s>>>(md, feature == MS_FEATURE_LOG ? 1 : 0, 1, 0, 0);
+  if (d_theta0) ls_set_theta_kernel<<<1, 64, 0, s>>>(md, d_theta0);
+  st = ls_train_enqueue(d_sample, S, md, partial, int(steps), learning_rate, d_loss_hist, d_theta0 == nullptr, s);
+  if (st != MS_OK) return st;
+  ls_get_theta_kernel<<<1, 64, 0, s>>>(md, int(steps) & 1, d_theta_out);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MS_OK : hip_fail(e, "training launch");
+}
+
+ms_status ms_learned_table(const float* d_theta, float* d_t, float* d_v, int* d_count, void* stream) {
+  if (!d_theta || !d_t || !d_v || !d_count) {
+    set_error("NULL pointer");
+    return MS_ERR_INVALID_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = nullptr;
+  ms_status st = step_scratch(s, 0, &w);
+  if (st != MS_OK) return st;
+  LsModel* md = reinterpret_cast<LsModel*>(w);
+  ls_setup_kernel<<<1, 64, 0, s>>>(md, 1, 1, 0, 0);
+  ls_set_theta_kernel<<<1, 64, 0, s>>>(md, d_theta);
+  ls_compile_kernel<<<1, 64, 0, s>>>(md, 0, nullptr);
+  ls_get_table_kernel<<<1, 64, 0, s>>>(md, d_t, d_v, d_count);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MS_OK : hip_fail(e, "table launch");
+}
+
+ms_status ms_learned_bucket_ids(const uint32_t* d_keys, size_t n, const float* d_theta, int feature, int use_network,
+                                uint32_t log2_buckets, uint32_t* d_out, void* stream) {
+  if (n == 0) return MS_OK;
+  if (!d_keys || !d_theta || !d_out || log2_buckets > 20) {
+    set_error("NULL pointer or more than 2^20 buckets");
+    return MS_ERR_INVALID_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = nullptr;
+  ms_status st = step_scratch(s, 0, &w);
+  if (st != MS_OK) return st;
+  LsModel* md = reinterpret_cast<LsModel*>(w);
+  const int cb = int(std::min<uint32_t>(log2_buckets, 10)), fb = int(log2_buckets) - cb;
+  ls_setup_kernel<<<1, 64, 0, s>>>(md, feature == MS_FEATURE_LOG ? 1 : 0, use_network ? 1 : 0, cb, fb);
+  ls_set_theta_kernel<<<1, 64, 0, s>>>(md, d_theta);
+  ls_compile_kernel<<<1, 64, 0, s>>>(md, 0, nullptr);
+  ls_bucket_ids_kernel<<<dim3(unsigned(ceil_div(n, 256))), 256, 0, s>>>(d_keys, n, md, d_out);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MS_OK : hip_fail(e, "bucket id launch");
+}
+
+}  // extern "C"

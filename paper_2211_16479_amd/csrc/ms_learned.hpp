@@ -1,0 +1,724 @@
+// Learned-bucket sort of uint32 keys: device kernels.
+//
+// The network is this library's small CDF model (the paper has none): a
+// two-layer ReLU MLP F(x) = b2 + sum_h w2_h relu(w1_h x + b1_h) of one input
+// feature x of the key, trained to map a key to its normalised rank.
+//
+// Pipeline (all on the device, no host readback):
+//   sample  : S keys at seeded positions, sorted by the plain merge sort;
+//   init    : closed-form start -- the piecewise-linear interpolant through
+//             H sample quantiles;
+//   train   : full-batch Adam on the sample's mean squared rank error, one
+//             launch per step; every workgroup re-derives the step's
+//             parameters from the previous launch's per-workgroup gradient
+//             partials, summed in a fixed order (deterministic, no grid-wide
+//             barrier);
+//   compile : the trained network as a piecewise-linear table with a
+//             running-max envelope, so that bucket ids are non-decreasing in
+//             the key exactly, FP32 rounding included;
+//   bucket  : b = floor(F(x) * B), B = 2^(coarse bits + fine bits);
+//   level 1 : coarse histogram (LDS), scan, scatter into coarse buckets
+//             through an LDS counting sort per chunk (coalesced runs);
+//   level 2 : fine histogram inside each coarse bucket, then per fine bucket
+//             either "kept" (at most `capacity` keys: placed contiguously
+//             for the LDS bucket sort) or "spilled" (to the spill array);
+//   check   : every kept bucket's minimum must be >= the maximum of all
+//             earlier kept buckets (the judge; it cannot fail for a
+//             non-decreasing bucket function, and forces the plain sort if
+//             it does);
+//   decide  : spilled > tau * n (or a failed check) -> the plain merge sort
+//             runs instead (device flag; every learned kernel then returns);
+//   sort    : kept buckets are sorted in LDS by the segmented small-class
+//             kernels; the spill is sorted by the plain merge sort; one
+//             merge-path pass merges the two (exact repair).
+#pragma once
+#include "ms_common.hpp"
+
+namespace ms {
+
+constexpr int LS_H = 16;             // hidden units
+constexpr int LS_P = 3 * LS_H + 1;   // parameters
+constexpr int LS_PS = LS_P + 1;      // parameters + squared-error sum
+constexpr int LS_TAB = 32;           // table capacity (>= LS_H + 2)
+constexpr int LS_TRAIN_G = 64;       // training workgroups
+constexpr int LS_TRAIN_WG = 256;     // training workgroup size
+constexpr int LS_WG = 512;           // histogram / scatter workgroup size
+constexpr int LS_CHK = 8192;         // keys per histogram / scatter chunk
+constexpr int LS_MAX_BINS = 1024;    // max coarse or fine bins per level
+constexpr float LS_BETA1 = 0.9f, LS_BETA2 = 0.999f, LS_EPS = 1e-8f;
+
+// Feature of a key (bit-identical to the CPU oracle's float32 computation).
+__device__ __forceinline__ float ls_feature(uint32_t k, int log_feature) {
+  if (log_feature) {
+    const float f = __fadd_rn(__uint2float_rn(k), 1.0f);
+    const int bits = __float_as_int(f) - 0x3F800000;
+    return __int2float_rn(bits) * 0x1p-28f;
+  }
+  return __uint2float_rn(k) * 0x1p-32f;
+}
+
+// Model / table / decision record in device memory.
+struct LsModel {
+  float theta[2][LS_P];  // double-buffered parameters (step parity)
+  float m[2][LS_P];      // Adam first moments
+  float v[2][LS_P];      // Adam second moments
+  float tab_t[LS_TAB];   // breakpoints (ascending; padded with +inf)
+  float tab_v[LS_TAB];   // non-decreasing values at the breakpoints
+  float tab_s[LS_TAB];   // slope of each segment (>= 0)
+  int tab_n;             // number of breakpoints
+  int use_table;         // 0: bucket = floor(x * B) (no network)
+  int log_feature;
+  int fine_bits, coarse_bits;
+  uint32_t nbins_c, nbins_f;
+  // decision
+  int do_learned, do_repair, fallback, misordered;
+  unsigned long long spilled, kept, max_bucket;
+  void* r_keys;          // key array the kept buckets live in (caller's or scratch)
+  uint64_t r_base;       // first kept position in r_keys
+  uint32_t total_chunks; // level-2 chunks
+  float loss0, loss_last;
+};
+
+// ------------------------------------------------------------ sampling
+__global__ __launch_bounds__(256) void ls_sample_kernel(const uint32_t* __restrict__ keys, uint64_t n, uint32_t S,
+                                                        uint64_t seed, uint32_t* __restrict__ out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S) return;
+  // splitmix64 of (seed, i), mapped to [0, n) by a 64x64 -> high-64 product
+  uint64_t z = seed * 0x9E3779B97F4A7C15ull + (uint64_t(i) + 1) * 0xD1B54A32D192ED03ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  out[i] = keys[__umul64hi(z, n)];
+}
+
+// ------------------------------------------------------------ start point
+// One thread: knots at sample positions q_i = floor(i (S-1) / H), i = 0..H,
+// values (q_i + 0.5) / S; of a run of equal knots only the last is kept;
+// unit h is relu(x - k_h) with output weight = slope change at k_h.
+__global__ void ls_init_kernel(const uint32_t* __restrict__ sample, uint32_t S, LsModel* md) {
+  if (threadIdx.x != 0) return;
+  double k[LS_H + 1], y[LS_H + 1];
+  int m = 0;
+  for (int i = 0; i <= LS_H; ++i) {
+    const uint32_t q = uint32_t((uint64_t(i) * (S - 1)) / LS_H);
+    const double kk = double(ls_feature(sample[q], md->log_feature));
+    const double yy = (double(q) + 0.5) / double(S);
+    if (m > 0 && k[m - 1] == kk) {
+      y[m - 1] = yy;  // keep the last of a run of equal knots
+    } else {
+      k[m] = kk;
+      y[m] = yy;
+      ++m;
+    }
+  }
+  float* th = md->theta[0];
+  double prev_slope = 0.0;
+  for (int h = 0; h < LS_H; ++h) {
+    th[h] = 1.0f;                                        // w1
+    th[LS_H + h] = float(-(h < m - 1 ? k[h] : k[m - 1]));  // b1
+    double w2 = 0.0;
+    if (h < m - 1) {
+      const double slope = (y[h + 1] - y[h]) / (k[h + 1] - k[h]);
+      w2 = slope - prev_slope;
+      prev_slope = slope;
+    }
+    th[2 * LS_H + h] = float(w2);
+  }
+  th[3 * LS_H] = float(y[0]);
+  for (int p = 0; p < LS_P; ++p) {
+    md->m[0][p] = 0.f;
+    md->v[0][p] = 0.f;
+  }
+}
+
+// ------------------------------------------------------------ training
+// Launch t (t = 0..T): parameters theta_t (for t > 0: one Adam step from
+// theta_{t-1} with the gradient summed from partial[(t-1)&1]); workgroup 0
+// stores theta_t; for t < T every workgroup then writes its gradient partial
+// (and squared-error sum) at theta_t to partial[t&1][blockIdx.x].
+// grad_out / loss_out (optional): the summed gradient + squared-error sum of
+// the previous launch.
+__global__ __launch_bounds__(LS_TRAIN_WG) void ls_train_kernel(const uint32_t* __restrict__ sample, uint32_t S,
+                                                                LsModel* md, float* __restrict__ partial, int t,
+                                                                int T, float lr, float* __restrict__ loss_hist,
+                                                                float* __restrict__ grad_out, const int* gate) {
+  if (gate && *gate == 0) return;
+  constexpr int ROW = LS_PS + 1;  // padded row of the transposed reduction
+  __shared__ float th[LS_P];
+  __shared__ float red[LS_TRAIN_WG * ROW > LS_TRAIN_G * LS_PS ? LS_TRAIN_WG * ROW : LS_TRAIN_G * LS_PS];
+  __shared__ float quart[4][LS_PS];
+  __shared__ float gsum[LS_PS];
+  const int tid = threadIdx.x;
+  const int G = gridDim.x;
+  if (t == 0) {
+    if (tid < LS_P) th[tid] = md->theta[0][tid];
+    __syncthreads();
+  } else {
+    // previous launch's partials, summed over workgroups in fixed order
+    const float* pp = partial + size_t((t - 1) & 1) * G * LS_PS;
+    for (int i = tid; i < G * LS_PS; i += LS_TRAIN_WG) red[i] = pp[i];
+    __syncthreads();
+    if (tid < LS_PS) {
+      float acc = 0.f;
+      for (int g = 0; g < G; ++g) acc += red[g * LS_PS + tid];
+      gsum[tid] = acc;
+    }
+    __syncthreads();
+    if (tid < LS_P) {
+      const int pb = (t - 1) & 1, nb = t & 1;
+      const float gr = gsum[tid];
+      const float m1 = LS_BETA1 * md->m[pb][tid] + (1.f - LS_BETA1) * gr;
+      const float v1 = LS_BETA2 * md->v[pb][tid] + (1.f - LS_BETA2) * gr * gr;
+      const float mh = m1 / (1.f - powf(LS_BETA1, float(t)));
+      const float vh = v1 / (1.f - powf(LS_BETA2, float(t)));
+      const float nt = md->theta[pb][tid] - lr * mh / (sqrtf(vh) + LS_EPS);
+      th[tid] = nt;
+      if (blockIdx.x == 0) {
+        md->theta[nb][tid] = nt;
+        md->m[nb][tid] = m1;
+        md->v[nb][tid] = v1;
+      }
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+      const float l = gsum[LS_P] / float(S);
+      if (loss_hist) loss_hist[t - 1] = l;
+      if (t == 1) md->loss0 = l;
+      md->loss_last = l;
+    }
+    if (blockIdx.x == 0 && grad_out && tid < LS_PS) grad_out[tid] = gsum[tid];
+    __syncthreads();
+  }
+  if (t >= T) return;
+  // gradient of the mean squared error at th over this workgroup's samples
+  float acc[LS_PS];
+#pragma unroll
+  for (int p = 0; p < LS_PS; ++p) acc[p] = 0.f;
+  const float inv2 = 2.f / float(S);
+  for (uint32_t i = blockIdx.x * LS_TRAIN_WG + tid; i < S; i += G * LS_TRAIN_WG) {
+    const float x = ls_feature(sample[i], md->log_feature);
+    const float y = (float(i) + 0.5f) / float(S);
+    float z[LS_H];
+    float F = th[3 * LS_H];
+#pragma unroll
+    for (int h = 0; h < LS_H; ++h) {
+      z[h] = fmaf(th[h], x, th[LS_H + h]);
+      F = fmaf(th[2 * LS_H + h], fmaxf(z[h], 0.f), F);
+    }
+    const float e = F - y;
+    const float r = e * inv2;
+#pragma unroll
+    for (int h = 0; h < LS_H; ++h) {
+      const float a = fmaxf(z[h], 0.f);
+      const float gz = z[h] > 0.f ? r * th[2 * LS_H + h] : 0.f;
+      acc[h] = fmaf(gz, x, acc[h]);           // w1
+      acc[LS_H + h] += gz;                   // b1
+      acc[2 * LS_H + h] = fmaf(r, a, acc[2 * LS_H + h]);  // w2
+    }
+    acc[3 * LS_H] += r;        // b2
+    acc[LS_P] = fmaf(e, e, acc[LS_P]);
+  }
+  // workgroup sum in a fixed order: every thread's row into LDS, then for
+  // each parameter 4 quarter sums over 64 rows each, then the 4 quarters
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < LS_PS; ++p) red[tid * ROW + p] = acc[p];
+  __syncthreads();
+  if (tid < 4 * LS_PS) {
+    const int p = tid % LS_PS, q = tid / LS_PS;
+    float s = 0.f;
+#pragma unroll 8
+    for (int j = 0; j < LS_TRAIN_WG / 4; ++j) s += red[(q * (LS_TRAIN_WG / 4) + j) * ROW + p];
+    quart[q][p] = s;
+  }
+  __syncthreads();
+  if (tid < LS_PS)
+    partial[size_t(t & 1) * G * LS_PS + size_t(blockIdx.x) * LS_PS + tid] =
+        ((quart[0][tid] + quart[1][tid]) + quart[2][tid]) + quart[3][tid];
+}
+
+// ------------------------------------------------------------ compile
+// One thread: the trained network's breakpoints inside (0, 1), plus 0 and 1,
+// sorted; F there in double; running maximum; FP32 table with slopes.
+__global__ void ls_compile_kernel(LsModel* md, int final_parity, const int* gate) {
+  if (gate && *gate == 0) return;
+  if (threadIdx.x != 0) return;
+  const float* th = md->theta[final_parity];
+  double t[LS_H + 2];
+  int nt = 0;
+  t[nt++] = 0.0;
+  t[nt++] = 1.0;
+  for (int h = 0; h < LS_H; ++h) {
+    const double w1 = th[h], b1 = th[LS_H + h];
+    if (w1 != 0.0) {
+      const double bp = -b1 / w1;
+      if (bp > 0.0 && bp < 1.0) t[nt++] = bp;
+    }
+  }
+  for (int i = 1; i < nt; ++i) {  // insertion sort
+    const double x = t[i];
+    int j = i - 1;
+    while (j >= 0 && t[j] > x) { t[j + 1] = t[j]; --j; }
+    t[j + 1] = x;
+  }
+  int u = 0;  // unique, and representable as distinct floats
+  for (int i = 0; i < nt; ++i)
+    if (u == 0 || float(t[i]) > float(t[u - 1])) t[u++] = t[i];
+  nt = u;
+  double V[LS_H + 2];
+  double run = -1e300;
+  for (int i = 0; i < nt; ++i) {
+    double F = th[3 * LS_H];
+    for (int h = 0; h < LS_H; ++h) {
+      const double z = double(th[h]) * t[i] + double(th[LS_H + h]);
+      if (z > 0.0) F += double(th[2 * LS_H + h]) * z;
+    }
+    run = F > run ? F : run;
+    V[i] = run;
+  }
+  for (int i = 0; i < LS_TAB; ++i) {
+    if (i < nt) {
+      md->tab_t[i] = float(t[i]);
+      md->tab_v[i] = float(V[i]);
+      const float dv = i + 1 < nt ? float(V[i + 1]) - float(V[i]) : 0.f;
+      const float dt = i + 1 < nt ? float(t[i + 1]) - float(t[i]) : 0.f;
+      md->tab_s[i] = (i + 1 < nt && dt > 0.f && dv > 0.f) ? dv / dt : 0.f;
+    } else {
+      md->tab_t[i] = __int_as_float(0x7f800000);  // +inf
+      md->tab_v[i] = md->tab_v[nt - 1];
+      md->tab_s[i] = 0.f;
+    }
+  }
+  md->tab_n = nt;
+}
+
+// Table in LDS for the per-key bucket function.
+struct LsTable {
+  float t[LS_TAB], v[LS_TAB], s[LS_TAB];
+  int n, use_table, log_feature, fine_bits;
+  float B;
+  uint32_t nb;  // total buckets
+};
+
+__device__ __forceinline__ void ls_load_table(const LsModel* md, LsTable* tb) {
+  const int tid = threadIdx.x;
+  if (tid < LS_TAB) {
+    tb->t[tid] = md->tab_t[tid];
+    tb->v[tid] = md->tab_v[tid];
+    tb->s[tid] = md->tab_s[tid];
+  }
+  if (tid == 0) {
+    tb->n = md->tab_n;
+    tb->use_table = md->use_table;
+    tb->log_feature = md->log_feature;
+    tb->fine_bits = md->fine_bits;
+    tb->nb = md->nbins_c << md->fine_bits;
+    tb->B = float(tb->nb);
+  }
+}
+
+// Bucket id of a key: non-decreasing in the key.
+__device__ __forceinline__ uint32_t ls_bucket(const LsTable* tb, uint32_t key) {
+  const float x = ls_feature(key, tb->log_feature);
+  float u;
+  if (tb->use_table) {
+    int j = 0;  // largest j with t[j] <= x (t[0] = 0 <= x), then clamp to n-2
+#pragma unroll
+    for (int step = LS_TAB / 2; step >= 1; step >>= 1)
+      if (tb->t[j + step] <= x) j += step;
+    j = j < tb->n - 2 ? j : tb->n - 2;
+    u = fminf(__fmaf_rn(tb->s[j], __fsub_rn(x, tb->t[j]), tb->v[j]), tb->v[j + 1]);
+  } else {
+    u = x;
+  }
+  const float f = __fmul_rn(fmaxf(u, 0.f), tb->B);
+  const uint32_t b = f >= tb->B ? tb->nb - 1 : uint32_t(f);
+  return b < tb->nb ? b : tb->nb - 1;
+}
+
+// ------------------------------------------------------------ scatter
+// Bin arrays and decisions of one learned sort (device scratch).
+struct LsBins {
+  uint32_t* cnt_c;        // [Bc] keys per coarse bucket
+  uint32_t* off_c;        // [Bc + 1] exclusive scan of cnt_c
+  uint32_t* cursor_c;     // [Bc] coarse scatter cursors
+  uint32_t* chunk_start;  // [Bc + 1] first level-2 chunk of each coarse bucket
+  uint32_t* cnt_f;        // [B] keys per fine bucket
+  uint32_t* fmin;         // [B] smallest key per fine bucket
+  uint32_t* fmax;         // [B] largest key per fine bucket
+  uint32_t* cursor_f;     // [B] fine scatter cursors
+  int64_t* seg_off;       // [B + 1] kept-bucket segments for the bucket sort
+  uint32_t* kept_tot;     // [Bc] per coarse bucket: kept keys
+  uint32_t* spill_tot;    // [Bc] spilled keys
+  uint32_t* cmin;         // [Bc] smallest kept key
+  uint32_t* cmax;         // [Bc] largest kept key
+  uint32_t* cbad;         // [Bc] 1 if kept buckets are out of order inside
+  uint32_t* cmaxb;        // [Bc] largest fine bucket
+  uint32_t* kept_base;    // [Bc] first kept position of the coarse bucket
+  uint32_t* spill_base;   // [Bc] first spill position of the coarse bucket
+};
+
+// Exclusive scan of cnt[0, nb) (nb <= 2 * LS_WG) into off[0, nb); *total
+// gets the sum.  Whole workgroup; ends with a barrier.
+__device__ __forceinline__ void ls_block_scan(const uint32_t* cnt, uint32_t* off, uint32_t nb, uint32_t* tmp,
+                                              uint32_t* total) {
+  const int tid = threadIdx.x;
+  const uint32_t i0 = 2u * tid, i1 = i0 + 1;
+  const uint32_t a = i0 < nb ? cnt[i0] : 0u, b = i1 < nb ? cnt[i1] : 0u;
+  const uint32_t s = a + b;
+  tmp[tid] = s;
+  __syncthreads();
+  for (int d = 1; d < LS_WG; d <<= 1) {
+    const uint32_t v = tid >= d ? tmp[tid - d] : 0u;
+    __syncthreads();
+    tmp[tid] += v;
+    __syncthreads();
+  }
+  const uint32_t ex = tmp[tid] - s;
+  if (i0 < nb) off[i0] = ex;
+  if (i1 < nb) off[i1] = ex + a;
+  if (tid == LS_WG - 1) *total = tmp[tid];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void ls_clear_kernel(LsBins bn, uint32_t nb_c, uint32_t nb) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb) {
+    bn.cnt_f[i] = 0;
+    bn.fmin[i] = 0xFFFFFFFFu;
+    bn.fmax[i] = 0;
+  }
+  if (i < nb_c) bn.cnt_c[i] = 0;
+}
+
+// Level 1: coarse histogram of one chunk per workgroup.
+__global__ __launch_bounds__(LS_WG) void ls_hist1_kernel(const uint32_t* __restrict__ keys, uint64_t n,
+                                                         const LsModel* md, LsBins bn) {
+  __shared__ LsTable tb;
+  __shared__ uint32_t h[LS_MAX_BINS];
+  ls_load_table(md, &tb);
+  const uint32_t nbc = md->nbins_c;
+  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) h[i] = 0;
+  __syncthreads();
+  const uint64_t base = uint64_t(blockIdx.x) * LS_CHK;
+  uint32_t kv[LS_CHK / LS_WG];
+#pragma unroll
+  for (int r = 0; r < LS_CHK / LS_WG; ++r) {
+    const uint64_t e = base + threadIdx.x + uint64_t(r) * LS_WG;
+    kv[r] = e < n ? keys[e] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < LS_CHK / LS_WG; ++r) {
+    const uint64_t e = base + threadIdx.x + uint64_t(r) * LS_WG;
+    if (e < n) atomicAdd(&h[ls_bucket(&tb, kv[r]) >> tb.fine_bits], 1u);
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG)
+    if (h[i]) atomicAdd(&bn.cnt_c[i], h[i]);
+}
+
+// Level 1 plan (one workgroup): coarse offsets, cursors, level-2 chunk map.
+__global__ __launch_bounds__(LS_WG) void ls_plan1_kernel(LsModel* md, LsBins bn) {
+  __shared__ uint32_t cnt[LS_MAX_BINS], off[LS_MAX_BINS], ch[LS_MAX_BINS], choff[LS_MAX_BINS], tmp[LS_WG];
+  __shared__ uint32_t total, tch;
+  const uint32_t nbc = md->nbins_c;
+  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) {
+    cnt[i] = bn.cnt_c[i];
+    ch[i] = (cnt[i] + LS_CHK - 1) / LS_CHK;
+  }
+  __syncthreads();
+  ls_block_scan(cnt, off, nbc, tmp, &total);
+  ls_block_scan(ch, choff, nbc, tmp, &tch);
+  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) {
+    bn.off_c[i] = off[i];
+    bn.cursor_c[i] = off[i];
+    bn.chunk_start[i] = choff[i];
+  }
+  if (threadIdx.x == 0) {
+    bn.off_c[nbc] = total;
+    bn.chunk_start[nbc] = tch;
+    md->total_chunks = tch;
+  }
+}
+
+// Shared body of the two scatters: counting sort of one chunk by bin in LDS,
+// one reservation per non-empty bin, then coalesced runs to the destination.
+struct LsScatterLds {
+  uint32_t cnt[LS_MAX_BINS], off[LS_MAX_BINS], gb[LS_MAX_BINS], tmp[LS_WG];
+  uint32_t stage[LS_CHK];
+  uint16_t sbin[LS_CHK];
+  uint32_t total;
+};
+
+// Level 1 scatter: chunk blockIdx.x of the input into coarse buckets.
+__global__ __launch_bounds__(LS_WG) void ls_scatter1_kernel(const uint32_t* __restrict__ keys, uint64_t n,
+                                                            const LsModel* md, LsBins bn, uint32_t* __restrict__ out) {
+  __shared__ LsTable tb;
+  __shared__ LsScatterLds L;
+  ls_load_table(md, &tb);
+  const uint32_t nbc = md->nbins_c;
+  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) L.cnt[i] = 0;
+  __syncthreads();
+  constexpr int R = LS_CHK / LS_WG;
+  const uint64_t base = uint64_t(blockIdx.x) * LS_CHK;
+  uint32_t kv[R], bin[R], rk[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint64_t e = base + threadIdx.x + uint64_t(r) * LS_WG;
+    kv[r] = e < n ? keys[e] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint64_t e = base + threadIdx.x + uint64_t(r) * LS_WG;
+    if (e < n) {
+      bin[r] = ls_bucket(&tb, kv[r]) >> tb.fine_bits;
+      rk[r] = atomicAdd(&L.cnt[bin[r]], 1u);
+    }
+  }
+  __syncthreads();
+  ls_block_scan(L.cnt, L.off, nbc, L.tmp, &L.total);
+  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG)
+    if (L.cnt[i]) L.gb[i] = atomicAdd(&bn.cursor_c[i], L.cnt[i]);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint64_t e = base + threadIdx.x + uint64_t(r) * LS_WG;
+    if (e < n) {
+      const uint32_t p = L.off[bin[r]] + rk[r];
+      L.stage[p] = kv[r];
+      L.sbin[p] = uint16_t(bin[r]);
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < L.total; i += LS_WG) {
+    const uint32_t b = L.sbin[i];
+    out[L.gb[b] + (i - L.off[b])] = L.stage[i];
+  }
+}
+
+// Level-2 chunk w -> coarse bucket c and key range [lo, hi).
+__device__ __forceinline__ bool ls_chunk(const LsModel* md, const LsBins& bn, uint32_t w, uint32_t* c,
+                                         uint32_t* lo, uint32_t* hi) {
+  if (w >= md->total_chunks) return false;
+  uint32_t a = 0, b = md->nbins_c;  // largest c with chunk_start[c] <= w
+  while (b - a > 1) {
+    const uint32_t m = (a + b) >> 1;
+    if (bn.chunk_start[m] <= w) a = m; else b = m;
+  }
+  *c = a;
+  const uint32_t j = w - bn.chunk_start[a];
+  const uint32_t s = bn.off_c[a] + j * LS_CHK, e = bn.off_c[a + 1];
+  *lo = s;
+  *hi = s + LS_CHK < e ? s + LS_CHK : e;
+  return true;
+}
+
+// Level 2 histogram with per-fine-bucket min / max (for the order check).
+__global__ __launch_bounds__(LS_WG) void ls_hist2_kernel(const uint32_t* __restrict__ keys, const LsModel* md,
+                                                         LsBins bn) {
+  __shared__ LsTable tb;
+  __shared__ uint32_t h[LS_MAX_BINS], mn[LS_MAX_BINS], mx[LS_MAX_BINS];
+  uint32_t c, lo, hi;
+  if (!ls_chunk(md, bn, blockIdx.x, &c, &lo, &hi)) return;
+  ls_load_table(md, &tb);
+  const uint32_t nbf = md->nbins_f;
+  for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG) {
+    h[i] = 0;
+    mn[i] = 0xFFFFFFFFu;
+    mx[i] = 0;
+  }
+  __syncthreads();
+  constexpr int R = LS_CHK / LS_WG;
+  uint32_t kv[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t e = lo + threadIdx.x + uint32_t(r) * LS_WG;
+    kv[r] = e < hi ? keys[e] : 0u;
+  }
+  const uint32_t fmask = nbf - 1;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t e = lo + threadIdx.x + uint32_t(r) * LS_WG;
+    if (e < hi) {
+      const uint32_t f = ls_bucket(&tb, kv[r]) & fmask;
+      atomicAdd(&h[f], 1u);
+      atomicMin(&mn[f], kv[r]);
+      atomicMax(&mx[f], kv[r]);
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG)
+    if (h[i]) {
+      const uint32_t b = (c << tb.fine_bits) | i;
+      atomicAdd(&bn.cnt_f[b], h[i]);
+      atomicMin(&bn.fmin[b], mn[i]);
+      atomicMax(&bn.fmax[b], mx[i]);
+    }
+}
+
+// Per coarse bucket (one workgroup each): kept / spilled totals, largest
+// bucket, and the order of its kept buckets.
+__global__ __launch_bounds__(LS_WG) void ls_totals_kernel(const LsModel* md, LsBins bn, uint32_t capacity) {
+  __shared__ uint32_t cnt[LS_MAX_BINS], mn[LS_MAX_BINS], mx[LS_MAX_BINS];
+  const uint32_t c = blockIdx.x;
+  const uint32_t nbf = md->nbins_f;
+  const uint32_t b0 = c << md->fine_bits;
+  for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG) {
+    cnt[i] = bn.cnt_f[b0 + i];
+    mn[i] = bn.fmin[b0 + i];
+    mx[i] = bn.fmax[b0 + i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t kept = 0, spill = 0, maxb = 0, bad = 0, first = 0xFFFFFFFFu, run = 0;
+    bool any = false;
+    for (uint32_t i = 0; i < nbf; ++i) {
+      const uint32_t k = cnt[i];
+      maxb = k > maxb ? k : maxb;
+      if (k == 0) continue;
+      if (k > capacity) {
+        spill += k;
+        continue;
+      }
+      kept += k;
+      if (!any) first = mn[i];
+      else if (mn[i] < run) bad = 1;
+      run = any ? (mx[i] > run ? mx[i] : run) : mx[i];
+      any = true;
+    }
+    bn.kept_tot[c] = kept;
+    bn.spill_tot[c] = spill;
+    bn.cmaxb[c] = maxb;
+    bn.cbad[c] = bad;
+    bn.cmin[c] = any ? first : 0xFFFFFFFFu;
+    bn.cmax[c] = any ? run : 0u;
+  }
+}
+
+// Decision (one workgroup): kept / spill bases, the order check across coarse
+// buckets, fallback and repair flags, where the kept buckets live.
+__global__ __launch_bounds__(LS_WG) void ls_plan2_kernel(LsModel* md, LsBins bn, uint64_t n, uint64_t spill_limit,
+                                                         int force_fallback, uint32_t* d_keys, uint32_t* xr) {
+  __shared__ uint32_t k[LS_MAX_BINS], sp[LS_MAX_BINS], kb[LS_MAX_BINS], sb[LS_MAX_BINS], tmp[LS_WG];
+  __shared__ uint32_t ktot, stot;
+  const uint32_t nbc = md->nbins_c;
+  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) {
+    k[i] = bn.kept_tot[i];
+    sp[i] = bn.spill_tot[i];
+  }
+  __syncthreads();
+  ls_block_scan(k, kb, nbc, tmp, &ktot);
+  ls_block_scan(sp, sb, nbc, tmp, &stot);
+  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) {
+    bn.kept_base[i] = kb[i];
+    bn.spill_base[i] = sb[i];
+  }
+  if (threadIdx.x == 0) {
+    uint32_t bad = 0, run = 0, maxb = 0;
+    bool any = false;
+    for (uint32_t c = 0; c < nbc; ++c) {
+      bad |= bn.cbad[c];
+      maxb = bn.cmaxb[c] > maxb ? bn.cmaxb[c] : maxb;
+      if (k[c] == 0) continue;
+      if (any && bn.cmin[c] < run) bad = 1;
+      run = any ? (bn.cmax[c] > run ? bn.cmax[c] : run) : bn.cmax[c];
+      any = true;
+    }
+    const uint64_t s = stot;
+    const int fb = (force_fallback || bad || s > spill_limit || uint64_t(ktot) + s != n) ? 1 : 0;
+    md->misordered = bad ? 1 : 0;
+    md->fallback = fb;
+    md->do_learned = fb ? 0 : 1;
+    md->do_repair = (!fb && s > 0) ? 1 : 0;
+    md->spilled = s;
+    md->kept = ktot;
+    md->max_bucket = maxb;
+    md->r_keys = (s == 0) ? static_cast<void*>(d_keys) : static_cast<void*>(xr);
+    md->r_base = (s == 0) ? 0 : s;
+  }
+}
+
+// Fine offsets (one workgroup per coarse bucket): scatter cursors and the
+// kept-bucket segments of the bucket sort (all empty on fallback).
+__global__ __launch_bounds__(LS_WG) void ls_offsets_kernel(const LsModel* md, LsBins bn, uint32_t capacity) {
+  __shared__ uint32_t kc[LS_MAX_BINS], sc[LS_MAX_BINS], ko[LS_MAX_BINS], so[LS_MAX_BINS], tmp[LS_WG];
+  __shared__ uint32_t kt, st;
+  const uint32_t c = blockIdx.x;
+  const uint32_t nbf = md->nbins_f;
+  const uint32_t b0 = c << md->fine_bits;
+  for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG) {
+    const uint32_t k = bn.cnt_f[b0 + i];
+    kc[i] = k <= capacity ? k : 0u;
+    sc[i] = k > capacity ? k : 0u;
+  }
+  __syncthreads();
+  ls_block_scan(kc, ko, nbf, tmp, &kt);
+  ls_block_scan(sc, so, nbf, tmp, &st);
+  const bool on = md->do_learned != 0;
+  const uint64_t rb = md->r_base;
+  const uint32_t kbase = bn.kept_base[c], sbase = bn.spill_base[c];
+  for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG) {
+    const uint32_t kpos = uint32_t(rb) + kbase + ko[i];
+    bn.cursor_f[b0 + i] = sc[i] ? sbase + so[i] : kpos;
+    bn.seg_off[b0 + i] = on ? int64_t(kpos) : 0;
+  }
+  if (c == md->nbins_c - 1 && threadIdx.x == 0)
+    bn.seg_off[(uint64_t(c) << md->fine_bits) + nbf] = on ? int64_t(rb + md->kept) : 0;
+}
+
+// Level 2 scatter: keys of a coarse chunk into their fine buckets, kept
+// buckets into the kept array, spilled ones into the spill area.
+__global__ __launch_bounds__(LS_WG) void ls_scatter2_kernel(const uint32_t* __restrict__ keys, const LsModel* md,
+                                                            LsBins bn, uint32_t capacity, uint32_t* xr) {
+  __shared__ LsTable tb;
+  __shared__ LsScatterLds L;
+  __shared__ uint8_t kept[LS_MAX_BINS];
+  if (md->do_learned == 0) return;
+  uint32_t c, lo, hi;
+  if (!ls_chunk(md, bn, blockIdx.x, &c, &lo, &hi)) return;
+  ls_load_table(md, &tb);
+  const uint32_t nbf = md->nbins_f;
+  const uint32_t b0 = c << md->fine_bits;
+  for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG) L.cnt[i] = 0;
+  __syncthreads();
+  constexpr int R = LS_CHK / LS_WG;
+  const uint32_t fmask = nbf - 1;
+  uint32_t kv[R], bin[R], rk[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t e = lo + threadIdx.x + uint32_t(r) * LS_WG;
+    kv[r] = e < hi ? keys[e] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t e = lo + threadIdx.x + uint32_t(r) * LS_WG;
+    if (e < hi) {
+      bin[r] = ls_bucket(&tb, kv[r]) & fmask;
+      rk[r] = atomicAdd(&L.cnt[bin[r]], 1u);
+    }
+  }
+  __syncthreads();
+  ls_block_scan(L.cnt, L.off, nbf, L.tmp, &L.total);
+  for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG)
+    if (L.cnt[i]) {
+      L.gb[i] = atomicAdd(&bn.cursor_f[b0 + i], L.cnt[i]);
+      kept[i] = bn.cnt_f[b0 + i] <= capacity ? 1 : 0;
+    }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t e = lo + threadIdx.x + uint32_t(r) * LS_WG;
+    if (e < hi) {
+      const uint32_t p = L.off[bin[r]] + rk[r];
+      L.stage[p] = kv[r];
+      L.sbin[p] = uint16_t(bin[r]);
+    }
+  }
+  __syncthreads();
+  uint32_t* rk_arr = static_cast<uint32_t*>(md->r_keys);
+  for (uint32_t i = threadIdx.x; i < L.total; i += LS_WG) {
+    const uint32_t b = L.sbin[i];
+    uint32_t* dst = kept[b] ? rk_arr : xr;
+    dst[L.gb[b] + (i - L.off[b])] = L.stage[i];
+  }
+}
+
+}  // namespace ms

@@ -34,6 +34,16 @@ __device__ __forceinline__ PassGeom pass_geom(uint64_t g, uint64_t n, uint64_t W
   return q;
 }
 
+// Pass geometry under a DevCtl: a device-side split point means a single
+// merge of [0, split) with [split, n).
+__device__ __forceinline__ PassGeom pass_geom(uint64_t g, uint64_t n, uint64_t W, const DevCtl& c) {
+  if (c.split_dev) {
+    const uint64_t sp = *c.split_dev;
+    return PassGeom{0, sp < n ? sp : n, n};
+  }
+  return pass_geom(g, n, W);
+}
+
 // Number of outputs among the first d of merge(A, B) that come from A.
 template <class K>
 __device__ __forceinline__ uint64_t merge_path_split(const K* A, uint64_t la, const K* B, uint64_t lb,
@@ -62,12 +72,13 @@ __global__ __launch_bounds__(256) void partition_kernel(const K* __restrict__ sr
   const uint64_t gid = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const uint64_t k = gid / G;
   if constexpr (G == 1) {
-    if (k >= num_tiles) return;
-    const uint64_t g = k * Tm;
-    if (g >= n) return;
-    const PassGeom q = pass_geom(g, n, W);
-    const uint64_t i = merge_path_split(src + q.pb, q.a_end - q.pb, src + q.a_end, q.b_end - q.a_end, g - q.pb);
-    part[k] = int64_t(q.pb + i);
+    for (uint64_t kk = gid; kk < num_tiles; kk += uint64_t(gridDim.x) * blockDim.x) {
+      const uint64_t g = kk * Tm;
+      if (g >= n) return;
+      const PassGeom q = pass_geom(g, n, W, ctl);
+      const uint64_t i = merge_path_split(src + q.pb, q.a_end - q.pb, src + q.a_end, q.b_end - q.a_end, g - q.pb);
+      part[kk] = int64_t(q.pb + i);
+    }
   } else {
     const uint32_t q = uint32_t(gid % G);
     const uint32_t gshift = (__lane_id() / G) * G;
@@ -77,7 +88,7 @@ __global__ __launch_bounds__(256) void partition_kernel(const K* __restrict__ sr
     const K* B = src;
     PassGeom geo{0, 0, 0};
     if (valid) {
-      geo = pass_geom(k * Tm, n, W);
+      geo = pass_geom(k * Tm, n, W, ctl);
       const uint64_t la = geo.a_end - geo.pb, lb = geo.b_end - geo.a_end;
       d = k * Tm - geo.pb;
       A = src + geo.pb;
@@ -231,25 +242,28 @@ __global__ __launch_bounds__(WG) void merge_kernel(const K* __restrict__ src_k, 
   extern __shared__ __align__(16) unsigned char smem[];
   if (gated_off(ctl)) return;
   const uint64_t n = live_n(ctl, n_host);
-  const uint64_t k = blockIdx.x;
-  const uint64_t g0 = k * MT::TM;
-  if (g0 >= n) return;
-  const uint64_t g1 = g0 + MT::TM < n ? g0 + MT::TM : n;
-  const PassGeom q = pass_geom(g0, n, W);
-  const uint64_t i0 = uint64_t(part[k]);
-  const uint64_t j0 = q.a_end + (g0 - q.pb) - (i0 - q.pb);
-  uint64_t i1, j1;
-  if (g1 == q.b_end) {
-    i1 = q.a_end;
-    j1 = q.b_end;
-  } else {
-    i1 = uint64_t(part[k + 1]);
-    j1 = q.a_end + (g1 - q.pb) - (i1 - q.pb);
-  }
-  if constexpr (MT::PAIRS) {
-    MT::run(src_k, src_v, dst_k, dst_v, i0, uint32_t(i1 - i0), j0, uint32_t(j1 - j0), g0, smem);
-  } else {
-    MT::template run<int>(src_k, nullptr, dst_k, nullptr, i0, uint32_t(i1 - i0), j0, uint32_t(j1 - j0), g0, smem);
+  // workgroup b merges tiles b, b + grid, ... (one each when the grid covers them)
+  for (uint64_t k = blockIdx.x; k * MT::TM < n; k += gridDim.x) {
+    const uint64_t g0 = k * MT::TM;
+    const uint64_t g1 = g0 + MT::TM < n ? g0 + MT::TM : n;
+    const PassGeom q = pass_geom(g0, n, W, ctl);
+    const uint64_t i0 = uint64_t(part[k]);
+    const uint64_t j0 = q.a_end + (g0 - q.pb) - (i0 - q.pb);
+    uint64_t i1, j1;
+    if (g1 == q.b_end) {
+      i1 = q.a_end;
+      j1 = q.b_end;
+    } else {
+      i1 = uint64_t(part[k + 1]);
+      j1 = q.a_end + (g1 - q.pb) - (i1 - q.pb);
+    }
+    if constexpr (MT::PAIRS) {
+      MT::run(src_k, src_v, dst_k, dst_v, i0, uint32_t(i1 - i0), j0, uint32_t(j1 - j0), g0, smem);
+    } else {
+      MT::template run<int>(src_k, nullptr, dst_k, nullptr, i0, uint32_t(i1 - i0), j0, uint32_t(j1 - j0), g0,
+                            smem);
+    }
+    __syncthreads();
   }
 }
 

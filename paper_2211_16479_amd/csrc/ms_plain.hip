@@ -1,5 +1,6 @@
 // Plain merge sort launcher: tile sort, then merge-path passes with
 // ping-pong buffers (see ms_plan.hpp for the pass count and parity).
+#include <algorithm>
 #include <type_traits>
 
 #include "ms_block_sort.hpp"
@@ -33,7 +34,7 @@ size_t plain_temp_bytes(uint64_t n) {
 }
 
 template <class K, class V>
-ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, void* ws) {
+ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, void* ws, uint64_t max_grid) {
   using C = PlainCfg<K, V>;
   using BS = TileSort<K, V, C::BS_WG, C::BS_IPT, C::BS_PAD>;
   using MT = MergeTile<K, V, C::MG_WG, C::MG_IPT, C::MG_PAD>;
@@ -55,10 +56,12 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
     return a != hipSuccess ? a : b;
   }();
   if (lds_ok != hipSuccess) return hip_fail(lds_ok, "LDS size attribute");
+  const uint64_t cap = max_grid ? max_grid : ~uint64_t(0);
   {
     ProfScope ps(PK_BLOCK_SORT, s);
     block_sort_kernel<K, V, C::BS_WG, C::BS_IPT, C::BS_PAD>
-        <<<dim3(unsigned(tiles)), dim3(C::BS_WG), BS::LDS_BYTES, s>>>(keys, vals, cur_k, cur_v, n, ctl);
+        <<<dim3(unsigned(std::min(tiles, cap))), dim3(C::BS_WG), BS::LDS_BYTES, s>>>(keys, vals, cur_k, cur_v, n,
+                                                                                     ctl);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "tile sort launch");
@@ -69,13 +72,14 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
     V* nxt_v = (cur_k == keys) ? tv : vals;
     {
       ProfScope ps(PK_PARTITION, s);
-      partition_kernel<K, MS_PART_G><<<dim3(unsigned(ceil_div(mtiles * MS_PART_G, 256))), dim3(256), 0, s>>>(
-          cur_k, n, ctl, W, C::MTILE, mtiles, part);
+      partition_kernel<K, MS_PART_G><<<dim3(unsigned(std::min(ceil_div(mtiles * MS_PART_G, 256), cap))), dim3(256), 0,
+                                       s>>>(cur_k, n, ctl, W, C::MTILE, mtiles, part);
     }
     {
       ProfScope ps(PK_MERGE, s);
       merge_kernel<K, V, C::MG_WG, C::MG_IPT, C::MG_PAD>
-          <<<dim3(unsigned(mtiles)), dim3(C::MG_WG), MT::LDS_BYTES, s>>>(cur_k, cur_v, nxt_k, nxt_v, n, ctl, W, part);
+          <<<dim3(unsigned(std::min(mtiles, cap))), dim3(C::MG_WG), MT::LDS_BYTES, s>>>(cur_k, cur_v, nxt_k, nxt_v, n,
+                                                                                     ctl, W, part);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "merge pass launch");
@@ -85,8 +89,28 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
   return MS_OK;
 }
 
+template <class K, class V>
+ms_status merge_two_runs(const K* src, K* dst, uint64_t n, DevCtl ctl, int64_t* part, hipStream_t s,
+                         uint64_t max_grid) {
+  using C = PlainCfg<K, V>;
+  using MT = MergeTile<K, V, C::MG_WG, C::MG_IPT, C::MG_PAD>;
+  static_assert(!C::PAIRS, "keys only");
+  if (n == 0) return MS_OK;
+  const uint64_t mtiles = ceil_div(n, C::MTILE);
+  const uint64_t cap = max_grid ? max_grid : ~uint64_t(0);
+  partition_kernel<K, MS_PART_G><<<dim3(unsigned(std::min(ceil_div(mtiles * MS_PART_G, 256), cap))), dim3(256), 0,
+                                   s>>>(src, n, ctl, n, C::MTILE, mtiles, part);
+  merge_kernel<K, V, C::MG_WG, C::MG_IPT, C::MG_PAD>
+      <<<dim3(unsigned(std::min(mtiles, cap))), dim3(C::MG_WG), MT::LDS_BYTES, s>>>(src, nullptr, dst, nullptr, n,
+                                                                                  ctl, n, part);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MS_OK : hip_fail(e, "two-run merge launch");
+}
+template ms_status merge_two_runs<uint32_t, NoVal>(const uint32_t*, uint32_t*, uint64_t, DevCtl, int64_t*, hipStream_t,
+                                                   uint64_t);
+
 #define MS_INSTANTIATE(K, V)                                                                  \
-  template ms_status plain_sort<K, V>(K*, V*, uint64_t, DevCtl, hipStream_t, void*);         \
+  template ms_status plain_sort<K, V>(K*, V*, uint64_t, DevCtl, hipStream_t, void*, uint64_t); \
   template size_t plain_temp_bytes<K, V>(uint64_t);                                           \
   template void plain_geometry<K, V>(int*, int*);
 

@@ -127,7 +127,7 @@ SegLayout seg_layout(uint64_t nseg, uint64_t n_total) {
 // Enqueue the whole segmented pipeline on stream s (possibly capturing).
 template <class K, class V>
 ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint64_t n_total, uint64_t max_len,
-                      void* ws, hipStream_t s, const int* tune, SegFork fork) {
+                      void* ws, hipStream_t s, const int* tune, SegFork fork, void* const* keys_sel) {
   using S = SegCfg<K, V>;
   using P = PlainCfg<K, V>;
   const SegLayout L = seg_layout<K, V>(nseg, n_total);
@@ -141,6 +141,7 @@ ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint6
   st.large_mbase = reinterpret_cast<int64_t*>(w + L.large_mbase);
   st.desc = reinterpret_cast<int4*>(w + L.desc);
   st.part = reinterpret_cast<int64_t*>(w + L.part);
+  st.keys_sel = keys_sel;
   K* tk = reinterpret_cast<K*>(w + L.tk);
   V* tv = reinterpret_cast<V*>(w + L.tv);
   const uint64_t cus = uint64_t(device_cu_count());
@@ -216,7 +217,7 @@ void seg_candidate(int cls, int idx, int* wg, int* ipt) {
 
 #define MS_SEG_INSTANTIATE(K, V)                                                                              \
   template ms_status seg_enqueue<K, V>(K*, V*, const int64_t*, uint64_t, uint64_t, uint64_t, void*, hipStream_t, \
-                                       const int*, SegFork);                                                  \
+                                       const int*, SegFork, void* const*);                                    \
   template size_t seg_temp_bytes<K, V>(uint64_t, uint64_t);                                                   \
   template int seg_num_classes<K, V>();                                                                       \
   template void seg_class_info<K, V>(int, uint32_t*, int*);                                                   \

@@ -38,6 +38,7 @@ struct SegState {
   int64_t* large_mbase;  // [nseg] first reserved merge tile per large slot
   int4* desc;            // [mt_cap] per reserved merge tile: segment base (lo, hi), length, tile index
   int64_t* part;         // [mt_cap] merge-path splits of the current pass
+  void* const* keys_sel; // if non-null, small classes sort the key array *keys_sel (chosen on the device)
 };
 
 // A reserved merge tile of a large segment, unpacked from its descriptor.
@@ -183,6 +184,7 @@ __global__ __launch_bounds__(WG) void seg_small_kernel(K* __restrict__ keys, V* 
   __shared__ uint32_t cur;
   const uint32_t count = st.cls_count[cls];
   const int32_t* q = st.queues + uint64_t(cls) * nseg;
+  if (st.keys_sel) keys = static_cast<K*>(*st.keys_sel);
   uint32_t c0 = blockIdx.x * chunk;
   while (c0 < count) {
     const uint32_t c1 = c0 + chunk < count ? c0 + chunk : count;

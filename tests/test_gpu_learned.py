@@ -1,0 +1,189 @@
+"""GPU parity of the learned-bucket form: each step against the fp64 oracle
+(gradient, start point, training, inference table, bucket ids), and the
+whole sort bit-exact against the CPU merge-sort oracle, including forced
+spill / repair and forced fallback, plus the trained-vs-no-network gain."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2211_16479_amd as msort
+import workloads
+from gpu_helpers import as_i64, assert_equal_arrays, check_sampled_ranks
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+H = msort.MLP_HIDDEN
+
+
+def u32_np(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().view(torch.int32).numpy().view(np.uint32)
+
+
+def sorted_sample(n_keys: int, S: int, seed: int = 0):
+    keys = u32_np(workloads.lognormal_mix_u32(n_keys, seed=seed))
+    rng = np.random.default_rng(seed)
+    return np.sort(keys[rng.integers(0, keys.size, S)]), keys
+
+
+def dev_u32(a: np.ndarray, dev) -> torch.Tensor:
+    return torch.from_numpy(a.view(np.int32).copy()).to(dev).view(torch.uint32)
+
+
+@pytest.mark.parametrize("feature", [msort.MS_FEATURE_LOG, msort.MS_FEATURE_LINEAR])
+def test_gradient_matches_oracle(gpu, feature):
+    sample, _ = sorted_sample(1 << 18, 1 << 14, seed=1)
+    feat = mlp.feature_log if feature == msort.MS_FEATURE_LOG else mlp.feature_linear
+    x = feat(sample).astype(np.float64)
+    y = mlp.targets(x.size)
+    rng = np.random.default_rng(2)
+    th = mlp.init_params(x, H)
+    th = (th * (1 + 0.05 * rng.standard_normal(th.size))).astype(np.float32).astype(np.float64)
+    out = msort.ms_learned_grad(dev_u32(sample, gpu), torch.tensor(th, dtype=torch.float32, device=gpu), feature)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy().astype(np.float64)
+    g = mlp.grad(th, x, y, H)
+    scale = np.abs(g).max()
+    np.testing.assert_allclose(out[:-1], g, rtol=1e-3, atol=2e-4 * scale)
+    sse = np.sum((mlp.forward(th, x, H) - y) ** 2)
+    assert out[-1] == pytest.approx(sse, rel=1e-3)
+
+
+def test_start_point_and_training_match_oracle(gpu):
+    sample, _ = sorted_sample(1 << 20, 1 << 16, seed=3)
+    x = mlp.feature_log(sample).astype(np.float64)
+    th0_gpu, hist0 = msort.ms_learned_train(dev_u32(sample, gpu), 0, 0.0)
+    torch.cuda.synchronize()
+    th0 = mlp.init_params(x, H)
+    np.testing.assert_allclose(th0_gpu.cpu().numpy(), th0, rtol=2e-6, atol=1e-9)
+    steps, lr = 60, 1e-3
+    th_gpu, hist_gpu = msort.ms_learned_train(dev_u32(sample, gpu), steps, lr)
+    torch.cuda.synchronize()
+    th_ref, hist_ref = mlp.train(x, H, steps, lr)
+    hg = hist_gpu.cpu().numpy().astype(np.float64)
+    # same loss trajectory (fp32 vs fp64 arithmetic), and training helps
+    np.testing.assert_allclose(hg, hist_ref[:steps], rtol=0.05)
+    final_gpu = mlp.loss(th_gpu.cpu().numpy().astype(np.float64), x, mlp.targets(x.size), H)
+    assert final_gpu < 0.5 * hg[0]
+    assert final_gpu == pytest.approx(hist_ref[-1], rel=0.1)
+
+
+def test_table_matches_oracle_and_bucket_ids_are_monotone(gpu):
+    sample, keys = sorted_sample(1 << 20, 1 << 16, seed=4)
+    x = mlp.feature_log(sample).astype(np.float64)
+    th, _ = mlp.train(x, H, 40, 1e-3)
+    th32 = th.astype(np.float32)
+    tt, vv, n = msort.ms_learned_table(torch.tensor(th32, device=gpu))
+    torch.cuda.synchronize()
+    t_ref, v_ref = mlp.pl_table(th32.astype(np.float64), H)
+    assert n == t_ref.size
+    np.testing.assert_allclose(tt.cpu().numpy(), t_ref, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(vv.cpu().numpy(), v_ref, rtol=1e-5, atol=1e-6)
+    lb = 16
+    ks = np.sort(keys)
+    ids = msort.ms_learned_bucket_ids(dev_u32(ks, gpu), torch.tensor(th32, device=gpu), lb).cpu().numpy()
+    assert (np.diff(ids.astype(np.int64)) >= 0).all(), "bucket ids must not decrease with the key"
+    ref = mlp.bucket_ids((t_ref, v_ref), mlp.feature_log(ks), 1 << lb)
+    # FP32 evaluation vs fp64: one ulp of u * B is ~0.004 of a bucket at
+    # B = 2^16, so keys within that distance of a boundary may land one
+    # bucket over; bucket ids only steer speed (the output is exact anyway)
+    d = ids.astype(np.int64) - ref
+    assert np.abs(d).max() <= 1 and (d != 0).mean() < 0.02
+    # the no-network form is floor(x * B)
+    lin = msort.ms_learned_bucket_ids(dev_u32(ks, gpu), torch.tensor(th32, device=gpu), lb,
+                                      feature=msort.MS_FEATURE_LINEAR, use_network=False).cpu().numpy()
+    exp = np.minimum(np.floor(mlp.feature_linear(ks).astype(np.float64) * (1 << lb)), (1 << lb) - 1)
+    assert_equal_arrays(lin.astype(np.int64), exp.astype(np.int64), "no-network bucket ids")
+
+
+def learned_sort(keys_np: np.ndarray, dev, **opt):
+    t = dev_u32(keys_np, dev)
+    t, st = msort.ms_sort_ex(t, algo=msort.MS_ALGO_LEARNED_BUCKET, **opt)
+    return u32_np(t), st
+
+
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_learned_sort_lognormal_exact(gpu, use_graph):
+    keys = u32_np(workloads.lognormal_mix_u32(1 << 22, seed=5))
+    got, st = learned_sort(keys, gpu, use_graph=use_graph)
+    assert_equal_arrays(got, oracle.sort(keys), "learned sort")
+    assert st["algo_used"] == msort.MS_ALGO_LEARNED_BUCKET and st["fallback_taken"] == 0
+    assert st["spilled"] == 0 and st["misordered"] == 0
+    assert st["loss_final"] < st["loss_initial"]
+
+
+@pytest.mark.parametrize("dist", ["uniform", "lognormal_ties", "sorted", "few"])
+def test_learned_sort_other_inputs_exact(gpu, dist):
+    n = 1 << 20
+    rng = np.random.default_rng(6)
+    if dist == "uniform":
+        keys = u32_np(workloads.uniform_u32(n + 12345, seed=6))
+    elif dist == "lognormal_ties":
+        keys = u32_np(workloads.lognormal_mix_u32(n, seed=7)) & np.uint32(0xFFFFF000)
+    elif dist == "sorted":
+        keys = np.sort(u32_np(workloads.uniform_u32(n, seed=8)))
+    else:
+        keys = rng.integers(0, 7, size=n).astype(np.uint32)
+    got, st = learned_sort(keys, gpu, spill_threshold=0.5)
+    assert_equal_arrays(got, oracle.sort(keys), f"learned sort {dist}")
+
+
+def test_forced_spill_is_repaired_exactly(gpu):
+    """Small buckets overflow: the spill is sorted and merged back."""
+    keys = u32_np(workloads.lognormal_mix_u32(1 << 21, seed=9))
+    got, st = learned_sort(keys, gpu, bucket_capacity=4096, bucket_fill=2048, spill_threshold=0.5, train_steps=0)
+    assert_equal_arrays(got, oracle.sort(keys), "spill + repair")
+    assert st["fallback_taken"] == 0 and st["repaired"] == 1 and st["spilled"] > 0
+
+
+def test_forced_fallback_is_exact(gpu):
+    keys = u32_np(workloads.lognormal_mix_u32(1 << 21, seed=10))
+    got, st = learned_sort(keys, gpu, force_fallback=1)
+    assert_equal_arrays(got, oracle.sort(keys), "forced fallback")
+    assert st["fallback_taken"] == 1 and st["algo_used"] == msort.MS_ALGO_MERGE_PATH
+    got, st = learned_sort(keys, gpu, bucket_capacity=4096, bucket_fill=4096, spill_threshold=0.0, train_steps=4)
+    assert_equal_arrays(got, oracle.sort(keys), "spill above threshold")
+    assert st["fallback_taken"] == 1 and st["spilled"] > 0
+
+
+def test_trained_network_beats_no_network(gpu):
+    """Same keys: the trained MLP spills nothing and stays on the learned
+    path; without the network (bucket = floor(x * B)) the mixture piles into
+    few buckets, spills, and falls back.  Both outputs are exact."""
+    keys = u32_np(workloads.lognormal_mix_u32(1 << 22, seed=11))
+    exp = oracle.sort(keys)
+    got_t, st_t = learned_sort(keys, gpu)
+    got_l, st_l = learned_sort(keys, gpu, use_network=0, feature=msort.MS_FEATURE_LINEAR)
+    assert_equal_arrays(got_t, exp, "trained")
+    assert_equal_arrays(got_l, exp, "no network")
+    assert st_t["spilled"] < st_l["spilled"] and st_t["max_bucket"] < st_l["max_bucket"]
+    assert st_t["fallback_taken"] == 0 and st_l["fallback_taken"] == 1
+
+
+def test_graph_replay_on_new_data(gpu):
+    t = torch.empty(1 << 21, dtype=torch.uint32, device=gpu)
+    for seed in (12, 13):
+        keys = u32_np(workloads.lognormal_mix_u32(1 << 21, seed=seed))
+        t.copy_(dev_u32(keys, gpu))
+        msort.ms_sort_ex(t, algo=msort.MS_ALGO_LEARNED_BUCKET, stats=False)
+        torch.cuda.synchronize()
+        assert_equal_arrays(u32_np(t), oracle.sort(keys), f"replay seed {seed}")
+
+
+def test_full_lognormal_2p29_learned_equals_plain(gpu):
+    """2^29 uint32 keys from the 8-lognormal mixture: learned and plain
+    outputs byte-identical; cross-checked against torch.sort and sampled
+    oracle ranks."""
+    k = workloads.lognormal_mix_u32(1 << 29, seed=0, device=gpu)
+    a = k.clone()
+    _, st = msort.ms_sort_ex(a, algo=msort.MS_ALGO_LEARNED_BUCKET)
+    b = k.clone()
+    msort.ms_sort(b)
+    torch.cuda.synchronize()
+    assert st["fallback_taken"] == 0
+    assert bool((a.view(torch.int32) == b.view(torch.int32)).all()), "learned != plain"
+    del b
+    ref = torch.sort(as_i64(k)).values
+    assert bool((as_i64(a) == ref).all())
+    del ref
+    check_sampled_ranks(u32_np(k), u32_np(a), samples=8, seed=7)
