@@ -25,12 +25,18 @@ empirical CDF through H knots at sample quantiles -- unit h is a ramp
 relu(x - k_h) whose output weight is the slope change at knot k_h.
 
 Inference: a 1-D two-layer ReLU network is a piecewise-linear function whose
-breakpoints are -b1_h / w1_h.  `pl_table` lists F at the breakpoints inside
-[0, 1] (plus 0 and 1) and replaces every value by the running maximum (the
-smallest non-decreasing function >= F at those points); `pl_eval` evaluates
-that table by linear interpolation, capped at the next point's value.  Where
-F is non-decreasing the table reproduces F exactly; everywhere it is
-non-decreasing, so bucket ids derived from it are ordered like the keys.
+breakpoints are -b1_h / w1_h.  `pl_table` restricts it to the sample's
+feature range [x_min, x_max]: points x_min, the breakpoints strictly inside,
+x_max; values the running maximum of F at those points (the smallest
+non-decreasing function >= F there), clamped into [0.5/S, 1 - 0.5/S], with
+the two ends pinned to 0.5/S and 1 - 0.5/S -- the mid-ranks of the sample's
+own extremes.  `pl_eval` clamps x into the range and interpolates linearly,
+capped at the next point's value.  Inside the range, wherever F is
+non-decreasing and within the clamp, the table reproduces F; everywhere it
+is non-decreasing, so bucket ids derived from it are ordered like the keys.
+(Pinning the ends keeps the thin tails of a distribution from collapsing
+into the first and last bucket when the trained F over- or undershoots
+there.)
 
 Input features are computed from the integer key in float32, exactly as the
 GPU computes them (IEEE round-to-nearest-even), so both sides see
@@ -138,23 +144,24 @@ def train(x_sorted: np.ndarray, H: int, steps: int, lr: float, theta0=None):
     return theta, np.array(hist)
 
 
-def pl_table(theta: np.ndarray, H: int):
-    """(t, V): breakpoints of F inside (0, 1) plus 0 and 1, ascending, and the
-    running maximum of F over those points."""
+def pl_table(theta: np.ndarray, H: int, x_min: float, x_max: float, S: int):
+    """(t, V) of the network on [x_min, x_max] as described in the header."""
     w1, b1, w2, b2 = unpack(theta, H)
     with np.errstate(divide="ignore", invalid="ignore"):
         bp = -b1 / w1
-    bp = bp[(w1 != 0) & (bp > 0) & (bp < 1)]
-    t = np.unique(np.concatenate([[0.0, 1.0], bp]))
-    V = np.maximum.accumulate(forward(theta, t, H))
+    bp = bp[(w1 != 0) & (bp > x_min) & (bp < x_max)]
+    t = np.concatenate([[x_min], np.unique(bp), [x_max]])
+    lo, hi = 0.5 / S, 1.0 - 0.5 / S
+    V = np.clip(np.maximum.accumulate(forward(theta, t, H)), lo, hi)
+    V[0], V[-1] = lo, hi
     return t, V
 
 
 def pl_eval(table, x: np.ndarray) -> np.ndarray:
-    """Monotone evaluation of a table: clamp x to [0, 1], find the segment,
-    interpolate, cap at the segment's right value."""
+    """Monotone evaluation of a table: clamp x to [t_0, t_last], find the
+    segment, interpolate, cap at the segment's right value."""
     t, V = table
-    x = np.clip(np.asarray(x, np.float64), 0.0, 1.0)
+    x = np.clip(np.asarray(x, np.float64), t[0], t[-1])
     j = np.clip(np.searchsorted(t, x, side="right") - 1, 0, t.size - 2)
     dt = t[j + 1] - t[j]
     slope = np.where(dt > 0, (V[j + 1] - V[j]) / np.where(dt > 0, dt, 1.0), 0.0)

@@ -87,21 +87,44 @@ def test_start_point_with_ties_reaches_post_tie_values():
 
 def test_pl_table_exact_for_monotone_networks_and_monotone_always():
     rng = np.random.default_rng(10)
-    xs = np.linspace(0.0, 1.0, 20001)
+    S = 1000
+    lo, hi = 0.5 / S, 1 - 0.5 / S
     for _ in range(40):
         H = int(rng.choice([2, 4, 16]))
-        # a non-decreasing network: positive slopes everywhere (w1, w2 > 0)
-        th = np.concatenate([rng.uniform(0.1, 3, H), rng.uniform(-2, 1, H), rng.uniform(0.01, 1, H), [0.1]])
-        np.testing.assert_allclose(mlp.pl_eval(mlp.pl_table(th, H), xs), mlp.forward(th, xs, H),
+        x_min, x_max = sorted(rng.uniform(0, 1, 2))
+        xs = np.linspace(x_min, x_max, 20001)
+        # a non-decreasing network that stays inside (lo, hi) on the range
+        th = np.concatenate([rng.uniform(0.1, 3, H), rng.uniform(-2, 1, H), rng.uniform(0.01, 1, H), [0.0]])
+        F = mlp.forward(th, xs, H)                       # b2 = 0 here
+        th[2 * H:3 * H] *= 0.4 / max(F[-1] - F[0], 1e-12)
+        th[3 * H] = 0.3 - mlp.forward(th, xs[:1], H)[0]   # F spans [0.3, 0.7] on the range
+        F = mlp.forward(th, xs, H)
+        tab = mlp.pl_table(th, H, x_min, x_max, S)
+        ev = mlp.pl_eval(tab, xs)
+        inner = slice(1, -1)   # the ends are pinned to lo / hi
+        np.testing.assert_allclose(ev[inner][(xs[inner] > tab[0][1]) & (xs[inner] < tab[0][-2])],
+                                   F[inner][(xs[inner] > tab[0][1]) & (xs[inner] < tab[0][-2])],
                                    rtol=1e-12, atol=1e-12)
-        # arbitrary network: table is non-decreasing and equals the running max at breakpoints
+        assert tab[1][0] == lo and tab[1][-1] == hi
+        # arbitrary network: non-decreasing, inside [lo, hi], running max at interior points
         th2 = rng.normal(scale=2.0, size=3 * H + 1)
-        t, V = mlp.pl_table(th2, H)
-        ev = mlp.pl_eval((t, V), xs)
-        assert (np.diff(ev) >= 0).all()
-        dense = np.linspace(0, 1, 200001)
-        runmax = np.maximum.accumulate(mlp.forward(th2, dense, H))
-        np.testing.assert_allclose(V, np.interp(t, dense, runmax), atol=1e-3 * (1 + np.abs(V).max()))
+        t, V = mlp.pl_table(th2, H, x_min, x_max, S)
+        ev = mlp.pl_eval((t, V), np.linspace(-0.5, 1.5, 40001))
+        assert (np.diff(ev) >= 0).all() and ev.min() >= lo and ev.max() <= hi
+        dense = np.linspace(x_min, x_max, 200001)
+        runmax = np.clip(np.maximum.accumulate(mlp.forward(th2, dense, H)), lo, hi)
+        np.testing.assert_allclose(V[1:-1], np.interp(t[1:-1], dense, runmax), atol=1e-3 * (1 + np.abs(V).max()))
+
+
+def test_pl_table_ends_spread_the_tails():
+    """A network that overshoots 1 before the sample maximum would send the
+    whole upper tail to the last bucket; the pinned ends spread it."""
+    H = 2
+    th = np.array([1.0, 0.0, 0.0, 0.0, 2.0, 0.0, 0.0])   # F(x) = 2x
+    x_min, x_max, S = 0.0, 1.0, 1 << 16
+    xs = np.linspace(0.5, 1.0, 1001)                     # F >= 1 on all of these
+    b = mlp.bucket_ids(mlp.pl_table(th, H, x_min, x_max, S), xs, 1024)
+    assert np.unique(b).size > 500
 
 
 def test_feature_values_and_monotonicity():
@@ -130,5 +153,5 @@ def test_training_improves_on_the_start_point():
     th, hist = mlp.train(x, 16, steps=200, lr=1e-3)
     assert hist[0] == pytest.approx(l0)
     assert hist[-1] < l0
-    b = mlp.bucket_ids(mlp.pl_table(th, 16), x, 64)
+    b = mlp.bucket_ids(mlp.pl_table(th, 16, x[0], x[-1], S), x, 64)
     assert (np.diff(b) >= 0).all()
