@@ -35,6 +35,9 @@ WORKLOADS = {
     "normal_i64_2p28": ("merge sort of 2^28 int64 keys round(N(0, 1) * 2^40), keys only", 1 << 28, 8, 0, 3),
     "nearly_sorted_i64_2p28": ("merge sort of the sorted 2^28 int64 normal array with 1% disjoint adjacent "
                                "swaps, keys only", 1 << 28, 8, 0, 3),
+    "lognormal_u32_2p29": ("2^29 uint32 keys from an equal-weight mixture of 8 lognormals (mu ~ U(0,4), "
+                           "sigma ~ U(0.1,1), scaled and clipped to uint32): learned-bucket sort vs plain merge "
+                           "path", 1 << 29, 4, 0, 0),
     "segments_u32_10000": ("batched segmented sort: 10,000 independent uint32 arrays, lengths log-uniform in "
                            "[16, 2^18], uniform keys, one graph launch, autotuned shape per size class",
                            None, 4, 0, 0),
@@ -138,6 +141,57 @@ def cpu_baseline(name, pristine, budget_s=20.0):
                       f"merge sort, {dt:.2f} s"}
 
 
+def time_restored(fn, work, pristine, steps, warmup):
+    """Mean event-timed duration (ms) of fn() over `steps` runs; before each
+    run the pristine input is copied into `work`, outside the event window."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        work.copy_(pristine)
+        fn()
+    torch.cuda.synchronize()
+    total = 0.0
+    for _ in range(steps):
+        work.copy_(pristine)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        total += a.elapsed_time(b)
+    return total / steps
+
+
+def learned_vs_plain(steps=5, warmup=2):
+    """Both forms on the 2^29 lognormal-mixture workload, the same way:
+    Gkeys/s of each, the speedup, whether the two outputs are byte-identical,
+    and the learned run's device-side statistics."""
+    import torch
+    import paper_2211_16479_amd as msort
+    import workloads
+    dev = torch.device("cuda:0")
+    n = 1 << 29
+    pristine = workloads.lognormal_mix_u32(n, seed=0, device=dev)
+    work = torch.empty_like(pristine)
+    t_plain = time_restored(lambda: msort.ms_sort(work), work, pristine, steps, warmup)
+    out_plain = work.clone()
+    t_learned = time_restored(lambda: msort.ms_sort_ex(work, algo=msort.MS_ALGO_LEARNED_BUCKET, stats=False),
+                              work, pristine, steps, warmup)
+    work.copy_(pristine)
+    _, st = msort.ms_sort_ex(work, algo=msort.MS_ALGO_LEARNED_BUCKET)
+    torch.cuda.synchronize()
+    same = bool((work.view(torch.int32) == out_plain.view(torch.int32)).all())
+    del out_plain, work, pristine
+    torch.cuda.empty_cache()
+    return {"workload": WORKLOADS["lognormal_u32_2p29"][0], "n": n,
+            "plain_ms": round(t_plain, 4), "plain_Gkeys_s": round(n / (t_plain * 1e-3) / 1e9, 3),
+            "learned_ms": round(t_learned, 4), "learned_Gkeys_s": round(n / (t_learned * 1e-3) / 1e9, 3),
+            "speedup": round(t_plain / t_learned, 3), "outputs_identical": same,
+            "learned_stats": {k: (round(v, 8) if isinstance(v, float) else v) for k, v in st.items()}}
+
+
 def bench_segmented(args, desc):
     """One step = one ms_segmented_sort (one graph launch) of all 10,000
     arrays.  The same buffers are reused so the cached graph is replayed; the
@@ -186,6 +240,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="zipf_pairs_u32_2p27", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-vs-plain comparison on the lognormal-mixture workload")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time without the per-launch events (no roofline)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -215,6 +271,15 @@ def main():
     K, W = args.steps, args.warmup
     if args.workload == "segments_u32_10000":
         return bench_segmented(args, desc)
+    if args.workload == "lognormal_u32_2p29":
+        r = learned_vs_plain(K, W)
+        print(json.dumps({
+            "metric": "Gkeys/s and HBM GB/s vs peak, plain merge-path vs learned-bucket, bit-exact",
+            "value": r["learned_Gkeys_s"], "unit": "Gkeys/s", "n_gpus": 1, "steps": K, "warmup": W,
+            "ms_per_step": r["learned_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u32", "data": "synthetic", "config": {"workload": desc, "n": n},
+            "learned_vs_plain": r, "roofline": None, "cpu_baseline": None}))
+        return
     bufs, pristine = make_inputs(args.workload, K + W, dev)
     torch.cuda.synchronize()
 
@@ -257,6 +322,11 @@ def main():
     plan = msort.ms_plan_query(n, kt, vb)
     total_bytes = n * (kb + vb) * 2 * (1 + plan["passes"])
 
+    del bufs
+    torch.cuda.empty_cache()
+    lvp = None
+    if not args.no_learned and args.workload == "zipf_pairs_u32_2p27":
+        lvp = learned_vs_plain()
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.workload, pristine)
@@ -280,6 +350,7 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "learned_vs_plain": lvp,
     }
     print(json.dumps(out))
 

@@ -157,8 +157,10 @@ ms_status ms_tuning_load(const char* path, const char* arch, int* applied);
  * sample of 2^sample_log2 keys that the plain merge sort ranks: closed-form
  * start at the piecewise-linear interpolant through 16 sample quantiles,
  * then full-batch Adam on the mean squared rank error.  The trained network
- * is evaluated as the piecewise-linear function it is, through a running-max
- * envelope, so bucket ids floor(F(x) * B) are non-decreasing in the key.
+ * is evaluated as the piecewise-linear function it is, on the sample's
+ * feature range with the ends pinned to the sample's extreme mid-ranks, and
+ * through a running-max envelope, so bucket ids floor(F(x) * B) are
+ * non-decreasing in the key.
  * Keys are scattered (two levels) into B ~ n / bucket_fill buckets; buckets
  * of at most bucket_capacity keys are sorted in LDS; larger ones spill.  The
  * spill is sorted by the plain merge sort and merged back with one exact
@@ -179,8 +181,8 @@ typedef struct ms_options {
   float spill_threshold;     /* fall back when spilled keys > this * n; [0, 0.5], default 0.05 */
   uint32_t bucket_capacity;  /* keys sorted per LDS bucket: 4096 or 16384 (default) */
   uint32_t bucket_fill;      /* target mean keys per bucket, 64..capacity, default 2048 */
-  uint32_t train_steps;      /* Adam steps, default 128 */
-  float learning_rate;       /* default 1e-3 */
+  uint32_t train_steps;      /* Adam steps, default 64 */
+  float learning_rate;       /* default 1e-4 */
   uint32_t sample_log2;      /* log2 of the sample size, 10..20, default 16 */
   uint64_t seed;             /* sample positions, default 0 */
   int feature;               /* ms_feature, default MS_FEATURE_LOG */
@@ -227,19 +229,22 @@ ms_status ms_sort_ex(void* d_keys, size_t n, ms_key_type kt, const ms_options* o
  *                       `steps` Adam steps; write the parameters to
  *                       d_theta_out[49] and, if d_loss_hist is not NULL, the
  *                       loss before each step to d_loss_hist[steps].
- *   ms_learned_table  : the inference table of theta: breakpoints d_t[32]
- *                       (ascending, +inf padded), running-max values d_v[32],
- *                       count d_count[1].
+ *   ms_learned_table  : the inference table of theta on the sorted sample's
+ *                       feature range: points d_t[32] (ascending, +inf
+ *                       padded), values d_v[32], count d_count[1].
  *   ms_learned_bucket_ids : bucket id in [0, 2^log2_buckets) of each of n
- *                       keys under theta (use_network = 0: floor(x * B)).
+ *                       keys under theta and the sorted sample's table
+ *                       (use_network = 0: floor(x * B)).
  */
 ms_status ms_learned_grad(const uint32_t* d_sample, uint32_t S, int feature, const float* d_theta, float* d_out,
                           void* stream);
 ms_status ms_learned_train(const uint32_t* d_sample, uint32_t S, int feature, uint32_t steps, float learning_rate,
                            const float* d_theta0, float* d_theta_out, float* d_loss_hist, void* stream);
-ms_status ms_learned_table(const float* d_theta, float* d_t, float* d_v, int* d_count, void* stream);
-ms_status ms_learned_bucket_ids(const uint32_t* d_keys, size_t n, const float* d_theta, int feature, int use_network,
-                                uint32_t log2_buckets, uint32_t* d_out, void* stream);
+ms_status ms_learned_table(const float* d_theta, const uint32_t* d_sample, uint32_t S, int feature, float* d_t,
+                           float* d_v, int* d_count, void* stream);
+ms_status ms_learned_bucket_ids(const uint32_t* d_keys, size_t n, const float* d_theta, const uint32_t* d_sample,
+                                uint32_t S, int feature, int use_network, uint32_t log2_buckets, uint32_t* d_out,
+                                void* stream);
 
 /*
  * ms_temp_bytes -- device scratch (bytes) that a plain sort of n keys with

@@ -83,8 +83,8 @@ def _declare(lib):
         "ms_sort_ex": (i32, [vp, sz, i32, c.POINTER(MsOptions), vp, vp]),
         "ms_learned_grad": (i32, [vp, c.c_uint32, i32, vp, vp, vp]),
         "ms_learned_train": (i32, [vp, c.c_uint32, i32, c.c_uint32, c.c_float, vp, vp, vp, vp]),
-        "ms_learned_table": (i32, [vp, vp, vp, vp, vp]),
-        "ms_learned_bucket_ids": (i32, [vp, sz, vp, i32, i32, c.c_uint32, vp, vp]),
+        "ms_learned_table": (i32, [vp, vp, c.c_uint32, i32, vp, vp, vp, vp]),
+        "ms_learned_bucket_ids": (i32, [vp, sz, vp, vp, c.c_uint32, i32, i32, c.c_uint32, vp, vp]),
         "ms_profile_enable": (i32, [i32]),
         "ms_profile_reset": (i32, []),
         "ms_profile_read": (i32, [i32, c.POINTER(c.c_uint64), c.POINTER(c.c_double)]),
@@ -297,27 +297,31 @@ def ms_learned_train(sample_sorted: torch.Tensor, steps: int, learning_rate: flo
     return th, hist[:steps]
 
 
-def ms_learned_table(theta: torch.Tensor):
-    """(breakpoints, running-max values, count) of theta's inference table."""
+def ms_learned_table(theta: torch.Tensor, sample_sorted: torch.Tensor, feature: int = MS_FEATURE_LOG):
+    """(points, values, count) of theta's inference table on the sorted sample's range."""
     _f32(theta, MLP_PARAMS, "theta")
+    _dev(sample_sorted, "sample")
     t = torch.empty(32, dtype=torch.float32, device=theta.device)
     v = torch.empty(32, dtype=torch.float32, device=theta.device)
     c = torch.empty(1, dtype=torch.int32, device=theta.device)
-    _check(lib().ms_learned_table(ctypes.c_void_p(theta.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+    _check(lib().ms_learned_table(ctypes.c_void_p(theta.data_ptr()), ctypes.c_void_p(sample_sorted.data_ptr()),
+                                  sample_sorted.numel(), feature, ctypes.c_void_p(t.data_ptr()),
                                   ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(c.data_ptr()), _stream(theta)),
            "ms_learned_table")
     n = int(c.item())
     return t[:n], v[:n], n
 
 
-def ms_learned_bucket_ids(keys: torch.Tensor, theta: torch.Tensor, log2_buckets: int,
+def ms_learned_bucket_ids(keys: torch.Tensor, theta: torch.Tensor, sample_sorted: torch.Tensor, log2_buckets: int,
                           feature: int = MS_FEATURE_LOG, use_network: bool = True):
     _dev(keys, "keys")
+    _dev(sample_sorted, "sample")
     _f32(theta, MLP_PARAMS, "theta")
     out = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
     _check(lib().ms_learned_bucket_ids(ctypes.c_void_p(keys.data_ptr()), keys.numel(),
-                                       ctypes.c_void_p(theta.data_ptr()), feature, 1 if use_network else 0,
-                                       log2_buckets, ctypes.c_void_p(out.data_ptr()), _stream(keys)),
+                                       ctypes.c_void_p(theta.data_ptr()), ctypes.c_void_p(sample_sorted.data_ptr()),
+                                       sample_sorted.numel(), feature, 1 if use_network else 0, log2_buckets,
+                                       ctypes.c_void_p(out.data_ptr()), _stream(keys)),
            "ms_learned_bucket_ids")
     return out
 

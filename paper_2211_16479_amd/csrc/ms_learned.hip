@@ -172,7 +172,7 @@ static ms_status learned_enqueue(uint32_t* keys, uint64_t n, const ms_options& o
   // train and compile the network
   st = ls_train_enqueue(sample, P.S, md, partial, int(o.train_steps), o.learning_rate, loss, true, s);
   if (st != MS_OK) return st;
-  ls_compile_kernel<<<1, 64, 0, s>>>(md, int(o.train_steps) & 1, nullptr);
+  ls_compile_kernel<<<1, 64, 0, s>>>(md, int(o.train_steps) & 1, sample, P.S, nullptr);
   // level 1
   ls_clear_kernel<<<dim3(unsigned(ceil_div(std::max<uint64_t>(P.B, P.nbc), 256))), 256, 0, s>>>(bn, P.nbc,
                                                                                                  uint32_t(P.B));
@@ -263,8 +263,8 @@ void ms_options_default(ms_options* o) {
   o->spill_threshold = 0.05f;
   o->bucket_capacity = 16384;
   o->bucket_fill = 2048;
-  o->train_steps = 128;
-  o->learning_rate = 1e-3f;
+  o->train_steps = 64;
+  o->learning_rate = 1e-4f;
   o->sample_log2 = 16;
   o->seed = 0;
   o->feature = MS_FEATURE_LOG;
@@ -370,9 +370,10 @@ ms_status ms_learned_train(const uint32_t* d_sample, uint32_t S, int feature, ui
   return e == hipSuccess ? MS_OK : hip_fail(e, "training launch");
 }
 
-ms_status ms_learned_table(const float* d_theta, float* d_t, float* d_v, int* d_count, void* stream) {
-  if (!d_theta || !d_t || !d_v || !d_count) {
-    set_error("NULL pointer");
+ms_status ms_learned_table(const float* d_theta, const uint32_t* d_sample, uint32_t S, int feature, float* d_t,
+                           float* d_v, int* d_count, void* stream) {
+  if (!d_theta || !d_sample || S == 0 || !d_t || !d_v || !d_count) {
+    set_error("NULL pointer or empty sample");
     return MS_ERR_INVALID_ARG;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -380,19 +381,20 @@ ms_status ms_learned_table(const float* d_theta, float* d_t, float* d_v, int* d_
   ms_status st = step_scratch(s, 0, &w);
   if (st != MS_OK) return st;
   LsModel* md = reinterpret_cast<LsModel*>(w);
-  ls_setup_kernel<<<1, 64, 0, s>>>(md, 1, 1, 0, 0);
+  ls_setup_kernel<<<1, 64, 0, s>>>(md, feature == MS_FEATURE_LOG ? 1 : 0, 1, 0, 0);
   ls_set_theta_kernel<<<1, 64, 0, s>>>(md, d_theta);
-  ls_compile_kernel<<<1, 64, 0, s>>>(md, 0, nullptr);
+  ls_compile_kernel<<<1, 64, 0, s>>>(md, 0, d_sample, S, nullptr);
   ls_get_table_kernel<<<1, 64, 0, s>>>(md, d_t, d_v, d_count);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? MS_OK : hip_fail(e, "table launch");
 }
 
-ms_status ms_learned_bucket_ids(const uint32_t* d_keys, size_t n, const float* d_theta, int feature, int use_network,
-                                uint32_t log2_buckets, uint32_t* d_out, void* stream) {
+ms_status ms_learned_bucket_ids(const uint32_t* d_keys, size_t n, const float* d_theta, const uint32_t* d_sample,
+                                uint32_t S, int feature, int use_network, uint32_t log2_buckets, uint32_t* d_out,
+                                void* stream) {
   if (n == 0) return MS_OK;
-  if (!d_keys || !d_theta || !d_out || log2_buckets > 20) {
-    set_error("NULL pointer or more than 2^20 buckets");
+  if (!d_keys || !d_theta || !d_sample || S == 0 || !d_out || log2_buckets > 20) {
+    set_error("NULL pointer, empty sample or more than 2^20 buckets");
     return MS_ERR_INVALID_ARG;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -403,7 +405,7 @@ ms_status ms_learned_bucket_ids(const uint32_t* d_keys, size_t n, const float* d
   const int cb = int(std::min<uint32_t>(log2_buckets, 10)), fb = int(log2_buckets) - cb;
   ls_setup_kernel<<<1, 64, 0, s>>>(md, feature == MS_FEATURE_LOG ? 1 : 0, use_network ? 1 : 0, cb, fb);
   ls_set_theta_kernel<<<1, 64, 0, s>>>(md, d_theta);
-  ls_compile_kernel<<<1, 64, 0, s>>>(md, 0, nullptr);
+  ls_compile_kernel<<<1, 64, 0, s>>>(md, 0, d_sample, S, nullptr);
   ls_bucket_ids_kernel<<<dim3(unsigned(ceil_div(n, 256))), 256, 0, s>>>(d_keys, n, md, d_out);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? MS_OK : hip_fail(e, "bucket id launch");

@@ -238,21 +238,24 @@ __global__ __launch_bounds__(LS_TRAIN_WG) void ls_train_kernel(const uint32_t* _
 }
 
 // ------------------------------------------------------------ compile
-// One thread: the trained network's breakpoints inside (0, 1), plus 0 and 1,
-// sorted; F there in double; running maximum; FP32 table with slopes.
-__global__ void ls_compile_kernel(LsModel* md, int final_parity, const int* gate) {
+// One thread: the trained network restricted to the sample's feature range
+// [x_min, x_max]: x_min, the breakpoints strictly inside (sorted), x_max;
+// F there in double; running maximum clamped into [0.5/S, 1 - 0.5/S], ends
+// pinned to those values; FP32 table with segment slopes.
+__global__ void ls_compile_kernel(LsModel* md, int final_parity, const uint32_t* __restrict__ sample, uint32_t S,
+                                  const int* gate) {
   if (gate && *gate == 0) return;
   if (threadIdx.x != 0) return;
   const float* th = md->theta[final_parity];
+  const double xmin = ls_feature(sample[0], md->log_feature);
+  const double xmax = ls_feature(sample[S - 1], md->log_feature);
   double t[LS_H + 2];
   int nt = 0;
-  t[nt++] = 0.0;
-  t[nt++] = 1.0;
   for (int h = 0; h < LS_H; ++h) {
     const double w1 = th[h], b1 = th[LS_H + h];
     if (w1 != 0.0) {
       const double bp = -b1 / w1;
-      if (bp > 0.0 && bp < 1.0) t[nt++] = bp;
+      if (bp > xmin && bp < xmax) t[nt++] = bp;
     }
   }
   for (int i = 1; i < nt; ++i) {  // insertion sort
@@ -261,35 +264,41 @@ __global__ void ls_compile_kernel(LsModel* md, int final_parity, const int* gate
     while (j >= 0 && t[j] > x) { t[j + 1] = t[j]; --j; }
     t[j + 1] = x;
   }
-  int u = 0;  // unique, and representable as distinct floats
+  // ends plus the interior points that are distinct floats strictly inside
+  double pts[LS_H + 2];
+  int np = 0;
+  pts[np++] = xmin;
   for (int i = 0; i < nt; ++i)
-    if (u == 0 || float(t[i]) > float(t[u - 1])) t[u++] = t[i];
-  nt = u;
+    if (float(t[i]) > float(pts[np - 1]) && float(t[i]) < float(xmax)) pts[np++] = t[i];
+  pts[np++] = xmax;
+  const double lo = 0.5 / double(S), hi = 1.0 - 0.5 / double(S);
   double V[LS_H + 2];
   double run = -1e300;
-  for (int i = 0; i < nt; ++i) {
+  for (int i = 0; i < np; ++i) {
     double F = th[3 * LS_H];
     for (int h = 0; h < LS_H; ++h) {
-      const double z = double(th[h]) * t[i] + double(th[LS_H + h]);
+      const double z = double(th[h]) * pts[i] + double(th[LS_H + h]);
       if (z > 0.0) F += double(th[2 * LS_H + h]) * z;
     }
     run = F > run ? F : run;
-    V[i] = run;
+    V[i] = run < lo ? lo : (run > hi ? hi : run);
   }
+  V[0] = lo;
+  V[np - 1] = hi;
   for (int i = 0; i < LS_TAB; ++i) {
-    if (i < nt) {
-      md->tab_t[i] = float(t[i]);
+    if (i < np) {
+      md->tab_t[i] = float(pts[i]);
       md->tab_v[i] = float(V[i]);
-      const float dv = i + 1 < nt ? float(V[i + 1]) - float(V[i]) : 0.f;
-      const float dt = i + 1 < nt ? float(t[i + 1]) - float(t[i]) : 0.f;
-      md->tab_s[i] = (i + 1 < nt && dt > 0.f && dv > 0.f) ? dv / dt : 0.f;
+      const float dv = i + 1 < np ? float(V[i + 1]) - float(V[i]) : 0.f;
+      const float dt = i + 1 < np ? float(pts[i + 1]) - float(pts[i]) : 0.f;
+      md->tab_s[i] = (i + 1 < np && dt > 0.f && dv > 0.f) ? dv / dt : 0.f;
     } else {
       md->tab_t[i] = __int_as_float(0x7f800000);  // +inf
-      md->tab_v[i] = md->tab_v[nt - 1];
+      md->tab_v[i] = md->tab_v[np - 1];
       md->tab_s[i] = 0.f;
     }
   }
-  md->tab_n = nt;
+  md->tab_n = np;
 }
 
 // Table in LDS for the per-key bucket function.
@@ -322,12 +331,13 @@ __device__ __forceinline__ uint32_t ls_bucket(const LsTable* tb, uint32_t key) {
   const float x = ls_feature(key, tb->log_feature);
   float u;
   if (tb->use_table) {
-    int j = 0;  // largest j with t[j] <= x (t[0] = 0 <= x), then clamp to n-2
+    const float xc = fminf(fmaxf(x, tb->t[0]), tb->t[tb->n - 1]);  // clamp to the table's range
+    int j = 0;  // largest j with t[j] <= xc, then at most n-2
 #pragma unroll
     for (int step = LS_TAB / 2; step >= 1; step >>= 1)
-      if (tb->t[j + step] <= x) j += step;
+      if (tb->t[j + step] <= xc) j += step;
     j = j < tb->n - 2 ? j : tb->n - 2;
-    u = fminf(__fmaf_rn(tb->s[j], __fsub_rn(x, tb->t[j]), tb->v[j]), tb->v[j + 1]);
+    u = fminf(__fmaf_rn(tb->s[j], __fsub_rn(xc, tb->t[j]), tb->v[j]), tb->v[j + 1]);
   } else {
     u = x;
   }

@@ -56,7 +56,7 @@ def test_start_point_and_training_match_oracle(gpu):
     torch.cuda.synchronize()
     th0 = mlp.init_params(x, H)
     np.testing.assert_allclose(th0_gpu.cpu().numpy(), th0, rtol=2e-6, atol=1e-9)
-    steps, lr = 60, 1e-3
+    steps, lr = 60, 3e-4
     th_gpu, hist_gpu = msort.ms_learned_train(dev_u32(sample, gpu), steps, lr)
     torch.cuda.synchronize()
     th_ref, hist_ref = mlp.train(x, H, steps, lr)
@@ -73,15 +73,16 @@ def test_table_matches_oracle_and_bucket_ids_are_monotone(gpu):
     x = mlp.feature_log(sample).astype(np.float64)
     th, _ = mlp.train(x, H, 40, 1e-3)
     th32 = th.astype(np.float32)
-    tt, vv, n = msort.ms_learned_table(torch.tensor(th32, device=gpu))
+    ds = dev_u32(sample, gpu)
+    tt, vv, n = msort.ms_learned_table(torch.tensor(th32, device=gpu), ds)
     torch.cuda.synchronize()
-    t_ref, v_ref = mlp.pl_table(th32.astype(np.float64), H)
+    t_ref, v_ref = mlp.pl_table(th32.astype(np.float64), H, x[0], x[-1], sample.size)
     assert n == t_ref.size
     np.testing.assert_allclose(tt.cpu().numpy(), t_ref, rtol=1e-6, atol=1e-7)
     np.testing.assert_allclose(vv.cpu().numpy(), v_ref, rtol=1e-5, atol=1e-6)
     lb = 16
     ks = np.sort(keys)
-    ids = msort.ms_learned_bucket_ids(dev_u32(ks, gpu), torch.tensor(th32, device=gpu), lb).cpu().numpy()
+    ids = msort.ms_learned_bucket_ids(dev_u32(ks, gpu), torch.tensor(th32, device=gpu), ds, lb).cpu().numpy()
     assert (np.diff(ids.astype(np.int64)) >= 0).all(), "bucket ids must not decrease with the key"
     ref = mlp.bucket_ids((t_ref, v_ref), mlp.feature_log(ks), 1 << lb)
     # FP32 evaluation vs fp64: one ulp of u * B is ~0.004 of a bucket at
@@ -90,7 +91,7 @@ def test_table_matches_oracle_and_bucket_ids_are_monotone(gpu):
     d = ids.astype(np.int64) - ref
     assert np.abs(d).max() <= 1 and (d != 0).mean() < 0.02
     # the no-network form is floor(x * B)
-    lin = msort.ms_learned_bucket_ids(dev_u32(ks, gpu), torch.tensor(th32, device=gpu), lb,
+    lin = msort.ms_learned_bucket_ids(dev_u32(ks, gpu), torch.tensor(th32, device=gpu), ds, lb,
                                       feature=msort.MS_FEATURE_LINEAR, use_network=False).cpu().numpy()
     exp = np.minimum(np.floor(mlp.feature_linear(ks).astype(np.float64) * (1 << lb)), (1 << lb) - 1)
     assert_equal_arrays(lin.astype(np.int64), exp.astype(np.int64), "no-network bucket ids")
