@@ -13,7 +13,7 @@ from gpu_helpers import (as_i64, assert_equal_arrays, check_sampled_ranks,
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [1, 2, 3, 63, 64, 65, 1000, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193,
+SIZES = [0, 1, 2, 3, 63, 64, 65, 1000, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193,
          12289, 65537, 131071, 300_007, 1_000_003]
 DTYPES = [np.uint32, np.int32, np.uint64, np.int64]
 
@@ -54,7 +54,7 @@ def test_sort_distributions(gpu, dtype, dist):
                          ids=lambda d: np.dtype(d).name)
 def test_pairs_stable_with_ties(gpu, kdt, vdt):
     rng = np.random.default_rng(13)
-    for n in (1, 5, 4096, 4097, 9000, 100_003):
+    for n in (0, 1, 5, 4096, 4097, 9000, 100_003):
         for dist in ("few", "uniform", "equal"):
             k = keys_fill(n, kdt, dist, rng)
             v = np.arange(n, dtype=vdt) * 3 + 1
