@@ -57,10 +57,10 @@ def merge_kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def profiled_traffic(workload: str):
-    """Calibrated HBM bytes per merge_kernel launch from the committed counter
+def profiled_traffic(workload: str, kernel: str = "merge_kernel"):
+    """Calibrated HBM bytes per launch of `kernel` from the committed counter
     summary, or None when there is none or the kernel sources changed since."""
-    path = os.path.join(ROOT, "profiles", f"merge_kernel_{workload}.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -306,21 +306,25 @@ def main():
     value = n / (ms_per_step * 1e-3) / 1e9
 
     kernels = {}
-    for name in ("tile_sort", "partition", "merge"):
+    for name in ("tile_sort", "partition", "merge", "partition4", "merge4"):
         cnt, tot = msort.ms_profile_read(name)
         if cnt:
             kernels[name] = {"launches": cnt, "avg_ms": tot / cnt, "ms_per_step": tot / K}
-    merge = kernels.get("merge")
+    # the dominant merge kernel: the fused four-run merge when passes are
+    # fused, else the two-run merge
+    dom = max((k for k in ("merge", "merge4") if k in kernels), key=lambda k: kernels[k]["ms_per_step"],
+              default=None)
     roofline = None
-    if merge:
+    if dom:
         bytes_per_launch = n * (kb + vb) * 2          # read + write of every key and value
-        achieved = bytes_per_launch / (merge["avg_ms"] * 1e-3) / 1e9
+        achieved = bytes_per_launch / (kernels[dom]["avg_ms"] * 1e-3) / 1e9
+        kname = "merge4_kernel" if dom == "merge4" else "merge_kernel"
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(args.workload),
-                    "kernel": "merge_kernel", "bytes_per_launch": bytes_per_launch}
-    # whole-sort algorithmic bytes (tile sort pass + merge passes)
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(args.workload, kname),
+                    "kernel": kname, "bytes_per_launch": bytes_per_launch}
+    # whole-sort algorithmic bytes (tile sort pass + HBM merge passes)
     plan = msort.ms_plan_query(n, kt, vb)
-    total_bytes = n * (kb + vb) * 2 * (1 + plan["passes"])
+    total_bytes = n * (kb + vb) * 2 * (1 + plan["hbm_passes"])
 
     del bufs
     torch.cuda.empty_cache()
@@ -345,7 +349,8 @@ def main():
         "dtype": "u32" if kb == 4 else "int64",
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "key_bytes": kb, "value_bytes": vb,
-                   "tile": plan["tile"], "merge_tile": plan["merge_tile"], "merge_passes": plan["passes"]},
+                   "tile": plan["tile"], "merge_tile": plan["merge_tile"], "merge4_tile": plan["merge4_tile"],
+                   "merge_levels": plan["passes"], "hbm_merge_passes": plan["hbm_passes"]},
         "whole_sort_hbm_GBs": round(total_bytes / (ms_per_step * 1e-3) / 1e9, 1),
         "kernels": kernels,
         "roofline": roofline,

@@ -255,13 +255,16 @@ size_t ms_temp_bytes(size_t n, ms_key_type kt, size_t val_bytes);
 
 /*
  * ms_plan_query -- the plan ms_sort / ms_sort_pairs would use for n keys:
- * tile size, merge tile size, number of merge passes, and whether the tile
- * sort writes the caller's buffer (1) or the scratch buffer (0) so that the
- * last pass lands in the caller's buffer.  Host arithmetic only; any output
- * pointer may be NULL.
+ * tile size; two-run merge tile size; number of merge-tree levels after the
+ * tile sort (ceil(log2(ceil(n / tile)))); whether the tile sort writes the
+ * caller's buffer (1) or the scratch buffer (0) so that the last pass lands
+ * in the caller's buffer; the number of HBM merge passes (pairs of levels
+ * run as one fused four-run pass, an odd level count adds one two-run pass);
+ * and the fused pass's merge tile (0 when passes are not fused).  Host
+ * arithmetic only; any output pointer may be NULL.
  */
 ms_status ms_plan_query(size_t n, ms_key_type kt, size_t val_bytes, int* tile, int* merge_tile,
-                        int* passes, int* tile_sort_in_place);
+                        int* passes, int* tile_sort_in_place, int* hbm_passes, int* merge4_tile);
 
 /* Free the library's scratch buffers and cached segmented-sort graphs of the
  * current device (all streams).  Synchronises the device first. */
@@ -274,7 +277,7 @@ ms_status ms_release_workspace(void);
  * kernel class `kernel` (0 tile sort, 1 partition, 2 merge, 3 segment
  * classify, 4 small-segment sort, 5 large-segment passes, 6 MLP training,
  * 7 learned histograms, 8 learned scatters, 9 bucket sort, 10 other learned
- * kernels), the number of launches and their summed duration in
+ * kernels, 11 four-way partition, 12 fused four-run merge), the number of launches and their summed duration in
  * milliseconds since the last ms_profile_reset().
  */
 ms_status ms_profile_enable(int on);

@@ -25,7 +25,8 @@ KEY_TYPES = {torch.uint32: MS_KEY_U32, torch.int32: MS_KEY_I32,
 
 PROFILE_KERNELS = {"tile_sort": 0, "partition": 1, "merge": 2, "seg_classify": 3,
                    "seg_small": 4, "seg_large": 5, "mlp_train": 6, "learned_hist": 7,
-                   "learned_scatter": 8, "bucket_sort": 9, "learned_other": 10}
+                   "learned_scatter": 8, "bucket_sort": 9, "learned_other": 10,
+                   "partition4": 11, "merge4": 12}
 
 MS_ALGO_AUTO, MS_ALGO_MERGE_PATH, MS_ALGO_LEARNED_BUCKET = 0, 1, 2
 MS_FEATURE_LOG, MS_FEATURE_LINEAR = 0, 1
@@ -70,7 +71,7 @@ def _declare(lib):
         "ms_sort_pairs": (i32, [vp, vp, sz, i32, sz, vp]),
         "ms_temp_bytes": (sz, [sz, i32, sz]),
         "ms_plan_query": (i32, [sz, i32, sz, c.POINTER(i32), c.POINTER(i32), c.POINTER(i32),
-                                c.POINTER(i32)]),
+                                c.POINTER(i32), c.POINTER(i32), c.POINTER(i32)]),
         "ms_release_workspace": (i32, []),
         "ms_segmented_sort": (i32, [vp, vp, vp, sz, sz, sz, i32, sz, vp]),
         "ms_seg_num_classes": (i32, [i32, sz, c.POINTER(i32)]),
@@ -331,11 +332,12 @@ def ms_temp_bytes(n: int, key_type: int, val_bytes: int = 0) -> int:
 
 
 def ms_plan_query(n: int, key_type: int, val_bytes: int = 0) -> dict:
-    t, mt, p, ip = (ctypes.c_int() for _ in range(4))
+    t, mt, p, ip, h, mt4 = (ctypes.c_int() for _ in range(6))
     _check(lib().ms_plan_query(n, key_type, val_bytes, ctypes.byref(t), ctypes.byref(mt),
-                               ctypes.byref(p), ctypes.byref(ip)), "ms_plan_query")
+                               ctypes.byref(p), ctypes.byref(ip), ctypes.byref(h), ctypes.byref(mt4)),
+           "ms_plan_query")
     return {"tile": t.value, "merge_tile": mt.value, "passes": p.value,
-            "tile_sort_in_place": bool(ip.value)}
+            "tile_sort_in_place": bool(ip.value), "hbm_passes": h.value, "merge4_tile": mt4.value}
 
 
 def ms_release_workspace():

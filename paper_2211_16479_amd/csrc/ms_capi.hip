@@ -393,22 +393,25 @@ size_t ms_temp_bytes(size_t n, ms_key_type kt, size_t val_bytes) {
 }
 
 ms_status ms_plan_query(size_t n, ms_key_type kt, size_t val_bytes, int* tile, int* merge_tile, int* passes,
-                        int* in_place) {
-  int t = 0, mt = 0;
+                        int* in_place, int* hbm_passes, int* merge4_tile) {
+  int t = 0, mt = 0, mt4 = 0, fused = 0;
   ms_status st = with_key_type(kt, [&](auto kz) -> ms_status {
     using K = decltype(kz);
     return with_val_type(val_bytes, [&](auto vz) -> ms_status {
       using V = decltype(vz);
-      plain_geometry<K, V>(&t, &mt);
+      plain_geometry<K, V>(&t, &mt, &mt4, &fused);
       return MS_OK;
     });
   });
   if (st != MS_OK) return st;
   const int p = plan_passes(n, uint64_t(t));
+  const int h = plan_hbm_passes(p, fused != 0);
   if (tile) *tile = t;
   if (merge_tile) *merge_tile = mt;
   if (passes) *passes = p;
-  if (in_place) *in_place = tile_sort_in_place(p) ? 1 : 0;
+  if (in_place) *in_place = tile_sort_in_place(h) ? 1 : 0;
+  if (hbm_passes) *hbm_passes = h;
+  if (merge4_tile) *merge4_tile = fused ? mt4 : 0;
   return MS_OK;
 }
 

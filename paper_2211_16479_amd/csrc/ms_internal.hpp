@@ -24,7 +24,9 @@ enum ProfKernel {
   PK_LEARN_SCATTER = 8,
   PK_LEARN_BUCKET = 9,
   PK_LEARN_OTHER = 10,
-  PK_COUNT = 11
+  PK_PARTITION4 = 11,
+  PK_MERGE4 = 12,
+  PK_COUNT = 13
 };
 
 // Records a start/stop event pair around a launch when profiling is on.
@@ -52,7 +54,7 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
 template <class K, class V>
 size_t plain_temp_bytes(uint64_t n);
 template <class K, class V>
-void plain_geometry(int* tile, int* merge_tile);
+void plain_geometry(int* tile, int* merge_tile, int* merge4_tile, int* fused);
 // One merge of src[0, split) with src[split, n) into dst (split on the device),
 // as the plain sort's partition + merge kernels; part needs ceil(n/merge tile).
 template <class K, class V>

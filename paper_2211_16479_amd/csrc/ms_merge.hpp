@@ -267,4 +267,370 @@ __global__ __launch_bounds__(WG) void merge_kernel(const K* __restrict__ src_k, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fused two-level passes.
+//
+// Two adjacent levels of the merge tree in one HBM round trip: runs R0..R3 of
+// width W (a "quad", clipped to n) become one run of width 4W, computed as
+// merge(X, Y) with X = merge(R0, R1) and Y = merge(R2, R3) -- the same two
+// tree levels as two passes, so the output is bit-identical (left wins ties
+// at both levels), but every element is read and written once instead of
+// twice.  A fused pass is three kernels:
+//   1. partition_kernel at width W: for every merge tile, the split of its
+//      pair at that diagonal (samples of X and Y every Tm outputs);
+//   2. partition4_kernel: for every output tile start d of merge(X, Y), the
+//      split x of the output between X and Y (a search whose probes need
+//      X[m] and Y[p]; each is one bounded search between two samples), and
+//      from it the start offsets in R0..R3;
+//   3. merge4_kernel: stages the four pieces in LDS, merges R0|R1 and R2|R3
+//      in LDS, then the two results, and stores coalesced.
+// The partition costs several times a two-run partition, so fused passes
+// pay where elements carry values (the merge moves more bytes per key).
+
+struct QuadGeom {
+  uint64_t qb, r1, r2, r3, end;  // starts of R0..R3 and the quad's end
+};
+
+__device__ __forceinline__ QuadGeom quad_geom(uint64_t g, uint64_t n, uint64_t W) {
+  QuadGeom q;
+  q.qb = (g / (4 * W)) * (4 * W);
+  q.r1 = q.qb + W < n ? q.qb + W : n;
+  q.r2 = q.qb + 2 * W < n ? q.qb + 2 * W : n;
+  q.r3 = q.qb + 3 * W < n ? q.qb + 3 * W : n;
+  q.end = q.qb + 4 * W < n ? q.qb + 4 * W : n;
+  return q;
+}
+
+// Merge-path split at diagonal d of merge(P, Q), P = src[p0, p0 + lp),
+// Q = src[q0, q0 + lq): how many of the first d outputs come from P.  p0 is
+// a multiple of Tm and part[(p0 + j*Tm) / Tm] - p0 is the split at diagonal
+// j*Tm (from partition_kernel), so the search only spans the interval the
+// two neighbouring samples leave: split(d0) <= split(d) <= split(d0) + d - d0
+// and split(d1) - (d1 - d) <= split(d) <= split(d1).
+template <class K>
+__device__ __forceinline__ uint64_t split_bounded(const K* __restrict__ src, uint64_t p0, uint64_t lp, uint64_t q0,
+                                                  uint64_t lq, const int64_t* __restrict__ part, uint32_t Tm,
+                                                  uint64_t d) {
+  uint64_t lo = d > lq ? d - lq : 0, hi = d < lp ? d : lp;
+  const uint64_t L = lp + lq;
+  const uint64_t d0 = (d / Tm) * Tm;
+  if (d0 < L) {
+    const uint64_t s0 = uint64_t(part[(p0 + d0) / Tm]) - p0;
+    lo = s0 > lo ? s0 : lo;
+    hi = s0 + (d - d0) < hi ? s0 + (d - d0) : hi;
+  }
+  const uint64_t d1 = d0 + Tm;
+  if (d1 < L) {
+    const uint64_t s1 = uint64_t(part[(p0 + d1) / Tm]) - p0;
+    hi = s1 < hi ? s1 : hi;
+    const uint64_t b = s1 > d1 - d ? s1 - (d1 - d) : 0;
+    lo = b > lo ? b : lo;
+  }
+  while (lo < hi) {
+    const uint64_t m = (lo + hi) >> 1;
+    if (src[q0 + d - 1 - m] < src[p0 + m]) hi = m; else lo = m + 1;
+  }
+  return lo;
+}
+
+// G lanes (an aligned group of one wavefront) find the first index in
+// [lo, hi) at which a monotone predicate (false ... false true ... true)
+// holds, or hi.  Each round the group probes G points spread over the
+// interval, and a ballot keeps the piece between the last false and the
+// first true probe, so the interval shrinks by a factor G + 1 per round.
+// Every lane of the wavefront must call it (the ballot); lanes with
+// valid == false only take part in the ballots.
+template <int G, class Pred>
+__device__ __forceinline__ uint64_t group_search(uint64_t lo, uint64_t hi, bool valid, Pred pred) {
+  const uint32_t q = __lane_id() % G;
+  const uint32_t gshift = (__lane_id() / G) * G;
+  const uint64_t gmask = (G == 64) ? ~0ull : ((1ull << G) - 1);
+  if (!valid) lo = hi = 0;
+  while (true) {
+    const bool active = lo < hi;
+    if (!__any(active)) break;
+    const uint64_t len = hi - lo;
+    const bool small = len <= uint64_t(G);
+    const uint64_t m = small ? lo + q : lo + ((q + 1) * len) / (G + 1);
+    const bool probe = active && (!small || q < len);
+    const bool p = probe && pred(m);
+    const uint64_t gm = (__ballot(p) >> gshift) & gmask;
+    if (active) {
+      if (small) {
+        lo = hi = lo + (gm ? uint64_t(__builtin_ctzll(gm)) : len);
+      } else if (gm == 0) {
+        lo = lo + (uint64_t(G) * len) / (G + 1) + 1;
+      } else {
+        const uint32_t f = __builtin_ctzll(gm);
+        hi = lo + ((f + 1) * len) / (G + 1);
+        lo = f ? lo + (uint64_t(f) * len) / (G + 1) + 1 : lo;
+      }
+    }
+  }
+  return lo;
+}
+
+// For every output tile k (start g = k*Tm < n) of the fused pass at width
+// W: the start offsets of its pieces of R0..R3, written as four global
+// indices to part4[4k .. 4k+3].  G lanes per tile.
+template <class K, int G>
+__global__ __launch_bounds__(256) void partition4_kernel(const K* __restrict__ src, uint64_t n_host, DevCtl ctl,
+                                                         uint64_t W, uint32_t Tm, uint64_t num_tiles,
+                                                         const int64_t* __restrict__ part,
+                                                         int64_t* __restrict__ part4) {
+  static_assert(G >= 1 && G <= 64 && (64 % G) == 0, "group size");
+  if (gated_off(ctl)) return;
+  const uint64_t n = live_n(ctl, n_host);
+  constexpr uint32_t PER_WG = 256 / G;
+  const uint32_t q = threadIdx.x % G;
+  for (uint64_t kb = uint64_t(blockIdx.x) * PER_WG; kb < num_tiles; kb += uint64_t(gridDim.x) * PER_WG) {
+    const uint64_t k = kb + threadIdx.x / G;
+    const bool valid = k < num_tiles && k * Tm < n;
+    const QuadGeom Q = quad_geom(valid ? k * Tm : 0, n, W);
+    const uint64_t la = Q.r1 - Q.qb, lb = Q.r2 - Q.r1, lc = Q.r3 - Q.r2, ld = Q.end - Q.r3;
+    const uint64_t lx = la + lb, ly = lc + ld;
+    const uint64_t dl = valid ? k * Tm - Q.qb : 0;
+    // first m with Y[dl-1-m] < X[m]; X[m] is the smaller head after the
+    // split at m, Y[p-1] the larger tail before the split at p
+    auto pred = [&](uint64_t m) -> bool {
+      const uint64_t s = split_bounded(src, Q.qb, la, Q.r1, lb, part, Tm, m);
+      const bool xa = s < la, xb = m - s < lb;
+      const K ka = src[xa ? Q.qb + s : Q.r1 + (m - s)];
+      const K kb2 = src[xb ? Q.r1 + (m - s) : Q.qb + s];
+      const K xk = kb2 < ka ? kb2 : ka;
+      const uint64_t p = dl - m;
+      const uint64_t t = split_bounded(src, Q.r2, lc, Q.r3, ld, part, Tm, p);
+      const bool yc = t >= 1, yd = p - t >= 1;
+      const K kc = src[yc ? Q.r2 + t - 1 : Q.r3 + (p - t) - 1];
+      const K kd = src[yd ? Q.r3 + (p - t) - 1 : Q.r2 + t - 1];
+      const K yk = kc < kd ? kd : kc;
+      return yk < xk;
+    };
+    const uint64_t lo = dl > ly ? dl - ly : 0, hi = dl < lx ? dl : lx;
+    // coarse: probes on sample diagonals j*Tm only (no inner search)
+    const uint64_t jlo = (lo + Tm - 1) / Tm, jhi = (hi + Tm - 1) / Tm;
+    const uint64_t jf = group_search<G>(jlo, jhi, valid, [&](uint64_t j) { return pred(j * Tm); });
+    const uint64_t wlo = jf > jlo ? (jf - 1) * Tm + 1 : lo;
+    const uint64_t whi = jf < jhi ? jf * Tm : hi;
+    // fine: inside one sample interval
+    const uint64_t x = group_search<G>(wlo, whi, valid, pred);
+    // the two final splits: lanes 0 and 1 of the group, or lane 0 alone
+    if (valid && q == 0) {
+      const uint64_t a = split_bounded(src, Q.qb, la, Q.r1, lb, part, Tm, x);
+      part4[4 * k + 0] = int64_t(Q.qb + a);
+      part4[4 * k + 1] = int64_t(Q.r1 + (x - a));
+    }
+    if (valid && q == (G == 1 ? 0u : 1u)) {
+      const uint64_t c = split_bounded(src, Q.r2, lc, Q.r3, ld, part, Tm, dl - x);
+      part4[4 * k + 2] = int64_t(Q.r2 + c);
+      part4[4 * k + 3] = int64_t(Q.r3 + (dl - x - c));
+    }
+  }
+}
+
+// One output tile of a fused pass: pieces P0..P3 of R0..R3 (total <= TM)
+// merged as merge(merge(P0, P1), merge(P2, P3)) in LDS.
+//   stage 0: coalesced load of P0|P1|P2|P3 into buffer 1;
+//   stage 1: each thread produces IPT consecutive positions of
+//            [merge(P0, P1) | merge(P2, P3)] into buffer 2 (a thread whose
+//            positions straddle the boundary restarts on the second merge);
+//            for pairs, buffer 2 also records where each key sits in
+//            buffer 1;
+//   stage 2: the two halves of buffer 2 merged as in MergeTile, stored to
+//            HBM (values fetched from buffer 1 through the recorded index).
+template <class K, class V, int WG, int IPT, int PAD>
+struct Merge4Tile {
+  static constexpr bool PAIRS = HasVal<V>::value;
+  using VV = typename std::conditional<PAIRS, V, int>::type;
+  static constexpr int TM = WG * IPT;
+  static_assert(TM <= 65536, "buffer-1 positions are 16-bit");
+  static constexpr uint32_t SLOTS = lds_padded_size<PAD>(TM);
+  static constexpr size_t al16(size_t b) { return (b + 15) / 16 * 16; }
+  static constexpr size_t K1_OFF = 0;
+  static constexpr size_t V1_OFF = al16(sizeof(K) * SLOTS);
+  static constexpr size_t K2_OFF = V1_OFF + (PAIRS ? al16(sizeof(VV) * SLOTS) : 0);
+  static constexpr size_t I2_OFF = K2_OFF + al16(sizeof(K) * SLOTS);
+  static constexpr size_t LDS_BYTES = I2_OFF + (PAIRS ? al16(sizeof(uint16_t) * SLOTS) : 0);
+
+  static __device__ __forceinline__ void run(const K* __restrict__ src_k, const VV* __restrict__ src_v,
+                                             K* __restrict__ dst_k, VV* __restrict__ dst_v, const uint64_t (&s)[4],
+                                             const uint32_t (&l)[4], uint64_t o0, unsigned char* smem) {
+    const uint32_t tid = threadIdx.x;
+    K* k1 = reinterpret_cast<K*>(smem + K1_OFF);
+    VV* v1 = reinterpret_cast<VV*>(smem + V1_OFF);
+    K* k2 = reinterpret_cast<K*>(smem + K2_OFF);
+    uint16_t* i2 = reinterpret_cast<uint16_t*>(smem + I2_OFF);
+    const uint32_t c1 = l[0], c2 = c1 + l[1], c3 = c2 + l[2], total = c3 + l[3];
+    // stage 0
+    {
+      K kv[IPT];
+      VV vv[PAIRS ? IPT : 1];
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const uint32_t e = tid + uint32_t(r) * WG;
+        if (e < total) {
+          const uint64_t g = e < c1 ? s[0] + e : e < c2 ? s[1] + (e - c1) : e < c3 ? s[2] + (e - c2) : s[3] + (e - c3);
+          kv[r] = src_k[g];
+          if constexpr (PAIRS) vv[r] = src_v[g];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const uint32_t e = tid + uint32_t(r) * WG;
+        if (e < total) {
+          k1[lds_pad<PAD>(e)] = kv[r];
+          if constexpr (PAIRS) v1[lds_pad<PAD>(e)] = vv[r];
+        }
+      }
+    }
+    __syncthreads();
+    const uint32_t e0 = tid * IPT;
+    const uint32_t last = total ? total - 1 : 0;
+    // stage 1
+    if (e0 < total) {
+      // merge state: P = k1[pb, pb + lp), Q = k1[pb + lp, pb + lp + lq)
+      const bool second = e0 >= c2;
+      const uint32_t pb = second ? c2 : 0u;
+      const uint32_t lp = second ? l[2] : l[0];
+      const uint32_t lq = second ? l[3] : l[1];
+      const uint32_t d = e0 - pb;
+      uint32_t lo = d > lq ? d - lq : 0, hi = d < lp ? d : lp;
+      while (lo < hi) {
+        const uint32_t m = (lo + hi) >> 1;
+        if (k1[lds_pad<PAD>(pb + lp + d - 1 - m)] < k1[lds_pad<PAD>(pb + m)]) hi = m; else lo = m + 1;
+      }
+      uint32_t i = pb + lo, j = pb + lp + (d - lo);
+      uint32_t iend = pb + lp, jend = pb + lp + lq;
+      K a = k1[lds_pad<PAD>(i < last ? i : last)];
+      K b = k1[lds_pad<PAD>(j < last ? j : last)];
+      // position where the second merge starts inside this thread's range
+      const uint32_t sw = (!second && c2 > e0 && c2 < e0 + IPT) ? c2 - e0 : uint32_t(IPT);
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        if (uint32_t(r) == sw) {
+          i = c2;
+          iend = c3;
+          j = c3;
+          jend = total;
+          a = k1[lds_pad<PAD>(i < last ? i : last)];
+          b = k1[lds_pad<PAD>(j < last ? j : last)];
+        }
+        const uint32_t pos = e0 + uint32_t(r);
+        if (pos < total) {
+          const bool take_b = (j < jend) && (i >= iend || b < a);
+          const uint32_t src = take_b ? j : i;
+          k2[lds_pad<PAD>(pos)] = take_b ? b : a;
+          if constexpr (PAIRS) i2[lds_pad<PAD>(pos)] = uint16_t(src);
+          i += take_b ? 0u : 1u;
+          j += take_b ? 1u : 0u;
+          const uint32_t nx = take_b ? j : i;
+          const K x = k1[lds_pad<PAD>(nx < last ? nx : last)];
+          a = take_b ? a : x;
+          b = take_b ? x : b;
+        }
+      }
+    }
+    __syncthreads();
+    // stage 2: A = k2[0, c2), B = k2[c2, total)
+    if (e0 >= total) return;
+    const uint32_t la = c2, lb = total - c2, d = e0;
+    uint32_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
+    while (lo < hi) {
+      const uint32_t m = (lo + hi) >> 1;
+      if (k2[lds_pad<PAD>(la + d - 1 - m)] < k2[lds_pad<PAD>(m)]) hi = m; else lo = m + 1;
+    }
+    uint32_t i = lo, j = d - lo;
+    K a = k2[lds_pad<PAD>(i < last ? i : last)];
+    K b = k2[lds_pad<PAD>(la + j < last ? la + j : last)];
+    K ko[IPT];
+    uint32_t src_idx[IPT];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+      const bool take_b = (j < lb) && (i >= la || b < a);
+      ko[r] = take_b ? b : a;
+      src_idx[r] = take_b ? la + j : i;
+      i += take_b ? 0u : 1u;
+      j += take_b ? 1u : 0u;
+      const uint32_t nx = take_b ? la + j : i;
+      const K x = k2[lds_pad<PAD>(nx < last ? nx : last)];
+      a = take_b ? a : x;
+      b = take_b ? x : b;
+    }
+    const uint32_t cnt = total - d < uint32_t(IPT) ? total - d : uint32_t(IPT);
+    K* out = dst_k + o0 + d;
+    if (cnt == IPT && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+      store_run<K, IPT>(out, ko);
+    } else {
+#pragma unroll
+      for (int r = 0; r < IPT; ++r)
+        if (uint32_t(r) < cnt) out[r] = ko[r];
+    }
+    if constexpr (PAIRS) {
+      VV vo[IPT];
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const uint32_t p2 = src_idx[r] < last ? src_idx[r] : last;
+        vo[r] = v1[lds_pad<PAD>(uint32_t(i2[lds_pad<PAD>(p2)]))];
+      }
+      VV* ov = dst_v + o0 + d;
+      if (cnt == IPT && (reinterpret_cast<uintptr_t>(ov) & 15) == 0) {
+        store_run<VV, IPT>(ov, vo);
+      } else {
+#pragma unroll
+        for (int r = 0; r < IPT; ++r)
+          if (uint32_t(r) < cnt) ov[r] = vo[r];
+      }
+    }
+  }
+};
+
+// Workgroup b merges output tiles b, b + grid, ...; a tile ends at the next
+// tile's offsets or, for the quad's last tile, at the run ends.
+template <class K, class V, int WG, int IPT, int PAD>
+__global__ __launch_bounds__(WG) void merge4_kernel(const K* __restrict__ src_k, const V* __restrict__ src_v,
+                                                    K* __restrict__ dst_k, V* __restrict__ dst_v, uint64_t n_host,
+                                                    DevCtl ctl, uint64_t W, const int64_t* __restrict__ part4) {
+  using MT = Merge4Tile<K, V, WG, IPT, PAD>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (gated_off(ctl)) return;
+  const uint64_t n = live_n(ctl, n_host);
+  for (uint64_t k = blockIdx.x; k * MT::TM < n; k += gridDim.x) {
+    const uint64_t g0 = k * MT::TM;
+    const uint64_t g1 = g0 + MT::TM < n ? g0 + MT::TM : n;
+    const QuadGeom Q = quad_geom(g0, n, W);
+    uint64_t s[4], e[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) s[r] = uint64_t(part4[4 * k + r]);
+    if (g1 == Q.end) {
+      e[0] = Q.r1;
+      e[1] = Q.r2;
+      e[2] = Q.r3;
+      e[3] = Q.end;
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) e[r] = uint64_t(part4[4 * (k + 1) + r]);
+    }
+    // offsets that do not describe four in-run pieces filling the tile are
+    // never dereferenced (the tile is skipped); exact partitions always pass
+    const uint64_t rs[4] = {Q.qb, Q.r1, Q.r2, Q.r3}, re[4] = {Q.r1, Q.r2, Q.r3, Q.end};
+    bool ok = true;
+    uint64_t sum = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      ok = ok && rs[r] <= s[r] && s[r] <= e[r] && e[r] <= re[r];
+      sum += e[r] - s[r];
+    }
+    ok = ok && sum == g1 - g0;
+    uint32_t l[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) l[r] = ok ? uint32_t(e[r] - s[r]) : 0u;
+    if constexpr (MT::PAIRS) {
+      MT::run(src_k, src_v, dst_k, dst_v, s, l, g0, smem);
+    } else {
+      MT::run(src_k, nullptr, dst_k, nullptr, s, l, g0, smem);
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace ms

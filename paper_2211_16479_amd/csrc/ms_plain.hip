@@ -1,5 +1,6 @@
 // Plain merge sort launcher: tile sort, then merge-path passes with
-// ping-pong buffers (see ms_plan.hpp for the pass count and parity).
+// ping-pong buffers (see ms_plan.hpp for the pass count and parity); pairs
+// of tree levels run as one fused pass.
 #include <algorithm>
 #include <type_traits>
 
@@ -20,9 +21,11 @@ static hipError_t allow_lds(F* kernel, size_t bytes) {
 }
 
 template <class K, class V>
-void plain_geometry(int* tile, int* merge_tile) {
+void plain_geometry(int* tile, int* merge_tile, int* merge4_tile, int* fused) {
   *tile = PlainCfg<K, V>::TILE;
   *merge_tile = PlainCfg<K, V>::MTILE;
+  *merge4_tile = PlainCfg<K, V>::M4TILE;
+  *fused = PlainCfg<K, V>::FUSED ? 1 : 0;
 }
 
 template <class K, class V>
@@ -30,7 +33,7 @@ size_t plain_temp_bytes(uint64_t n) {
   using C = PlainCfg<K, V>;
   const int P = plan_passes(n, C::TILE);
   const size_t vb = C::PAIRS ? sizeof(typename std::conditional<C::PAIRS, V, int>::type) : 0;
-  return plain_layout(n, sizeof(K), vb, C::MTILE, P).bytes;
+  return plain_layout(n, sizeof(K), vb, C::MTILE, C::M4TILE, P, C::FUSED).bytes;
 }
 
 template <class K, class V>
@@ -38,22 +41,26 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
   using C = PlainCfg<K, V>;
   using BS = TileSort<K, V, C::BS_WG, C::BS_IPT, C::BS_PAD>;
   using MT = MergeTile<K, V, C::MG_WG, C::MG_IPT, C::MG_PAD>;
+  using M4 = Merge4Tile<K, V, C::M4_WG, C::M4_IPT, C::M4_PAD>;
   if (n == 0) return MS_OK;
   const int P = plan_passes(n, C::TILE);
+  const int H = plan_hbm_passes(P, C::FUSED);
   const size_t vb = C::PAIRS ? sizeof(typename std::conditional<C::PAIRS, V, int>::type) : 0;
-  const PlainLayout L = plain_layout(n, sizeof(K), vb, C::MTILE, P);
+  const PlainLayout L = plain_layout(n, sizeof(K), vb, C::MTILE, C::M4TILE, P, C::FUSED);
   char* w = static_cast<char*>(ws);
   K* tk = P ? reinterpret_cast<K*>(w + L.keys_off) : nullptr;
   V* tv = (P && C::PAIRS) ? reinterpret_cast<V*>(w + L.vals_off) : nullptr;
   int64_t* part = P ? reinterpret_cast<int64_t*>(w + L.part_off) : nullptr;
+  int64_t* part4 = P ? reinterpret_cast<int64_t*>(w + L.part4_off) : nullptr;
 
-  K* cur_k = tile_sort_in_place(P) ? keys : tk;
-  V* cur_v = tile_sort_in_place(P) ? vals : tv;
+  K* cur_k = tile_sort_in_place(H) ? keys : tk;
+  V* cur_v = tile_sort_in_place(H) ? vals : tv;
   const uint64_t tiles = ceil_div(n, C::TILE);
   static const hipError_t lds_ok = [] {
     hipError_t a = allow_lds(&block_sort_kernel<K, V, C::BS_WG, C::BS_IPT, C::BS_PAD>, BS::LDS_BYTES);
     hipError_t b = allow_lds(&merge_kernel<K, V, C::MG_WG, C::MG_IPT, C::MG_PAD>, MT::LDS_BYTES);
-    return a != hipSuccess ? a : b;
+    hipError_t c = allow_lds(&merge4_kernel<K, V, C::M4_WG, C::M4_IPT, C::M4_PAD>, M4::LDS_BYTES);
+    return a != hipSuccess ? a : (b != hipSuccess ? b : c);
   }();
   if (lds_ok != hipSuccess) return hip_fail(lds_ok, "LDS size attribute");
   const uint64_t cap = max_grid ? max_grid : ~uint64_t(0);
@@ -65,21 +72,46 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "tile sort launch");
-  const uint64_t mtiles = ceil_div(n, C::MTILE);
-  for (int p = 0; p < P; ++p) {
+  auto partition = [&](uint64_t W, uint32_t Tm) {
+    const uint64_t nt = ceil_div(n, Tm);
+    ProfScope ps(PK_PARTITION, s);
+    partition_kernel<K, MS_PART_G><<<dim3(unsigned(std::min(ceil_div(nt * MS_PART_G, 256), cap))), dim3(256), 0,
+                                     s>>>(cur_k, n, ctl, W, Tm, nt, part);
+  };
+  // levels p (width W = T * 2^p): an odd level count starts with one two-run
+  // pass, then every fused pass takes two levels
+  int p = 0;
+  while (p < P) {
     const uint64_t W = uint64_t(C::TILE) << p;
     K* nxt_k = (cur_k == keys) ? tk : keys;
     V* nxt_v = (cur_k == keys) ? tv : vals;
-    {
-      ProfScope ps(PK_PARTITION, s);
-      partition_kernel<K, MS_PART_G><<<dim3(unsigned(std::min(ceil_div(mtiles * MS_PART_G, 256), cap))), dim3(256), 0,
-                                       s>>>(cur_k, n, ctl, W, C::MTILE, mtiles, part);
-    }
-    {
-      ProfScope ps(PK_MERGE, s);
-      merge_kernel<K, V, C::MG_WG, C::MG_IPT, C::MG_PAD>
-          <<<dim3(unsigned(std::min(mtiles, cap))), dim3(C::MG_WG), MT::LDS_BYTES, s>>>(cur_k, cur_v, nxt_k, nxt_v, n,
-                                                                                     ctl, W, part);
+    const bool fuse = C::FUSED && (P - p) % 2 == 0;
+    if (fuse) {
+      const uint64_t mt4 = ceil_div(n, C::M4TILE);
+      partition(W, C::M4TILE);
+      {
+        ProfScope ps(PK_PARTITION4, s);
+        constexpr int PER_WG = 256 / MS_PART4_G;
+        partition4_kernel<K, MS_PART4_G><<<dim3(unsigned(std::min(ceil_div(mt4, PER_WG), cap))), dim3(256), 0, s>>>(
+            cur_k, n, ctl, W, C::M4TILE, mt4, part, part4);
+      }
+      {
+        ProfScope ps(PK_MERGE4, s);
+        merge4_kernel<K, V, C::M4_WG, C::M4_IPT, C::M4_PAD>
+            <<<dim3(unsigned(std::min(mt4, cap))), dim3(C::M4_WG), M4::LDS_BYTES, s>>>(cur_k, cur_v, nxt_k, nxt_v, n,
+                                                                                     ctl, W, part4);
+      }
+      p += 2;
+    } else {
+      const uint64_t mtiles = ceil_div(n, C::MTILE);
+      partition(W, C::MTILE);
+      {
+        ProfScope ps(PK_MERGE, s);
+        merge_kernel<K, V, C::MG_WG, C::MG_IPT, C::MG_PAD>
+            <<<dim3(unsigned(std::min(mtiles, cap))), dim3(C::MG_WG), MT::LDS_BYTES, s>>>(cur_k, cur_v, nxt_k, nxt_v,
+                                                                                       n, ctl, W, part);
+      }
+      p += 1;
     }
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "merge pass launch");
@@ -112,7 +144,7 @@ template ms_status merge_two_runs<uint32_t, NoVal>(const uint32_t*, uint32_t*, u
 #define MS_INSTANTIATE(K, V)                                                                  \
   template ms_status plain_sort<K, V>(K*, V*, uint64_t, DevCtl, hipStream_t, void*, uint64_t); \
   template size_t plain_temp_bytes<K, V>(uint64_t);                                           \
-  template void plain_geometry<K, V>(int*, int*);
+  template void plain_geometry<K, V>(int*, int*, int*, int*);
 
 MS_INSTANTIATE(uint32_t, NoVal)
 MS_INSTANTIATE(int32_t, NoVal)

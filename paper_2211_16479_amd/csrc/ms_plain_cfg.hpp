@@ -66,6 +66,40 @@ namespace ms {
 #ifndef MS_PAD_W
 #define MS_PAD_W 5
 #endif
+// Fused two-level merge passes (four runs in, one out) and their shapes.
+// MS_FUSED: 0 never, 1 for sorts with values (default), 2 always.  The
+// four-way partition costs several two-run partitions, which the saved HBM
+// round trip repays only when the merge moves values too.
+#ifndef MS_FUSED
+#define MS_FUSED 1
+#endif
+#ifndef MS_PART4_G
+#define MS_PART4_G 2  // lanes per four-way partition search
+#endif
+#ifndef MS_M4_WG_K
+#define MS_M4_WG_K 256
+#endif
+#ifndef MS_M4_IPT_K
+#define MS_M4_IPT_K 8
+#endif
+#ifndef MS_M4_PAD_K
+#define MS_M4_PAD_K 0
+#endif
+#ifndef MS_M4_WG_P
+#define MS_M4_WG_P 256
+#endif
+#ifndef MS_M4_IPT_P
+#define MS_M4_IPT_P 8
+#endif
+#ifndef MS_M4_PAD_P
+#define MS_M4_PAD_P 5
+#endif
+#ifndef MS_M4_WG_W
+#define MS_M4_WG_W 256
+#endif
+#ifndef MS_M4_IPT_W
+#define MS_M4_IPT_W 8
+#endif
 template <class K, class V>
 struct PlainCfg {
   static constexpr bool PAIRS = HasVal<V>::value;
@@ -76,9 +110,15 @@ struct PlainCfg {
   static constexpr int MG_WG = WIDE ? MS_MG_WG_W : (PAIRS ? MS_MG_WG_P : MS_MG_WG_K);
   static constexpr int MG_IPT = WIDE ? MS_MG_IPT_W : (PAIRS ? MS_MG_IPT_P : MS_MG_IPT_K);
   static constexpr int MG_PAD = WIDE ? MS_PAD_W : (PAIRS ? MS_MG_PAD_P : MS_MG_PAD_K);
+  static constexpr int M4_WG = WIDE ? MS_M4_WG_W : (PAIRS ? MS_M4_WG_P : MS_M4_WG_K);
+  static constexpr int M4_IPT = WIDE ? MS_M4_IPT_W : (PAIRS ? MS_M4_IPT_P : MS_M4_IPT_K);
+  static constexpr int M4_PAD = WIDE ? MS_PAD_W : (PAIRS ? MS_M4_PAD_P : MS_M4_PAD_K);
+  static constexpr bool FUSED = MS_FUSED == 2 || (MS_FUSED == 1 && PAIRS);
   static constexpr int TILE = BS_WG * BS_IPT;
   static constexpr int MTILE = MG_WG * MG_IPT;
+  static constexpr int M4TILE = M4_WG * M4_IPT;
   static_assert((2 * TILE) % MTILE == 0, "a merge tile must never straddle two run pairs");
+  static_assert((2 * TILE) % M4TILE == 0, "second-pair samples must sit on merge-tile starts");
 };
 
 }  // namespace ms

@@ -66,7 +66,13 @@ def test_plan_arithmetic(kt, vb):
         assert T & (T - 1) == 0 and (2 * T) % p["merge_tile"] == 0
         runs = max(1, math.ceil(n / T))
         assert p["passes"] == math.ceil(math.log2(runs))
-        assert p["tile_sort_in_place"] == (p["passes"] % 2 == 0)
+        if p["merge4_tile"]:
+            # pairs of levels fused into one four-run pass
+            assert (4 * T) % p["merge4_tile"] == 0 and (2 * T) % p["merge4_tile"] == 0
+            assert p["hbm_passes"] == p["passes"] // 2 + p["passes"] % 2
+        else:
+            assert p["hbm_passes"] == p["passes"]
+        assert p["tile_sort_in_place"] == (p["hbm_passes"] % 2 == 0)
         tb = msort.ms_temp_bytes(n, kt, vb)
         if p["passes"] == 0:
             assert tb == 0
