@@ -62,10 +62,16 @@ __device__ __forceinline__ uint64_t merge_path_split(const K* A, uint64_t la, co
 // sub-interval holding the split, so the interval shrinks by G + 1 per round
 // (fewer dependent global loads).  Both use the same predicate:
 // split <= m  iff  B[d-1-m] < A[m].
+//
+// With head/tail non-null (G == 1), the kernel also records the keys around
+// each split: head[k] = the pair's merged output at diagonal d (the smaller
+// of the two next elements), tail[k] = the output just before it (the larger
+// of the two last taken; undefined at d = 0).
 template <class K, int G>
 __global__ __launch_bounds__(256) void partition_kernel(const K* __restrict__ src, uint64_t n_host, DevCtl ctl,
                                                         uint64_t W, uint32_t Tm, uint64_t num_tiles,
-                                                        int64_t* __restrict__ part) {
+                                                        int64_t* __restrict__ part, K* __restrict__ head = nullptr,
+                                                        K* __restrict__ tail = nullptr) {
   static_assert(G >= 1 && G <= 64 && (64 % G) == 0, "group size");
   if (gated_off(ctl)) return;
   const uint64_t n = live_n(ctl, n_host);
@@ -76,8 +82,23 @@ __global__ __launch_bounds__(256) void partition_kernel(const K* __restrict__ sr
       const uint64_t g = kk * Tm;
       if (g >= n) return;
       const PassGeom q = pass_geom(g, n, W, ctl);
-      const uint64_t i = merge_path_split(src + q.pb, q.a_end - q.pb, src + q.a_end, q.b_end - q.a_end, g - q.pb);
+      const uint64_t la = q.a_end - q.pb, lb = q.b_end - q.a_end, d = g - q.pb;
+      const uint64_t i = merge_path_split(src + q.pb, la, src + q.a_end, lb, d);
       part[kk] = int64_t(q.pb + i);
+      if (head) {
+        // d < la + lb, so at least one next element exists; the index
+        // fallbacks below only ever name an existing element
+        const bool na = i < la, nb = d - i < lb;
+        const K x0 = src[na ? q.pb + i : q.a_end + (d - i)];
+        const K x1 = src[nb ? q.a_end + (d - i) : q.pb + i];
+        head[kk] = x1 < x0 ? x1 : x0;
+        const bool pa = i >= 1, pbv = d - i >= 1;
+        if (pa || pbv) {
+          const K y0 = src[pa ? q.pb + i - 1 : q.a_end + (d - i) - 1];
+          const K y1 = src[pbv ? q.a_end + (d - i) - 1 : q.pb + i - 1];
+          tail[kk] = y0 < y1 ? y1 : y0;
+        }
+      }
     }
   } else {
     const uint32_t q = uint32_t(gid % G);
@@ -280,12 +301,10 @@ __global__ __launch_bounds__(WG) void merge_kernel(const K* __restrict__ src_k, 
 //      pair at that diagonal (samples of X and Y every Tm outputs);
 //   2. partition4_kernel: for every output tile start d of merge(X, Y), the
 //      split x of the output between X and Y (a search whose probes need
-//      X[m] and Y[p]; each is one bounded search between two samples), and
-//      from it the start offsets in R0..R3;
+//      X[m] and Y[p]: O(1) at the samples, one bounded search each in
+//      between), and from it the start offsets in R0..R3;
 //   3. merge4_kernel: stages the four pieces in LDS, merges R0|R1 and R2|R3
 //      in LDS, then the two results, and stores coalesced.
-// The partition costs several times a two-run partition, so fused passes
-// pay where elements carry values (the merge moves more bytes per key).
 
 struct QuadGeom {
   uint64_t qb, r1, r2, r3, end;  // starts of R0..R3 and the quad's end
@@ -301,31 +320,12 @@ __device__ __forceinline__ QuadGeom quad_geom(uint64_t g, uint64_t n, uint64_t W
   return q;
 }
 
-// Merge-path split at diagonal d of merge(P, Q), P = src[p0, p0 + lp),
-// Q = src[q0, q0 + lq): how many of the first d outputs come from P.  p0 is
-// a multiple of Tm and part[(p0 + j*Tm) / Tm] - p0 is the split at diagonal
-// j*Tm (from partition_kernel), so the search only spans the interval the
-// two neighbouring samples leave: split(d0) <= split(d) <= split(d0) + d - d0
-// and split(d1) - (d1 - d) <= split(d) <= split(d1).
+// Merge-path split at diagonal d of merge(P, Q) (P = src[p0 ...),
+// Q = src[q0 ...), P wins ties), searched in [lo, hi], which the caller
+// knows to hold it.
 template <class K>
-__device__ __forceinline__ uint64_t split_bounded(const K* __restrict__ src, uint64_t p0, uint64_t lp, uint64_t q0,
-                                                  uint64_t lq, const int64_t* __restrict__ part, uint32_t Tm,
-                                                  uint64_t d) {
-  uint64_t lo = d > lq ? d - lq : 0, hi = d < lp ? d : lp;
-  const uint64_t L = lp + lq;
-  const uint64_t d0 = (d / Tm) * Tm;
-  if (d0 < L) {
-    const uint64_t s0 = uint64_t(part[(p0 + d0) / Tm]) - p0;
-    lo = s0 > lo ? s0 : lo;
-    hi = s0 + (d - d0) < hi ? s0 + (d - d0) : hi;
-  }
-  const uint64_t d1 = d0 + Tm;
-  if (d1 < L) {
-    const uint64_t s1 = uint64_t(part[(p0 + d1) / Tm]) - p0;
-    hi = s1 < hi ? s1 : hi;
-    const uint64_t b = s1 > d1 - d ? s1 - (d1 - d) : 0;
-    lo = b > lo ? b : lo;
-  }
+__device__ __forceinline__ uint64_t split_in(const K* __restrict__ src, uint64_t p0, uint64_t q0, uint64_t d,
+                                             uint64_t lo, uint64_t hi) {
   while (lo < hi) {
     const uint64_t m = (lo + hi) >> 1;
     if (src[q0 + d - 1 - m] < src[p0 + m]) hi = m; else lo = m + 1;
@@ -333,98 +333,128 @@ __device__ __forceinline__ uint64_t split_bounded(const K* __restrict__ src, uin
   return lo;
 }
 
-// G lanes (an aligned group of one wavefront) find the first index in
-// [lo, hi) at which a monotone predicate (false ... false true ... true)
-// holds, or hi.  Each round the group probes G points spread over the
-// interval, and a ballot keeps the piece between the last false and the
-// first true probe, so the interval shrinks by a factor G + 1 per round.
-// Every lane of the wavefront must call it (the ballot); lanes with
-// valid == false only take part in the ballots.
-template <int G, class Pred>
-__device__ __forceinline__ uint64_t group_search(uint64_t lo, uint64_t hi, bool valid, Pred pred) {
-  const uint32_t q = __lane_id() % G;
-  const uint32_t gshift = (__lane_id() / G) * G;
-  const uint64_t gmask = (G == 64) ? ~0ull : ((1ull << G) - 1);
-  if (!valid) lo = hi = 0;
-  while (true) {
-    const bool active = lo < hi;
-    if (!__any(active)) break;
-    const uint64_t len = hi - lo;
-    const bool small = len <= uint64_t(G);
-    const uint64_t m = small ? lo + q : lo + ((q + 1) * len) / (G + 1);
-    const bool probe = active && (!small || q < len);
-    const bool p = probe && pred(m);
-    const uint64_t gm = (__ballot(p) >> gshift) & gmask;
-    if (active) {
-      if (small) {
-        lo = hi = lo + (gm ? uint64_t(__builtin_ctzll(gm)) : len);
-      } else if (gm == 0) {
-        lo = lo + (uint64_t(G) * len) / (G + 1) + 1;
-      } else {
-        const uint32_t f = __builtin_ctzll(gm);
-        hi = lo + ((f + 1) * len) / (G + 1);
-        lo = f ? lo + (uint64_t(f) * len) / (G + 1) + 1 : lo;
-      }
-    }
+// A merge-path split f (f(d) = how many of the first d outputs come from the
+// first run) is non-decreasing and so is d - f(d).  Known exactly at dL <= d
+// <= dR, it is bounded at d by [max(fL, fR - (dR - d)), min(fR, fL + (d - dL))],
+// and always by [max(0, d - lq), min(d, lp)].
+struct Bracket {
+  uint64_t dL, fL, dR, fR;
+  __device__ __forceinline__ void bounds(uint64_t d, uint64_t lp, uint64_t lq, uint64_t* lo, uint64_t* hi) const {
+    uint64_t a = fR > dR - d ? fR - (dR - d) : 0;
+    a = a > fL ? a : fL;
+    const uint64_t g = d > lq ? d - lq : 0;
+    *lo = a > g ? a : g;
+    uint64_t b = fL + (d - dL);
+    b = b < fR ? b : fR;
+    *hi = b < d ? (b < lp ? b : lp) : (d < lp ? d : lp);
   }
-  return lo;
+};
+
+// Split of a pair at a diagonal that is a multiple of Tm (read from the
+// two-run partition) or the pair's full length.
+__device__ __forceinline__ uint64_t split_at_sample(const int64_t* __restrict__ part, uint64_t p0, uint64_t lp,
+                                                    uint64_t L, uint32_t Tm, uint64_t d) {
+  return d >= L ? lp : uint64_t(part[(p0 + d) / Tm]) - p0;
 }
 
 // For every output tile k (start g = k*Tm < n) of the fused pass at width
 // W: the start offsets of its pieces of R0..R3, written as four global
-// indices to part4[4k .. 4k+3].  G lanes per tile.
-template <class K, int G>
+// indices to part4[4k .. 4k+3].  One thread per tile.  x = the number of
+// X elements among the first dl outputs of merge(X, Y) is the first m with
+// Y[dl-1-m] < X[m] (X wins ties).
+//   coarse: a binary search over the sample diagonals m = j*Tm, where X[m]
+//           and Y[dl-m-1] are the recorded head and tail keys (one load
+//           each);
+//   fine:   a binary search inside the remaining sample interval; each
+//           probe finds the R0/R1 split at m and the R2/R3 split at dl - m
+//           by searches bounded by the exact splits at the current interval
+//           ends (brackets), which shrink with the interval.
+template <class K>
 __global__ __launch_bounds__(256) void partition4_kernel(const K* __restrict__ src, uint64_t n_host, DevCtl ctl,
                                                          uint64_t W, uint32_t Tm, uint64_t num_tiles,
                                                          const int64_t* __restrict__ part,
+                                                         const K* __restrict__ head, const K* __restrict__ tail,
                                                          int64_t* __restrict__ part4) {
-  static_assert(G >= 1 && G <= 64 && (64 % G) == 0, "group size");
   if (gated_off(ctl)) return;
   const uint64_t n = live_n(ctl, n_host);
-  constexpr uint32_t PER_WG = 256 / G;
-  const uint32_t q = threadIdx.x % G;
-  for (uint64_t kb = uint64_t(blockIdx.x) * PER_WG; kb < num_tiles; kb += uint64_t(gridDim.x) * PER_WG) {
-    const uint64_t k = kb + threadIdx.x / G;
-    const bool valid = k < num_tiles && k * Tm < n;
-    const QuadGeom Q = quad_geom(valid ? k * Tm : 0, n, W);
+  for (uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < num_tiles;
+       k += uint64_t(gridDim.x) * blockDim.x) {
+    if (k * Tm >= n) return;
+    const QuadGeom Q = quad_geom(k * Tm, n, W);
     const uint64_t la = Q.r1 - Q.qb, lb = Q.r2 - Q.r1, lc = Q.r3 - Q.r2, ld = Q.end - Q.r3;
     const uint64_t lx = la + lb, ly = lc + ld;
-    const uint64_t dl = valid ? k * Tm - Q.qb : 0;
-    // first m with Y[dl-1-m] < X[m]; X[m] is the smaller head after the
-    // split at m, Y[p-1] the larger tail before the split at p
-    auto pred = [&](uint64_t m) -> bool {
-      const uint64_t s = split_bounded(src, Q.qb, la, Q.r1, lb, part, Tm, m);
-      const bool xa = s < la, xb = m - s < lb;
-      const K ka = src[xa ? Q.qb + s : Q.r1 + (m - s)];
-      const K kb2 = src[xb ? Q.r1 + (m - s) : Q.qb + s];
-      const K xk = kb2 < ka ? kb2 : ka;
-      const uint64_t p = dl - m;
-      const uint64_t t = split_bounded(src, Q.r2, lc, Q.r3, ld, part, Tm, p);
-      const bool yc = t >= 1, yd = p - t >= 1;
-      const K kc = src[yc ? Q.r2 + t - 1 : Q.r3 + (p - t) - 1];
-      const K kd = src[yd ? Q.r3 + (p - t) - 1 : Q.r2 + t - 1];
+    const uint64_t dl = k * Tm - Q.qb;
+    uint64_t lo = dl > ly ? dl - ly : 0, hi = dl < lx ? dl : lx;
+    // coarse
+    {
+      uint64_t jlo = (lo + Tm - 1) / Tm, jhi = (hi + Tm - 1) / Tm;
+      const uint64_t j0 = jlo, j1 = jhi;
+      while (jlo < jhi) {
+        const uint64_t j = (jlo + jhi) >> 1;
+        const uint64_t m = j * Tm, p = dl - m;  // 1 <= p <= ly
+        const K xk = head[(Q.qb + m) / Tm];
+        K yk;
+        if (p < ly) {
+          yk = tail[(Q.r2 + p) / Tm];
+        } else {  // the last element of Y
+          const K c = src[lc ? Q.r3 - 1 : Q.end - 1];
+          const K e = src[ld ? Q.end - 1 : Q.r3 - 1];
+          yk = c < e ? e : c;
+        }
+        if (yk < xk) jhi = j; else jlo = j + 1;
+      }
+      const uint64_t wlo = jlo > j0 ? (jlo - 1) * Tm + 1 : lo;
+      const uint64_t whi = jlo < j1 ? jlo * Tm : hi;
+      lo = wlo;
+      hi = whi;
+    }
+    // fine: [lo, hi] lies inside [k0*Tm, k0*Tm + Tm]
+    const uint64_t mL = (lo / Tm) * Tm;
+    const uint64_t mR = mL + Tm < lx ? mL + Tm : lx;
+    Bracket bx{mL, split_at_sample(part, Q.qb, la, lx, Tm, mL), mR, split_at_sample(part, Q.qb, la, lx, Tm, mR)};
+    const uint64_t pR = dl - mL < ly ? dl - mL : ly;
+    const uint64_t pL = dl > mL + Tm ? dl - mL - Tm : 0;
+    Bracket by{pL, split_at_sample(part, Q.r2, lc, ly, Tm, pL), pR, split_at_sample(part, Q.r2, lc, ly, Tm, pR)};
+    while (lo < hi) {
+      const uint64_t m = (lo + hi) >> 1, p = dl - m;
+      uint64_t a0, a1, c0, c1;
+      bx.bounds(m, la, lb, &a0, &a1);
+      by.bounds(p, lc, ld, &c0, &c1);
+      const uint64_t sx = split_in(src, Q.qb, Q.r1, m, a0, a1);
+      const uint64_t ty = split_in(src, Q.r2, Q.r3, p, c0, c1);
+      // X[m]: the smaller next element; Y[p-1]: the larger last taken one
+      const bool xa = sx < la, xb = m - sx < lb;
+      const K ka = src[xa ? Q.qb + sx : Q.r1 + (m - sx)];
+      const K kb = src[xb ? Q.r1 + (m - sx) : Q.qb + sx];
+      const K xk = kb < ka ? kb : ka;
+      const bool yc = ty >= 1, yd = p - ty >= 1;
+      const K kc = src[yc ? Q.r2 + ty - 1 : Q.r3 + (p - ty) - 1];
+      const K kd = src[yd ? Q.r3 + (p - ty) - 1 : Q.r2 + ty - 1];
       const K yk = kc < kd ? kd : kc;
-      return yk < xk;
-    };
-    const uint64_t lo = dl > ly ? dl - ly : 0, hi = dl < lx ? dl : lx;
-    // coarse: probes on sample diagonals j*Tm only (no inner search)
-    const uint64_t jlo = (lo + Tm - 1) / Tm, jhi = (hi + Tm - 1) / Tm;
-    const uint64_t jf = group_search<G>(jlo, jhi, valid, [&](uint64_t j) { return pred(j * Tm); });
-    const uint64_t wlo = jf > jlo ? (jf - 1) * Tm + 1 : lo;
-    const uint64_t whi = jf < jhi ? jf * Tm : hi;
-    // fine: inside one sample interval
-    const uint64_t x = group_search<G>(wlo, whi, valid, pred);
-    // the two final splits: lanes 0 and 1 of the group, or lane 0 alone
-    if (valid && q == 0) {
-      const uint64_t a = split_bounded(src, Q.qb, la, Q.r1, lb, part, Tm, x);
-      part4[4 * k + 0] = int64_t(Q.qb + a);
-      part4[4 * k + 1] = int64_t(Q.r1 + (x - a));
+      if (yk < xk) {
+        hi = m;
+        bx.dR = m;
+        bx.fR = sx;
+        by.dL = p;
+        by.fL = ty;
+      } else {
+        lo = m + 1;
+        bx.dL = m;
+        bx.fL = sx;
+        by.dR = p;
+        by.fR = ty;
+      }
     }
-    if (valid && q == (G == 1 ? 0u : 1u)) {
-      const uint64_t c = split_bounded(src, Q.r2, lc, Q.r3, ld, part, Tm, dl - x);
-      part4[4 * k + 2] = int64_t(Q.r2 + c);
-      part4[4 * k + 3] = int64_t(Q.r3 + (dl - x - c));
-    }
+    const uint64_t x = lo;
+    uint64_t a0, a1, c0, c1;
+    bx.bounds(x, la, lb, &a0, &a1);
+    by.bounds(dl - x, lc, ld, &c0, &c1);
+    const uint64_t a = split_in(src, Q.qb, Q.r1, x, a0, a1);
+    const uint64_t c = split_in(src, Q.r2, Q.r3, dl - x, c0, c1);
+    part4[4 * k + 0] = int64_t(Q.qb + a);
+    part4[4 * k + 1] = int64_t(Q.r1 + (x - a));
+    part4[4 * k + 2] = int64_t(Q.r2 + c);
+    part4[4 * k + 3] = int64_t(Q.r3 + (dl - x - c));
   }
 }
 

@@ -52,6 +52,8 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
   V* tv = (P && C::PAIRS) ? reinterpret_cast<V*>(w + L.vals_off) : nullptr;
   int64_t* part = P ? reinterpret_cast<int64_t*>(w + L.part_off) : nullptr;
   int64_t* part4 = P ? reinterpret_cast<int64_t*>(w + L.part4_off) : nullptr;
+  K* head = P ? reinterpret_cast<K*>(w + L.head_off) : nullptr;
+  K* tail = P ? reinterpret_cast<K*>(w + L.tail_off) : nullptr;
 
   K* cur_k = tile_sort_in_place(H) ? keys : tk;
   V* cur_v = tile_sort_in_place(H) ? vals : tv;
@@ -78,6 +80,12 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
     partition_kernel<K, MS_PART_G><<<dim3(unsigned(std::min(ceil_div(nt * MS_PART_G, 256), cap))), dim3(256), 0,
                                      s>>>(cur_k, n, ctl, W, Tm, nt, part);
   };
+  auto partition_samples = [&](uint64_t W, uint32_t Tm) {  // splits plus head/tail keys
+    const uint64_t nt = ceil_div(n, Tm);
+    ProfScope ps(PK_PARTITION, s);
+    partition_kernel<K, 1><<<dim3(unsigned(std::min(ceil_div(nt, 256), cap))), dim3(256), 0, s>>>(
+        cur_k, n, ctl, W, Tm, nt, part, head, tail);
+  };
   // levels p (width W = T * 2^p): an odd level count starts with one two-run
   // pass, then every fused pass takes two levels
   int p = 0;
@@ -88,12 +96,11 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
     const bool fuse = C::FUSED && (P - p) % 2 == 0;
     if (fuse) {
       const uint64_t mt4 = ceil_div(n, C::M4TILE);
-      partition(W, C::M4TILE);
+      partition_samples(W, C::M4TILE);
       {
         ProfScope ps(PK_PARTITION4, s);
-        constexpr int PER_WG = 256 / MS_PART4_G;
-        partition4_kernel<K, MS_PART4_G><<<dim3(unsigned(std::min(ceil_div(mt4, PER_WG), cap))), dim3(256), 0, s>>>(
-            cur_k, n, ctl, W, C::M4TILE, mt4, part, part4);
+        partition4_kernel<K><<<dim3(unsigned(std::min(ceil_div(mt4, 256), cap))), dim3(256), 0, s>>>(
+            cur_k, n, ctl, W, C::M4TILE, mt4, part, head, tail, part4);
       }
       {
         ProfScope ps(PK_MERGE4, s);

@@ -67,14 +67,9 @@ namespace ms {
 #define MS_PAD_W 5
 #endif
 // Fused two-level merge passes (four runs in, one out) and their shapes.
-// MS_FUSED: 0 never, 1 for sorts with values (default), 2 always.  The
-// four-way partition costs several two-run partitions, which the saved HBM
-// round trip repays only when the merge moves values too.
+// MS_FUSED = 0 keeps one HBM pass per tree level.
 #ifndef MS_FUSED
 #define MS_FUSED 1
-#endif
-#ifndef MS_PART4_G
-#define MS_PART4_G 2  // lanes per four-way partition search
 #endif
 #ifndef MS_M4_WG_K
 #define MS_M4_WG_K 256
@@ -113,7 +108,7 @@ struct PlainCfg {
   static constexpr int M4_WG = WIDE ? MS_M4_WG_W : (PAIRS ? MS_M4_WG_P : MS_M4_WG_K);
   static constexpr int M4_IPT = WIDE ? MS_M4_IPT_W : (PAIRS ? MS_M4_IPT_P : MS_M4_IPT_K);
   static constexpr int M4_PAD = WIDE ? MS_PAD_W : (PAIRS ? MS_M4_PAD_P : MS_M4_PAD_K);
-  static constexpr bool FUSED = MS_FUSED == 2 || (MS_FUSED == 1 && PAIRS);
+  static constexpr bool FUSED = MS_FUSED != 0;
   static constexpr int TILE = BS_WG * BS_IPT;
   static constexpr int MTILE = MG_WG * MG_IPT;
   static constexpr int M4TILE = M4_WG * M4_IPT;

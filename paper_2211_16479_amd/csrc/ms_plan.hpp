@@ -30,9 +30,10 @@ inline int plan_hbm_passes(int levels, bool fused) { return fused ? levels / 2 +
 inline bool tile_sort_in_place(int hbm_passes) { return hbm_passes % 2 == 0; }
 
 // Scratch layout of one plain sort:
-// [keys n*kb | values n*vb | partitions | fused-pass tile offsets].
+// [keys n*kb | values n*vb | partitions | fused-pass tile offsets |
+//  fused-pass sample head keys | sample tail keys].
 struct PlainLayout {
-  size_t keys_off, vals_off, part_off, part4_off, bytes;
+  size_t keys_off, vals_off, part_off, part4_off, head_off, tail_off, bytes;
 };
 
 inline PlainLayout plain_layout(uint64_t n, size_t kb, size_t vb, uint64_t merge_tile, uint64_t merge4_tile,
@@ -40,13 +41,16 @@ inline PlainLayout plain_layout(uint64_t n, size_t kb, size_t vb, uint64_t merge
   PlainLayout L{};
   if (levels == 0) return L;
   const uint64_t tmin = merge_tile < merge4_tile ? merge_tile : merge4_tile;
+  const bool f = fused && levels >= 2;
+  const uint64_t t4 = ceil_div(n, merge4_tile) + 1;
   L.keys_off = 0;
   L.vals_off = align_up(n * kb, 256);
   L.part_off = align_up(L.vals_off + n * vb, 256);
   L.part4_off = align_up(L.part_off + (ceil_div(n, tmin) + 1) * sizeof(int64_t), 256);
-  // four start offsets per fused-pass output tile
-  const size_t p4 = (fused && levels >= 2) ? (ceil_div(n, merge4_tile) + 1) * 4 * sizeof(int64_t) : 0;
-  L.bytes = align_up(L.part4_off + p4, 256);
+  // four start offsets per fused-pass output tile, and two keys per sample
+  L.head_off = align_up(L.part4_off + (f ? t4 * 4 * sizeof(int64_t) : 0), 256);
+  L.tail_off = align_up(L.head_off + (f ? t4 * kb : 0), 256);
+  L.bytes = align_up(L.tail_off + (f ? t4 * kb : 0), 256);
   return L;
 }
 
