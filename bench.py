@@ -319,9 +319,11 @@ def main():
         bytes_per_launch = n * (kb + vb) * 2          # read + write of every key and value
         achieved = bytes_per_launch / (kernels[dom]["avg_ms"] * 1e-3) / 1e9
         kname = "merge4_kernel" if dom == "merge4" else "merge_kernel"
+        levels = 2 if dom == "merge4" else 1       # merge-tree levels one launch completes
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(args.workload, kname),
-                    "kernel": kname, "bytes_per_launch": bytes_per_launch}
+                    "kernel": kname, "bytes_per_launch": bytes_per_launch, "tree_levels_per_launch": levels,
+                    "per_level_equivalent_GBs": round(achieved * levels, 1)}
     # whole-sort algorithmic bytes (tile sort pass + HBM merge passes)
     plan = msort.ms_plan_query(n, kt, vb)
     total_bytes = n * (kb + vb) * 2 * (1 + plan["hbm_passes"])

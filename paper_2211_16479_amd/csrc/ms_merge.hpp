@@ -462,13 +462,15 @@ __global__ __launch_bounds__(256) void partition4_kernel(const K* __restrict__ s
 // merged as merge(merge(P0, P1), merge(P2, P3)) in LDS.
 //   stage 0: coalesced load of P0|P1|P2|P3 into buffer 1;
 //   stage 1: each thread produces IPT consecutive positions of
-//            [merge(P0, P1) | merge(P2, P3)] into buffer 2 (a thread whose
-//            positions straddle the boundary restarts on the second merge);
-//            for pairs, buffer 2 also records where each key sits in
-//            buffer 1;
-//   stage 2: the two halves of buffer 2 merged as in MergeTile, stored to
-//            HBM (values fetched from buffer 1 through the recorded index).
-template <class K, class V, int WG, int IPT, int PAD>
+//            [merge(P0, P1) | merge(P2, P3)] (a thread whose positions
+//            straddle the boundary restarts on the second merge); for
+//            pairs, each result also records where its key sits in
+//            buffer 1.  REUSE = 0 writes them to a second key buffer;
+//            REUSE = 1 holds them in registers across a barrier and writes
+//            them over buffer 1's keys (less LDS, one more barrier);
+//   stage 2: the two halves merged as in MergeTile, stored to HBM (values
+//            fetched from buffer 1 through the recorded index).
+template <class K, class V, int WG, int IPT, int PAD, int REUSE>
 struct Merge4Tile {
   static constexpr bool PAIRS = HasVal<V>::value;
   using VV = typename std::conditional<PAIRS, V, int>::type;
@@ -479,7 +481,7 @@ struct Merge4Tile {
   static constexpr size_t K1_OFF = 0;
   static constexpr size_t V1_OFF = al16(sizeof(K) * SLOTS);
   static constexpr size_t K2_OFF = V1_OFF + (PAIRS ? al16(sizeof(VV) * SLOTS) : 0);
-  static constexpr size_t I2_OFF = K2_OFF + al16(sizeof(K) * SLOTS);
+  static constexpr size_t I2_OFF = K2_OFF + (REUSE ? 0 : al16(sizeof(K) * SLOTS));
   static constexpr size_t LDS_BYTES = I2_OFF + (PAIRS ? al16(sizeof(uint16_t) * SLOTS) : 0);
 
   static __device__ __forceinline__ void run(const K* __restrict__ src_k, const VV* __restrict__ src_v,
@@ -488,17 +490,18 @@ struct Merge4Tile {
     const uint32_t tid = threadIdx.x;
     K* k1 = reinterpret_cast<K*>(smem + K1_OFF);
     VV* v1 = reinterpret_cast<VV*>(smem + V1_OFF);
-    K* k2 = reinterpret_cast<K*>(smem + K2_OFF);
+    K* k2 = reinterpret_cast<K*>(smem + (REUSE ? K1_OFF : K2_OFF));  // stage-1 results
     uint16_t* i2 = reinterpret_cast<uint16_t*>(smem + I2_OFF);
     const uint32_t c1 = l[0], c2 = c1 + l[1], c3 = c2 + l[2], total = c3 + l[3];
-    // stage 0
+    // stage 0 (a full tile, the usual case, needs no bounds predicates)
     {
       K kv[IPT];
       VV vv[PAIRS ? IPT : 1];
+      const bool full = total == uint32_t(TM);
 #pragma unroll
       for (int r = 0; r < IPT; ++r) {
         const uint32_t e = tid + uint32_t(r) * WG;
-        if (e < total) {
+        if (full || e < total) {
           const uint64_t g = e < c1 ? s[0] + e : e < c2 ? s[1] + (e - c1) : e < c3 ? s[2] + (e - c2) : s[3] + (e - c3);
           kv[r] = src_k[g];
           if constexpr (PAIRS) vv[r] = src_v[g];
@@ -507,7 +510,7 @@ struct Merge4Tile {
 #pragma unroll
       for (int r = 0; r < IPT; ++r) {
         const uint32_t e = tid + uint32_t(r) * WG;
-        if (e < total) {
+        if (full || e < total) {
           k1[lds_pad<PAD>(e)] = kv[r];
           if constexpr (PAIRS) v1[lds_pad<PAD>(e)] = vv[r];
         }
@@ -517,6 +520,8 @@ struct Merge4Tile {
     const uint32_t e0 = tid * IPT;
     const uint32_t last = total ? total - 1 : 0;
     // stage 1
+    K ko1[REUSE ? IPT : 1];
+    uint16_t io1[(REUSE && PAIRS) ? IPT : 1];
     if (e0 < total) {
       // merge state: P = k1[pb, pb + lp), Q = k1[pb + lp, pb + lp + lq)
       const bool second = e0 >= c2;
@@ -549,8 +554,13 @@ struct Merge4Tile {
         if (pos < total) {
           const bool take_b = (j < jend) && (i >= iend || b < a);
           const uint32_t src = take_b ? j : i;
-          k2[lds_pad<PAD>(pos)] = take_b ? b : a;
-          if constexpr (PAIRS) i2[lds_pad<PAD>(pos)] = uint16_t(src);
+          if constexpr (REUSE) {
+            ko1[r] = take_b ? b : a;
+            if constexpr (PAIRS) io1[r] = uint16_t(src);
+          } else {
+            k2[lds_pad<PAD>(pos)] = take_b ? b : a;
+            if constexpr (PAIRS) i2[lds_pad<PAD>(pos)] = uint16_t(src);
+          }
           i += take_b ? 0u : 1u;
           j += take_b ? 1u : 0u;
           const uint32_t nx = take_b ? j : i;
@@ -559,6 +569,15 @@ struct Merge4Tile {
           b = take_b ? x : b;
         }
       }
+    }
+    if constexpr (REUSE) {
+      __syncthreads();  // every stage-1 read of buffer 1's keys is done
+#pragma unroll
+      for (int r = 0; r < IPT; ++r)
+        if (e0 + uint32_t(r) < total) {
+          k2[lds_pad<PAD>(e0 + r)] = ko1[r];
+          if constexpr (PAIRS) i2[lds_pad<PAD>(e0 + r)] = io1[r];
+        }
     }
     __syncthreads();
     // stage 2: A = k2[0, c2), B = k2[c2, total)
@@ -616,11 +635,11 @@ struct Merge4Tile {
 
 // Workgroup b merges output tiles b, b + grid, ...; a tile ends at the next
 // tile's offsets or, for the quad's last tile, at the run ends.
-template <class K, class V, int WG, int IPT, int PAD>
+template <class K, class V, int WG, int IPT, int PAD, int REUSE>
 __global__ __launch_bounds__(WG) void merge4_kernel(const K* __restrict__ src_k, const V* __restrict__ src_v,
                                                     K* __restrict__ dst_k, V* __restrict__ dst_v, uint64_t n_host,
                                                     DevCtl ctl, uint64_t W, const int64_t* __restrict__ part4) {
-  using MT = Merge4Tile<K, V, WG, IPT, PAD>;
+  using MT = Merge4Tile<K, V, WG, IPT, PAD, REUSE>;
   extern __shared__ __align__(16) unsigned char smem[];
   if (gated_off(ctl)) return;
   const uint64_t n = live_n(ctl, n_host);

@@ -41,7 +41,7 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
   using C = PlainCfg<K, V>;
   using BS = TileSort<K, V, C::BS_WG, C::BS_IPT, C::BS_PAD>;
   using MT = MergeTile<K, V, C::MG_WG, C::MG_IPT, C::MG_PAD>;
-  using M4 = Merge4Tile<K, V, C::M4_WG, C::M4_IPT, C::M4_PAD>;
+  using M4 = Merge4Tile<K, V, C::M4_WG, C::M4_IPT, C::M4_PAD, C::M4_REUSE>;
   if (n == 0) return MS_OK;
   const int P = plan_passes(n, C::TILE);
   const int H = plan_hbm_passes(P, C::FUSED);
@@ -61,7 +61,7 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
   static const hipError_t lds_ok = [] {
     hipError_t a = allow_lds(&block_sort_kernel<K, V, C::BS_WG, C::BS_IPT, C::BS_PAD>, BS::LDS_BYTES);
     hipError_t b = allow_lds(&merge_kernel<K, V, C::MG_WG, C::MG_IPT, C::MG_PAD>, MT::LDS_BYTES);
-    hipError_t c = allow_lds(&merge4_kernel<K, V, C::M4_WG, C::M4_IPT, C::M4_PAD>, M4::LDS_BYTES);
+    hipError_t c = allow_lds(&merge4_kernel<K, V, C::M4_WG, C::M4_IPT, C::M4_PAD, C::M4_REUSE>, M4::LDS_BYTES);
     return a != hipSuccess ? a : (b != hipSuccess ? b : c);
   }();
   if (lds_ok != hipSuccess) return hip_fail(lds_ok, "LDS size attribute");
@@ -104,7 +104,7 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
       }
       {
         ProfScope ps(PK_MERGE4, s);
-        merge4_kernel<K, V, C::M4_WG, C::M4_IPT, C::M4_PAD>
+        merge4_kernel<K, V, C::M4_WG, C::M4_IPT, C::M4_PAD, C::M4_REUSE>
             <<<dim3(unsigned(std::min(mt4, cap))), dim3(C::M4_WG), M4::LDS_BYTES, s>>>(cur_k, cur_v, nxt_k, nxt_v, n,
                                                                                      ctl, W, part4);
       }

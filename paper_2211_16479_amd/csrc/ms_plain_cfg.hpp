@@ -92,6 +92,17 @@ namespace ms {
 #ifndef MS_M4_WG_W
 #define MS_M4_WG_W 256
 #endif
+// fused merge: 1 = stage-1 results overwrite the staged keys (less LDS,
+// one more barrier); faster where LDS limits occupancy
+#ifndef MS_M4_REUSE_K
+#define MS_M4_REUSE_K 0
+#endif
+#ifndef MS_M4_REUSE_P
+#define MS_M4_REUSE_P 1
+#endif
+#ifndef MS_M4_REUSE_W
+#define MS_M4_REUSE_W 1
+#endif
 #ifndef MS_M4_IPT_W
 #define MS_M4_IPT_W 8
 #endif
@@ -108,6 +119,7 @@ struct PlainCfg {
   static constexpr int M4_WG = WIDE ? MS_M4_WG_W : (PAIRS ? MS_M4_WG_P : MS_M4_WG_K);
   static constexpr int M4_IPT = WIDE ? MS_M4_IPT_W : (PAIRS ? MS_M4_IPT_P : MS_M4_IPT_K);
   static constexpr int M4_PAD = WIDE ? MS_PAD_W : (PAIRS ? MS_M4_PAD_P : MS_M4_PAD_K);
+  static constexpr int M4_REUSE = WIDE ? MS_M4_REUSE_W : (PAIRS ? MS_M4_REUSE_P : MS_M4_REUSE_K);
   static constexpr bool FUSED = MS_FUSED != 0;
   static constexpr int TILE = BS_WG * BS_IPT;
   static constexpr int MTILE = MG_WG * MG_IPT;
