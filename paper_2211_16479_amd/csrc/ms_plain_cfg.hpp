@@ -72,7 +72,7 @@ namespace ms {
 #define MS_FUSED 1
 #endif
 #ifndef MS_M4_WG_K
-#define MS_M4_WG_K 256
+#define MS_M4_WG_K 512
 #endif
 #ifndef MS_M4_IPT_K
 #define MS_M4_IPT_K 8
