@@ -19,6 +19,19 @@
 #pragma once
 #include "ms_common.hpp"
 
+// Lanes spanned by the runs that the bitonic wavefront merges build before
+// LDS merge-path levels take over: 32-bit keys alone stay on lane exchanges
+// up to the whole wavefront; pairs and 64-bit keys (wider items, costlier
+// exchanges) switch to LDS after the quad-permute levels.  Measured on
+// MI355X: 32-bit keys 1.00 ms (64) vs 1.11 ms (4) per 2^27; Zipf pairs
+// 1.59 vs 1.42 ms; 2^28 int64 2.46 vs 1.87 ms.
+#ifndef MS_TS_LANES_K
+#define MS_TS_LANES_K 64
+#endif
+#ifndef MS_TS_LANES_PW
+#define MS_TS_LANES_PW 4
+#endif
+
 namespace ms {
 
 template <class IT, class T>
@@ -86,20 +99,34 @@ __device__ __forceinline__ void wave_merge_level(T (&v)[N], int lane) {
   }
 }
 
-template <class IT, int L2, int N, class T>
+// Wavefront merge levels from runs spanning L2/2 lanes up to runs spanning
+// LMAX lanes.
+template <class IT, int L2, int LMAX, int N, class T>
 __device__ __forceinline__ void wave_merges(T (&v)[N], int lane) {
-  wave_merge_level<IT, L2>(v, lane);
-  if constexpr (L2 < 64) wave_merges<IT, L2 * 2>(v, lane);
+  if constexpr (L2 <= LMAX) {
+    wave_merge_level<IT, L2>(v, lane);
+    wave_merges<IT, L2 * 2, LMAX>(v, lane);
+  }
+}
+
+// Orders LDS accesses among the lanes of one wavefront (merge levels whose
+// runs never leave the wavefront's own part of LDS need nothing wider).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // One LDS merge-path level: sorted runs of R items (blocked in registers
 // across the workgroup) become runs of 2R.  lds must hold WG*N items.
-template <class IT, int WG, int PAD, int N, class T>
+// WAVE: 2R <= 64*N, so every pair of runs lies in the part of LDS that one
+// wavefront writes and reads, and a wavefront-wide sync suffices.
+template <class IT, int WG, int PAD, bool WAVE = false, int N, class T>
 __device__ __forceinline__ void lds_merge_level(T (&v)[N], T* lds, int R) {
   const int tid = threadIdx.x;
 #pragma unroll
   for (int r = 0; r < N; ++r) lds[lds_pad<PAD>(tid * N + r)] = v[r];
-  __syncthreads();
+  if constexpr (WAVE) wave_lds_sync(); else __syncthreads();
   const int per_blk = (2 * R) / N;  // threads per merged run
   const int blk = tid / per_blk;
   const int d = (tid - blk * per_blk) * N;
@@ -122,7 +149,7 @@ __device__ __forceinline__ void lds_merge_level(T (&v)[N], T* lds, int R) {
     a = take_b ? a : x;
     b = take_b ? x : b;
   }
-  __syncthreads();
+  if constexpr (WAVE) wave_lds_sync(); else __syncthreads();
 }
 
 template <class K, class V, int WG, int IPT, int PAD>
@@ -134,7 +161,12 @@ struct TileSort {
   static constexpr int NW = WG / 64;
   static_assert(WG % 64 == 0 && (WG & (WG - 1)) == 0 && WG <= 1024, "WG");
   static_assert((IPT & (IPT - 1)) == 0 && IPT >= 2 && IPT <= 32, "IPT");
-  static constexpr size_t LDS_ITEMS = (NW > 1) ? (sizeof(T) * lds_padded_size<PAD>(TILE) + 15) / 16 * 16 : 0;
+  // lane-exchange (bitonic) merges build runs spanning LANES lanes; LDS
+  // merge-path levels take them from there to the whole tile
+  static constexpr int LANES = (PAIRS || sizeof(K) == 8) ? MS_TS_LANES_PW : MS_TS_LANES_K;
+  static_assert(LANES >= 1 && LANES <= 64 && (LANES & (LANES - 1)) == 0, "LANES");
+  static constexpr bool USE_LDS = NW > 1 || LANES < 64;
+  static constexpr size_t LDS_ITEMS = USE_LDS ? (sizeof(T) * lds_padded_size<PAD>(TILE) + 15) / 16 * 16 : 0;
   static constexpr size_t LDS_VALS = PAIRS ? sizeof(typename std::conditional<PAIRS, V, int>::type) * TILE : 0;
   static constexpr size_t LDS_BYTES = LDS_ITEMS + LDS_VALS;
 
@@ -177,15 +209,20 @@ struct TileSort {
       }
     }
     register_sort<IT>(v);
-    wave_merges<IT, 2>(v, lane);
-    if constexpr (NW > 1) {
+    wave_merges<IT, 2, LANES>(v, lane);
+    if constexpr (USE_LDS) {
       // all loads of this tile are done before the first barrier, so the
       // output may overwrite the input in place
 #pragma unroll
-      for (int R = 64 * IPT; R < TILE; R *= 2) lds_merge_level<IT, WG, PAD>(v, lds, R);
-    } else {
-      __syncthreads();
+      for (int R = LANES * IPT; R < 64 * IPT && R < TILE; R *= 2) lds_merge_level<IT, WG, PAD, true>(v, lds, R);
+      if constexpr (NW > 1) {
+#pragma unroll
+        for (int R = 64 * IPT; R < TILE; R *= 2) lds_merge_level<IT, WG, PAD>(v, lds, R);
+      }
     }
+    // staged values are read across the workgroup below (a multi-wavefront
+    // tile already ended its last level with a workgroup barrier)
+    if constexpr (NW == 1) __syncthreads();
     // store
     K ko[IPT];
 #pragma unroll
