@@ -121,8 +121,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 // across the workgroup) become runs of 2R.  lds must hold WG*N items.
 // WAVE: 2R <= 64*N, so every pair of runs lies in the part of LDS that one
 // wavefront writes and reads, and a wavefront-wide sync suffices.
+// A merged block that lies wholly past the tile's length holds only padding
+// items, which are already in order (pad(e) at position e), so it is
+// skipped.
 template <class IT, int WG, int PAD, bool WAVE = false, int N, class T>
-__device__ __forceinline__ void lds_merge_level(T (&v)[N], T* lds, int R) {
+__device__ __forceinline__ void lds_merge_level(T (&v)[N], T* lds, int R, uint32_t len) {
   const int tid = threadIdx.x;
 #pragma unroll
   for (int r = 0; r < N; ++r) lds[lds_pad<PAD>(tid * N + r)] = v[r];
@@ -131,23 +134,29 @@ __device__ __forceinline__ void lds_merge_level(T (&v)[N], T* lds, int R) {
   const int blk = tid / per_blk;
   const int d = (tid - blk * per_blk) * N;
   const uint32_t a0 = blk * 2 * R, b0 = a0 + R;  // runs A and B (through lds_pad)
-  int lo = d > R ? d - R : 0, hi = d < R ? d : R;
-  while (lo < hi) {
-    const int m = (lo + hi) >> 1;
-    if (IT::less(lds[lds_pad<PAD>(b0 + d - 1 - m)], lds[lds_pad<PAD>(a0 + m)])) hi = m; else lo = m + 1;
-  }
-  int i = lo, j = d - lo;
-  T a = lds[lds_pad<PAD>(a0 + (i < R ? i : R - 1))], b = lds[lds_pad<PAD>(b0 + (j < R ? j : R - 1))];
+  // the barrier below is reached by every thread whichever branch it takes
+  if (a0 >= len) {
 #pragma unroll
-  for (int r = 0; r < N; ++r) {
-    const bool take_b = (j < R) && (i >= R || IT::less(b, a));
-    v[r] = take_b ? b : a;
-    i += take_b ? 0 : 1;
-    j += take_b ? 1 : 0;
-    const uint32_t nx = take_b ? b0 + (j < R ? j : R - 1) : a0 + (i < R ? i : R - 1);
-    const T x = lds[lds_pad<PAD>(nx)];
-    a = take_b ? a : x;
-    b = take_b ? x : b;
+    for (int r = 0; r < N; ++r) v[r] = IT::pad(a0 + d + r);
+  } else {
+    int lo = d > R ? d - R : 0, hi = d < R ? d : R;
+    while (lo < hi) {
+      const int m = (lo + hi) >> 1;
+      if (IT::less(lds[lds_pad<PAD>(b0 + d - 1 - m)], lds[lds_pad<PAD>(a0 + m)])) hi = m; else lo = m + 1;
+    }
+    int i = lo, j = d - lo;
+    T a = lds[lds_pad<PAD>(a0 + (i < R ? i : R - 1))], b = lds[lds_pad<PAD>(b0 + (j < R ? j : R - 1))];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      const bool take_b = (j < R) && (i >= R || IT::less(b, a));
+      v[r] = take_b ? b : a;
+      i += take_b ? 0 : 1;
+      j += take_b ? 1 : 0;
+      const uint32_t nx = take_b ? b0 + (j < R ? j : R - 1) : a0 + (i < R ? i : R - 1);
+      const T x = lds[lds_pad<PAD>(nx)];
+      a = take_b ? a : x;
+      b = take_b ? x : b;
+    }
   }
   if constexpr (WAVE) wave_lds_sync(); else __syncthreads();
 }
@@ -208,17 +217,23 @@ struct TileSort {
         v[r] = e < len ? IT::make(in_k[e], e) : IT::pad(e);
       }
     }
-    register_sort<IT>(v);
-    wave_merges<IT, 2, LANES>(v, lane);
-    if constexpr (USE_LDS) {
+    // a wavefront whose items are all padding holds them in order already
+    // and skips its wavefront-local levels (short segments, partial tiles)
+    const bool pad_wave = uint32_t(tid & ~63) * IPT >= len;
+    if (!pad_wave) {
+      register_sort<IT>(v);
+      wave_merges<IT, 2, LANES>(v, lane);
+      if constexpr (USE_LDS) {
+#pragma unroll
+        for (int R = LANES * IPT; R < 64 * IPT && R < TILE; R *= 2)
+          lds_merge_level<IT, WG, PAD, true>(v, lds, R, len);
+      }
+    }
+    if constexpr (USE_LDS && NW > 1) {
       // all loads of this tile are done before the first barrier, so the
       // output may overwrite the input in place
 #pragma unroll
-      for (int R = LANES * IPT; R < 64 * IPT && R < TILE; R *= 2) lds_merge_level<IT, WG, PAD, true>(v, lds, R);
-      if constexpr (NW > 1) {
-#pragma unroll
-        for (int R = 64 * IPT; R < TILE; R *= 2) lds_merge_level<IT, WG, PAD>(v, lds, R);
-      }
+      for (int R = 64 * IPT; R < TILE; R *= 2) lds_merge_level<IT, WG, PAD>(v, lds, R, len);
     }
     // staged values are read across the workgroup below (a multi-wavefront
     // tile already ended its last level with a workgroup barrier)
