@@ -180,7 +180,7 @@ typedef struct ms_options {
   int algo;                  /* ms_algo */
   float spill_threshold;     /* fall back when spilled keys > this * n; [0, 0.5], default 0.05 */
   uint32_t bucket_capacity;  /* keys sorted per LDS bucket: 4096 or 16384 (default) */
-  uint32_t bucket_fill;      /* target mean keys per bucket, 64..capacity, default 2048 */
+  uint32_t bucket_fill;      /* target mean keys per bucket, 64..capacity, default 512 */
   uint32_t train_steps;      /* Adam steps, default 64 */
   float learning_rate;       /* default 1e-4 */
   uint32_t sample_log2;      /* log2 of the sample size, 10..20, default 16 */

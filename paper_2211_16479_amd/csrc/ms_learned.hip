@@ -179,7 +179,7 @@ static ms_status learned_enqueue(uint32_t* keys, uint64_t n, const ms_options& o
   const unsigned chunks1 = unsigned(ceil_div(n, LS_CHK));
   {
     ProfScope ps(PK_LEARN_HIST, s);
-    ls_hist1_kernel<<<chunks1, LS_WG, 0, s>>>(keys, n, md, bn);
+    ls_hist1_kernel<<<unsigned(ceil_div(chunks1, LS_H1)), LS_WG, 0, s>>>(keys, n, md, bn);
   }
   ls_plan1_kernel<<<1, LS_WG, 0, s>>>(md, bn);
   {
@@ -262,7 +262,7 @@ void ms_options_default(ms_options* o) {
   o->algo = MS_ALGO_AUTO;
   o->spill_threshold = 0.05f;
   o->bucket_capacity = 16384;
-  o->bucket_fill = 2048;
+  o->bucket_fill = 512;
   o->train_steps = 64;
   o->learning_rate = 1e-4f;
   o->sample_log2 = 16;

@@ -45,6 +45,10 @@ constexpr int LS_TRAIN_WG = 256;     // training workgroup size
 constexpr int LS_WG = 512;           // histogram / scatter workgroup size
 constexpr int LS_CHK = 8192;         // keys per histogram / scatter chunk
 constexpr int LS_MAX_BINS = 1024;    // max coarse or fine bins per level
+#ifndef MS_LS_H1
+#define MS_LS_H1 4
+#endif
+constexpr int LS_H1 = MS_LS_H1;      // level-1 histogram chunks per workgroup
 constexpr float LS_BETA1 = 0.9f, LS_BETA2 = 0.999f, LS_EPS = 1e-8f;
 
 // Feature of a key (bit-identical to the CPU oracle's float32 computation).
@@ -401,7 +405,9 @@ __global__ __launch_bounds__(256) void ls_clear_kernel(LsBins bn, uint32_t nb_c,
   if (i < nb_c) bn.cnt_c[i] = 0;
 }
 
-// Level 1: coarse histogram of one chunk per workgroup.
+// Level 1: coarse histogram of LS_H1 consecutive chunks per workgroup (one
+// flush of LDS counts into the global counters per LS_H1 chunks, which
+// keeps the 1024 global counters from serialising the whole launch).
 __global__ __launch_bounds__(LS_WG) void ls_hist1_kernel(const uint32_t* __restrict__ keys, uint64_t n,
                                                          const LsModel* md, LsBins bn) {
   __shared__ LsTable tb;
@@ -410,17 +416,20 @@ __global__ __launch_bounds__(LS_WG) void ls_hist1_kernel(const uint32_t* __restr
   const uint32_t nbc = md->nbins_c;
   for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) h[i] = 0;
   __syncthreads();
-  const uint64_t base = uint64_t(blockIdx.x) * LS_CHK;
-  uint32_t kv[LS_CHK / LS_WG];
+  for (int c = 0; c < LS_H1; ++c) {
+    const uint64_t base = (uint64_t(blockIdx.x) * LS_H1 + c) * LS_CHK;
+    if (base >= n) break;  // workgroup-uniform
+    uint32_t kv[LS_CHK / LS_WG];
 #pragma unroll
-  for (int r = 0; r < LS_CHK / LS_WG; ++r) {
-    const uint64_t e = base + threadIdx.x + uint64_t(r) * LS_WG;
-    kv[r] = e < n ? keys[e] : 0u;
-  }
+    for (int r = 0; r < LS_CHK / LS_WG; ++r) {
+      const uint64_t e = base + threadIdx.x + uint64_t(r) * LS_WG;
+      kv[r] = e < n ? keys[e] : 0u;
+    }
 #pragma unroll
-  for (int r = 0; r < LS_CHK / LS_WG; ++r) {
-    const uint64_t e = base + threadIdx.x + uint64_t(r) * LS_WG;
-    if (e < n) atomicAdd(&h[ls_bucket(&tb, kv[r]) >> tb.fine_bits], 1u);
+    for (int r = 0; r < LS_CHK / LS_WG; ++r) {
+      const uint64_t e = base + threadIdx.x + uint64_t(r) * LS_WG;
+      if (e < n) atomicAdd(&h[ls_bucket(&tb, kv[r]) >> tb.fine_bits], 1u);
+    }
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG)
