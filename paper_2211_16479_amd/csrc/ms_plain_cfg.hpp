@@ -19,7 +19,7 @@ namespace ms {
 #define MS_BS_WG_K 1024
 #endif
 #ifndef MS_BS_IPT_K
-#define MS_BS_IPT_K 16
+#define MS_BS_IPT_K 32
 #endif
 #ifndef MS_BS_PAD_K
 #define MS_BS_PAD_K 0
@@ -90,7 +90,7 @@ namespace ms {
 #define MS_M4_PAD_P 5
 #endif
 #ifndef MS_M4_WG_W
-#define MS_M4_WG_W 256
+#define MS_M4_WG_W 512
 #endif
 // fused merge: 1 = stage-1 results overwrite the staged keys (less LDS,
 // one more barrier); faster where LDS limits occupancy

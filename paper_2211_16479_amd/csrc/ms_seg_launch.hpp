@@ -163,19 +163,21 @@ ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint6
     e = SegCands<K, V>::launch(S::cls_max(c), tune[c], keys, vals, off, st, c, nseg, side);
     if (e != hipSuccess) return hip_fail(e, "small-segment sort launch");
   }
-  if (max_len > uint64_t(S::TILE)) {
-    using TS = TileSort<K, V, P::BS_WG, P::BS_IPT, P::BS_PAD>;
+  // segments longer than the last small class take the large path (a tile
+  // sort, then merge passes when they span several tiles)
+  if (max_len > uint64_t(S::cls_max(S::NCLS - 1))) {
+    using TS = TileSort<K, V, S::LWG, S::LIPT, P::BS_PAD>;
     using MT = MergeTile<K, V, P::MG_WG, P::MG_IPT, P::MG_PAD>;
     static const hipError_t lds_ok = [] {
-      hipError_t a = seg_allow_lds(&seg_large_tile_kernel<K, V, P::BS_WG, P::BS_IPT, P::BS_PAD>, TS::LDS_BYTES);
+      hipError_t a = seg_allow_lds(&seg_large_tile_kernel<K, V, S::LWG, S::LIPT, P::BS_PAD>, TS::LDS_BYTES);
       hipError_t b = seg_allow_lds(&seg_merge_kernel<K, V, P::MG_WG, P::MG_IPT, P::MG_PAD>, MT::LDS_BYTES);
       return a != hipSuccess ? a : b;
     }();
     if (lds_ok != hipSuccess) return hip_fail(lds_ok, "LDS size attribute");
     // one workgroup per reserved (merge) tile up to the host-side bound
     const uint64_t tiles_cap = L.mt_cap / S::C;
-    seg_large_tile_kernel<K, V, P::BS_WG, P::BS_IPT, P::BS_PAD>
-        <<<dim3(unsigned(tiles_cap)), dim3(P::BS_WG), TS::LDS_BYTES, s>>>(keys, vals, tk, tv, st);
+    seg_large_tile_kernel<K, V, S::LWG, S::LIPT, P::BS_PAD>
+        <<<dim3(unsigned(tiles_cap)), dim3(S::LWG), TS::LDS_BYTES, s>>>(keys, vals, tk, tv, st);
     const int passes = plan_passes(max_len, S::TILE);
     for (int p = 0; p < passes; ++p) {
       seg_partition_kernel<K, V><<<dim3(unsigned(ceil_div(L.mt_cap, 256))), dim3(256), 0, s>>>(keys, tk, st, p);

@@ -72,7 +72,11 @@ __device__ __forceinline__ int seg_passes(uint64_t L, uint64_t T) {
 template <class K, class V>
 struct SegCfg {
   using P = PlainCfg<K, V>;
-  static constexpr int TILE = P::TILE;    // large segments: tile-sort tile
+  // large segments: the plain sort's tile-sort shape, at most 16384 items per
+  // tile (longer segments merge; a bigger tile pays off only for long arrays)
+  static constexpr int LWG = P::BS_WG;
+  static constexpr int LIPT = P::TILE > 16384 ? P::BS_IPT / (P::TILE / 16384) : P::BS_IPT;
+  static constexpr int TILE = LWG * LIPT;  // large segments: tile-sort tile
   static constexpr int MTILE = P::MTILE;  // large segments: merge tile
   static constexpr int C = TILE / MTILE;  // merge tiles per tile
   static constexpr int NCLS = TILE >= 16384 ? 4 : (TILE >= 4096 ? 3 : (TILE >= 2048 ? 3 : 2));
