@@ -462,10 +462,16 @@ __global__ __launch_bounds__(LS_WG) void ls_plan1_kernel(LsModel* md, LsBins bn)
 
 // Shared body of the two scatters: counting sort of one chunk by bin in LDS,
 // one reservation per non-empty bin, then coalesced runs to the destination.
+// With LS_SBIN = 0 the write-out recomputes each staged key's bin instead of
+// keeping it in LDS (16 KB less LDS per workgroup, more occupancy).
+#ifndef MS_LS_SBIN
+#define MS_LS_SBIN 1
+#endif
+constexpr int LS_SBIN = MS_LS_SBIN;
 struct LsScatterLds {
   uint32_t cnt[LS_MAX_BINS], off[LS_MAX_BINS], gb[LS_MAX_BINS], tmp[LS_WG];
   uint32_t stage[LS_CHK];
-  uint16_t sbin[LS_CHK];
+  uint16_t sbin[LS_SBIN ? LS_CHK : 1];
   uint32_t total;
 };
 
@@ -504,13 +510,14 @@ __global__ __launch_bounds__(LS_WG) void ls_scatter1_kernel(const uint32_t* __re
     if (e < n) {
       const uint32_t p = L.off[bin[r]] + rk[r];
       L.stage[p] = kv[r];
-      L.sbin[p] = uint16_t(bin[r]);
+      if constexpr (LS_SBIN) L.sbin[p] = uint16_t(bin[r]);
     }
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < L.total; i += LS_WG) {
-    const uint32_t b = L.sbin[i];
-    out[L.gb[b] + (i - L.off[b])] = L.stage[i];
+    const uint32_t x = L.stage[i];
+    const uint32_t b = LS_SBIN ? uint32_t(L.sbin[i]) : ls_bucket(&tb, x) >> tb.fine_bits;
+    out[L.gb[b] + (i - L.off[b])] = x;
   }
 }
 
@@ -574,42 +581,71 @@ __global__ __launch_bounds__(LS_WG) void ls_hist2_kernel(const uint32_t* __restr
     }
 }
 
+// Inclusive prefix maximum of x[0, nb) in place (nb <= 2 * LS_WG), whole
+// workgroup, Hillis-Steele over LDS; ends with a barrier.
+__device__ __forceinline__ void ls_block_prefix_max(uint32_t* x, uint32_t nb) {
+  for (uint32_t d = 1; d < nb; d <<= 1) {
+    uint32_t v[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t i = threadIdx.x + uint32_t(h) * LS_WG;
+      v[h] = (i < nb && i >= d) ? x[i - d] : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t i = threadIdx.x + uint32_t(h) * LS_WG;
+      if (i < nb && i >= d) x[i] = x[i] > v[h] ? x[i] : v[h];
+    }
+    __syncthreads();
+  }
+}
+
 // Per coarse bucket (one workgroup each): kept / spilled totals, largest
-// bucket, and the order of its kept buckets.
+// bucket, and the order of its kept buckets: every kept bucket's minimum
+// must not be below the maximum of the kept buckets before it.
 __global__ __launch_bounds__(LS_WG) void ls_totals_kernel(const LsModel* md, LsBins bn, uint32_t capacity) {
   __shared__ uint32_t cnt[LS_MAX_BINS], mn[LS_MAX_BINS], mx[LS_MAX_BINS];
+  __shared__ uint32_t kept, spill, maxb, bad, kmin, kmax;
   const uint32_t c = blockIdx.x;
   const uint32_t nbf = md->nbins_f;
   const uint32_t b0 = c << md->fine_bits;
+  if (threadIdx.x == 0) {
+    kept = spill = maxb = bad = kmax = 0;
+    kmin = 0xFFFFFFFFu;
+  }
   for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG) {
-    cnt[i] = bn.cnt_f[b0 + i];
-    mn[i] = bn.fmin[b0 + i];
-    mx[i] = bn.fmax[b0 + i];
+    const uint32_t k = bn.cnt_f[b0 + i];
+    const bool kp = k != 0 && k <= capacity;
+    cnt[i] = k;
+    mn[i] = kp ? bn.fmin[b0 + i] : 0xFFFFFFFFu;
+    mx[i] = kp ? bn.fmax[b0 + i] : 0u;  // 0 is neutral for the running maximum
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t kept = 0, spill = 0, maxb = 0, bad = 0, first = 0xFFFFFFFFu, run = 0;
-    bool any = false;
-    for (uint32_t i = 0; i < nbf; ++i) {
-      const uint32_t k = cnt[i];
-      maxb = k > maxb ? k : maxb;
-      if (k == 0) continue;
-      if (k > capacity) {
-        spill += k;
-        continue;
-      }
-      kept += k;
-      if (!any) first = mn[i];
-      else if (mn[i] < run) bad = 1;
-      run = any ? (mx[i] > run ? mx[i] : run) : mx[i];
-      any = true;
+  for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG) {
+    const uint32_t k = cnt[i];
+    if (k > capacity) atomicAdd(&spill, k);
+    else if (k) {
+      atomicAdd(&kept, k);
+      atomicMin(&kmin, mn[i]);
+      atomicMax(&kmax, mx[i]);
     }
+    atomicMax(&maxb, k);
+  }
+  ls_block_prefix_max(mx, nbf);
+  for (uint32_t i = threadIdx.x + 1; i < nbf; i += LS_WG)
+    if (mn[i] != 0xFFFFFFFFu && mn[i] < mx[i - 1]) bad = 1;
+  // kept buckets with every key equal to 0xFFFFFFFF carry that as their
+  // minimum too; they can only follow buckets whose maximum is <= it
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const bool any = kept != 0;
     bn.kept_tot[c] = kept;
     bn.spill_tot[c] = spill;
     bn.cmaxb[c] = maxb;
     bn.cbad[c] = bad;
-    bn.cmin[c] = any ? first : 0xFFFFFFFFu;
-    bn.cmax[c] = any ? run : 0u;
+    bn.cmin[c] = any ? kmin : 0xFFFFFFFFu;
+    bn.cmax[c] = any ? kmax : 0u;
   }
 }
 
@@ -631,15 +667,24 @@ __global__ __launch_bounds__(LS_WG) void ls_plan2_kernel(LsModel* md, LsBins bn,
     bn.kept_base[i] = kb[i];
     bn.spill_base[i] = sb[i];
   }
+  // the walk below reads LDS copies (loaded in parallel), not global memory
+  __shared__ uint32_t cb[LS_MAX_BINS], cm[LS_MAX_BINS], cn[LS_MAX_BINS], cx[LS_MAX_BINS];
+  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) {
+    cb[i] = bn.cbad[i];
+    cm[i] = bn.cmaxb[i];
+    cn[i] = bn.cmin[i];
+    cx[i] = bn.cmax[i];
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t bad = 0, run = 0, maxb = 0;
     bool any = false;
     for (uint32_t c = 0; c < nbc; ++c) {
-      bad |= bn.cbad[c];
-      maxb = bn.cmaxb[c] > maxb ? bn.cmaxb[c] : maxb;
+      bad |= cb[c];
+      maxb = cm[c] > maxb ? cm[c] : maxb;
       if (k[c] == 0) continue;
-      if (any && bn.cmin[c] < run) bad = 1;
-      run = any ? (bn.cmax[c] > run ? bn.cmax[c] : run) : bn.cmax[c];
+      if (any && cn[c] < run) bad = 1;
+      run = any ? (cx[c] > run ? cx[c] : run) : cx[c];
       any = true;
     }
     const uint64_t s = stot;
@@ -728,15 +773,16 @@ __global__ __launch_bounds__(LS_WG) void ls_scatter2_kernel(const uint32_t* __re
     if (e < hi) {
       const uint32_t p = L.off[bin[r]] + rk[r];
       L.stage[p] = kv[r];
-      L.sbin[p] = uint16_t(bin[r]);
+      if constexpr (LS_SBIN) L.sbin[p] = uint16_t(bin[r]);
     }
   }
   __syncthreads();
   uint32_t* rk_arr = static_cast<uint32_t*>(md->r_keys);
   for (uint32_t i = threadIdx.x; i < L.total; i += LS_WG) {
-    const uint32_t b = L.sbin[i];
+    const uint32_t x = L.stage[i];
+    const uint32_t b = LS_SBIN ? uint32_t(L.sbin[i]) : (ls_bucket(&tb, x) & fmask);
     uint32_t* dst = kept[b] ? rk_arr : xr;
-    dst[L.gb[b] + (i - L.off[b])] = L.stage[i];
+    dst[L.gb[b] + (i - L.off[b])] = x;
   }
 }
 
