@@ -67,6 +67,33 @@ __device__ __forceinline__ uint64_t merge_path_split(const K* A, uint64_t la, co
 // each split: head[k] = the pair's merged output at diagonal d (the smaller
 // of the two next elements), tail[k] = the output just before it (the larger
 // of the two last taken; undefined at d = 0).
+// The split of merge tile k (start g = k*Tm < n) of its pair, and with
+// head / tail non-null the keys around it (see partition_kernel).
+template <class K>
+__device__ __forceinline__ void partition_tile(const K* __restrict__ src, uint64_t n, uint64_t W, uint32_t Tm,
+                                               uint64_t k, const DevCtl& ctl, int64_t* __restrict__ part,
+                                               K* __restrict__ head, K* __restrict__ tail) {
+  const uint64_t g = k * Tm;
+  const PassGeom q = pass_geom(g, n, W, ctl);
+  const uint64_t la = q.a_end - q.pb, lb = q.b_end - q.a_end, d = g - q.pb;
+  const uint64_t i = merge_path_split(src + q.pb, la, src + q.a_end, lb, d);
+  part[k] = int64_t(q.pb + i);
+  if (head) {
+    // d < la + lb, so at least one next element exists; the index
+    // fallbacks below only ever name an existing element
+    const bool na = i < la, nb = d - i < lb;
+    const K x0 = src[na ? q.pb + i : q.a_end + (d - i)];
+    const K x1 = src[nb ? q.a_end + (d - i) : q.pb + i];
+    head[k] = x1 < x0 ? x1 : x0;
+    const bool pa = i >= 1, pbv = d - i >= 1;
+    if (pa || pbv) {
+      const K y0 = src[pa ? q.pb + i - 1 : q.a_end + (d - i) - 1];
+      const K y1 = src[pbv ? q.a_end + (d - i) - 1 : q.pb + i - 1];
+      tail[k] = y0 < y1 ? y1 : y0;
+    }
+  }
+}
+
 template <class K, int G>
 __global__ __launch_bounds__(256) void partition_kernel(const K* __restrict__ src, uint64_t n_host, DevCtl ctl,
                                                         uint64_t W, uint32_t Tm, uint64_t num_tiles,
@@ -79,26 +106,8 @@ __global__ __launch_bounds__(256) void partition_kernel(const K* __restrict__ sr
   const uint64_t k = gid / G;
   if constexpr (G == 1) {
     for (uint64_t kk = gid; kk < num_tiles; kk += uint64_t(gridDim.x) * blockDim.x) {
-      const uint64_t g = kk * Tm;
-      if (g >= n) return;
-      const PassGeom q = pass_geom(g, n, W, ctl);
-      const uint64_t la = q.a_end - q.pb, lb = q.b_end - q.a_end, d = g - q.pb;
-      const uint64_t i = merge_path_split(src + q.pb, la, src + q.a_end, lb, d);
-      part[kk] = int64_t(q.pb + i);
-      if (head) {
-        // d < la + lb, so at least one next element exists; the index
-        // fallbacks below only ever name an existing element
-        const bool na = i < la, nb = d - i < lb;
-        const K x0 = src[na ? q.pb + i : q.a_end + (d - i)];
-        const K x1 = src[nb ? q.a_end + (d - i) : q.pb + i];
-        head[kk] = x1 < x0 ? x1 : x0;
-        const bool pa = i >= 1, pbv = d - i >= 1;
-        if (pa || pbv) {
-          const K y0 = src[pa ? q.pb + i - 1 : q.a_end + (d - i) - 1];
-          const K y1 = src[pbv ? q.a_end + (d - i) - 1 : q.pb + i - 1];
-          tail[kk] = y0 < y1 ? y1 : y0;
-        }
-      }
+      if (kk * Tm >= n) return;
+      partition_tile(src, n, W, Tm, kk, ctl, part, head, tail);
     }
   } else {
     const uint32_t q = uint32_t(gid % G);
@@ -370,6 +379,88 @@ __device__ __forceinline__ uint64_t split_at_sample(const int64_t* __restrict__ 
 //           by searches bounded by the exact splits at the current interval
 //           ends (brackets), which shrink with the interval.
 template <class K>
+__device__ __forceinline__ void partition4_tile(const K* __restrict__ src, uint64_t n, uint64_t W, uint32_t Tm,
+                                                uint64_t k, const int64_t* __restrict__ part,
+                                                const K* __restrict__ head, const K* __restrict__ tail,
+                                                int64_t* __restrict__ part4) {
+  const QuadGeom Q = quad_geom(k * Tm, n, W);
+  const uint64_t la = Q.r1 - Q.qb, lb = Q.r2 - Q.r1, lc = Q.r3 - Q.r2, ld = Q.end - Q.r3;
+  const uint64_t lx = la + lb, ly = lc + ld;
+  const uint64_t dl = k * Tm - Q.qb;
+  uint64_t lo = dl > ly ? dl - ly : 0, hi = dl < lx ? dl : lx;
+  // coarse
+  {
+    uint64_t jlo = (lo + Tm - 1) / Tm, jhi = (hi + Tm - 1) / Tm;
+    const uint64_t j0 = jlo, j1 = jhi;
+    while (jlo < jhi) {
+      const uint64_t j = (jlo + jhi) >> 1;
+      const uint64_t m = j * Tm, p = dl - m;  // 1 <= p <= ly
+      const K xk = head[(Q.qb + m) / Tm];
+      K yk;
+      if (p < ly) {
+        yk = tail[(Q.r2 + p) / Tm];
+      } else {  // the last element of Y
+        const K c = src[lc ? Q.r3 - 1 : Q.end - 1];
+        const K e = src[ld ? Q.end - 1 : Q.r3 - 1];
+        yk = c < e ? e : c;
+      }
+      if (yk < xk) jhi = j; else jlo = j + 1;
+    }
+    const uint64_t wlo = jlo > j0 ? (jlo - 1) * Tm + 1 : lo;
+    const uint64_t whi = jlo < j1 ? jlo * Tm : hi;
+    lo = wlo;
+    hi = whi;
+  }
+  // fine: [lo, hi] lies inside [k0*Tm, k0*Tm + Tm]
+  const uint64_t mL = (lo / Tm) * Tm;
+  const uint64_t mR = mL + Tm < lx ? mL + Tm : lx;
+  Bracket bx{mL, split_at_sample(part, Q.qb, la, lx, Tm, mL), mR, split_at_sample(part, Q.qb, la, lx, Tm, mR)};
+  const uint64_t pR = dl - mL < ly ? dl - mL : ly;
+  const uint64_t pL = dl > mL + Tm ? dl - mL - Tm : 0;
+  Bracket by{pL, split_at_sample(part, Q.r2, lc, ly, Tm, pL), pR, split_at_sample(part, Q.r2, lc, ly, Tm, pR)};
+  while (lo < hi) {
+    const uint64_t m = (lo + hi) >> 1, p = dl - m;
+    uint64_t a0, a1, c0, c1;
+    bx.bounds(m, la, lb, &a0, &a1);
+    by.bounds(p, lc, ld, &c0, &c1);
+    const uint64_t sx = split_in(src, Q.qb, Q.r1, m, a0, a1);
+    const uint64_t ty = split_in(src, Q.r2, Q.r3, p, c0, c1);
+    // X[m]: the smaller next element; Y[p-1]: the larger last taken one
+    const bool xa = sx < la, xb = m - sx < lb;
+    const K ka = src[xa ? Q.qb + sx : Q.r1 + (m - sx)];
+    const K kb = src[xb ? Q.r1 + (m - sx) : Q.qb + sx];
+    const K xk = kb < ka ? kb : ka;
+    const bool yc = ty >= 1, yd = p - ty >= 1;
+    const K kc = src[yc ? Q.r2 + ty - 1 : Q.r3 + (p - ty) - 1];
+    const K kd = src[yd ? Q.r3 + (p - ty) - 1 : Q.r2 + ty - 1];
+    const K yk = kc < kd ? kd : kc;
+    if (yk < xk) {
+      hi = m;
+      bx.dR = m;
+      bx.fR = sx;
+      by.dL = p;
+      by.fL = ty;
+    } else {
+      lo = m + 1;
+      bx.dL = m;
+      bx.fL = sx;
+      by.dR = p;
+      by.fR = ty;
+    }
+  }
+  const uint64_t x = lo;
+  uint64_t a0, a1, c0, c1;
+  bx.bounds(x, la, lb, &a0, &a1);
+  by.bounds(dl - x, lc, ld, &c0, &c1);
+  const uint64_t a = split_in(src, Q.qb, Q.r1, x, a0, a1);
+  const uint64_t c = split_in(src, Q.r2, Q.r3, dl - x, c0, c1);
+  part4[4 * k + 0] = int64_t(Q.qb + a);
+  part4[4 * k + 1] = int64_t(Q.r1 + (x - a));
+  part4[4 * k + 2] = int64_t(Q.r2 + c);
+  part4[4 * k + 3] = int64_t(Q.r3 + (dl - x - c));
+}
+
+template <class K>
 __global__ __launch_bounds__(256) void partition4_kernel(const K* __restrict__ src, uint64_t n_host, DevCtl ctl,
                                                          uint64_t W, uint32_t Tm, uint64_t num_tiles,
                                                          const int64_t* __restrict__ part,
@@ -380,81 +471,7 @@ __global__ __launch_bounds__(256) void partition4_kernel(const K* __restrict__ s
   for (uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < num_tiles;
        k += uint64_t(gridDim.x) * blockDim.x) {
     if (k * Tm >= n) return;
-    const QuadGeom Q = quad_geom(k * Tm, n, W);
-    const uint64_t la = Q.r1 - Q.qb, lb = Q.r2 - Q.r1, lc = Q.r3 - Q.r2, ld = Q.end - Q.r3;
-    const uint64_t lx = la + lb, ly = lc + ld;
-    const uint64_t dl = k * Tm - Q.qb;
-    uint64_t lo = dl > ly ? dl - ly : 0, hi = dl < lx ? dl : lx;
-    // coarse
-    {
-      uint64_t jlo = (lo + Tm - 1) / Tm, jhi = (hi + Tm - 1) / Tm;
-      const uint64_t j0 = jlo, j1 = jhi;
-      while (jlo < jhi) {
-        const uint64_t j = (jlo + jhi) >> 1;
-        const uint64_t m = j * Tm, p = dl - m;  // 1 <= p <= ly
-        const K xk = head[(Q.qb + m) / Tm];
-        K yk;
-        if (p < ly) {
-          yk = tail[(Q.r2 + p) / Tm];
-        } else {  // the last element of Y
-          const K c = src[lc ? Q.r3 - 1 : Q.end - 1];
-          const K e = src[ld ? Q.end - 1 : Q.r3 - 1];
-          yk = c < e ? e : c;
-        }
-        if (yk < xk) jhi = j; else jlo = j + 1;
-      }
-      const uint64_t wlo = jlo > j0 ? (jlo - 1) * Tm + 1 : lo;
-      const uint64_t whi = jlo < j1 ? jlo * Tm : hi;
-      lo = wlo;
-      hi = whi;
-    }
-    // fine: [lo, hi] lies inside [k0*Tm, k0*Tm + Tm]
-    const uint64_t mL = (lo / Tm) * Tm;
-    const uint64_t mR = mL + Tm < lx ? mL + Tm : lx;
-    Bracket bx{mL, split_at_sample(part, Q.qb, la, lx, Tm, mL), mR, split_at_sample(part, Q.qb, la, lx, Tm, mR)};
-    const uint64_t pR = dl - mL < ly ? dl - mL : ly;
-    const uint64_t pL = dl > mL + Tm ? dl - mL - Tm : 0;
-    Bracket by{pL, split_at_sample(part, Q.r2, lc, ly, Tm, pL), pR, split_at_sample(part, Q.r2, lc, ly, Tm, pR)};
-    while (lo < hi) {
-      const uint64_t m = (lo + hi) >> 1, p = dl - m;
-      uint64_t a0, a1, c0, c1;
-      bx.bounds(m, la, lb, &a0, &a1);
-      by.bounds(p, lc, ld, &c0, &c1);
-      const uint64_t sx = split_in(src, Q.qb, Q.r1, m, a0, a1);
-      const uint64_t ty = split_in(src, Q.r2, Q.r3, p, c0, c1);
-      // X[m]: the smaller next element; Y[p-1]: the larger last taken one
-      const bool xa = sx < la, xb = m - sx < lb;
-      const K ka = src[xa ? Q.qb + sx : Q.r1 + (m - sx)];
-      const K kb = src[xb ? Q.r1 + (m - sx) : Q.qb + sx];
-      const K xk = kb < ka ? kb : ka;
-      const bool yc = ty >= 1, yd = p - ty >= 1;
-      const K kc = src[yc ? Q.r2 + ty - 1 : Q.r3 + (p - ty) - 1];
-      const K kd = src[yd ? Q.r3 + (p - ty) - 1 : Q.r2 + ty - 1];
-      const K yk = kc < kd ? kd : kc;
-      if (yk < xk) {
-        hi = m;
-        bx.dR = m;
-        bx.fR = sx;
-        by.dL = p;
-        by.fL = ty;
-      } else {
-        lo = m + 1;
-        bx.dL = m;
-        bx.fL = sx;
-        by.dR = p;
-        by.fR = ty;
-      }
-    }
-    const uint64_t x = lo;
-    uint64_t a0, a1, c0, c1;
-    bx.bounds(x, la, lb, &a0, &a1);
-    by.bounds(dl - x, lc, ld, &c0, &c1);
-    const uint64_t a = split_in(src, Q.qb, Q.r1, x, a0, a1);
-    const uint64_t c = split_in(src, Q.r2, Q.r3, dl - x, c0, c1);
-    part4[4 * k + 0] = int64_t(Q.qb + a);
-    part4[4 * k + 1] = int64_t(Q.r1 + (x - a));
-    part4[4 * k + 2] = int64_t(Q.r2 + c);
-    part4[4 * k + 3] = int64_t(Q.r3 + (dl - x - c));
+    partition4_tile(src, n, W, Tm, k, part, head, tail, part4);
   }
 }
 
@@ -633,50 +650,61 @@ struct Merge4Tile {
   }
 };
 
-// Workgroup b merges output tiles b, b + grid, ...; a tile ends at the next
-// tile's offsets or, for the quad's last tile, at the run ends.
+// Output tile k (k*TM < n) of a fused pass: a tile ends at the next tile's
+// offsets or, for the quad's last tile, at the run ends.  Every thread of
+// the workgroup calls it.
+template <class MT, class K, class VV>
+__device__ __forceinline__ void merge4_tile(const K* __restrict__ src_k, const VV* __restrict__ src_v,
+                                            K* __restrict__ dst_k, VV* __restrict__ dst_v, uint64_t n, uint64_t W,
+                                            uint64_t k, const int64_t* __restrict__ part4, unsigned char* smem) {
+  const uint64_t g0 = k * MT::TM;
+  const uint64_t g1 = g0 + MT::TM < n ? g0 + MT::TM : n;
+  const QuadGeom Q = quad_geom(g0, n, W);
+  uint64_t s[4], e[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) s[r] = uint64_t(part4[4 * k + r]);
+  if (g1 == Q.end) {
+    e[0] = Q.r1;
+    e[1] = Q.r2;
+    e[2] = Q.r3;
+    e[3] = Q.end;
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) e[r] = uint64_t(part4[4 * (k + 1) + r]);
+  }
+  // offsets that do not describe four in-run pieces filling the tile are
+  // never dereferenced (the tile is skipped); exact partitions always pass
+  const uint64_t rs[4] = {Q.qb, Q.r1, Q.r2, Q.r3}, re[4] = {Q.r1, Q.r2, Q.r3, Q.end};
+  bool ok = true;
+  uint64_t sum = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    ok = ok && rs[r] <= s[r] && s[r] <= e[r] && e[r] <= re[r];
+    sum += e[r] - s[r];
+  }
+  ok = ok && sum == g1 - g0;
+  uint32_t l[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) l[r] = ok ? uint32_t(e[r] - s[r]) : 0u;
+  MT::run(src_k, src_v, dst_k, dst_v, s, l, g0, smem);
+}
+
+// Workgroup b merges output tiles b, b + grid, ...
 template <class K, class V, int WG, int IPT, int PAD, int REUSE>
 __global__ __launch_bounds__(WG) void merge4_kernel(const K* __restrict__ src_k, const V* __restrict__ src_v,
                                                     K* __restrict__ dst_k, V* __restrict__ dst_v, uint64_t n_host,
                                                     DevCtl ctl, uint64_t W, const int64_t* __restrict__ part4) {
   using MT = Merge4Tile<K, V, WG, IPT, PAD, REUSE>;
+  using VV = typename MT::VV;
   extern __shared__ __align__(16) unsigned char smem[];
   if (gated_off(ctl)) return;
   const uint64_t n = live_n(ctl, n_host);
   for (uint64_t k = blockIdx.x; k * MT::TM < n; k += gridDim.x) {
-    const uint64_t g0 = k * MT::TM;
-    const uint64_t g1 = g0 + MT::TM < n ? g0 + MT::TM : n;
-    const QuadGeom Q = quad_geom(g0, n, W);
-    uint64_t s[4], e[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) s[r] = uint64_t(part4[4 * k + r]);
-    if (g1 == Q.end) {
-      e[0] = Q.r1;
-      e[1] = Q.r2;
-      e[2] = Q.r3;
-      e[3] = Q.end;
-    } else {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) e[r] = uint64_t(part4[4 * (k + 1) + r]);
-    }
-    // offsets that do not describe four in-run pieces filling the tile are
-    // never dereferenced (the tile is skipped); exact partitions always pass
-    const uint64_t rs[4] = {Q.qb, Q.r1, Q.r2, Q.r3}, re[4] = {Q.r1, Q.r2, Q.r3, Q.end};
-    bool ok = true;
-    uint64_t sum = 0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      ok = ok && rs[r] <= s[r] && s[r] <= e[r] && e[r] <= re[r];
-      sum += e[r] - s[r];
-    }
-    ok = ok && sum == g1 - g0;
-    uint32_t l[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) l[r] = ok ? uint32_t(e[r] - s[r]) : 0u;
     if constexpr (MT::PAIRS) {
-      MT::run(src_k, src_v, dst_k, dst_v, s, l, g0, smem);
+      merge4_tile<MT>(src_k, src_v, dst_k, dst_v, n, W, k, part4, smem);
     } else {
-      MT::run(src_k, nullptr, dst_k, nullptr, s, l, g0, smem);
+      merge4_tile<MT>(src_k, static_cast<const VV*>(nullptr), dst_k, static_cast<VV*>(nullptr), n, W, k, part4,
+                      smem);
     }
     __syncthreads();
   }

@@ -98,7 +98,8 @@ struct SegCands {
 };
 
 struct SegLayout {
-  size_t cls_count, cls_work, large_ctr, queues, large_seg, large_mbase, desc, part, tk, tv, bytes;
+  size_t cls_count, cls_work, large_ctr, queues, large_seg, large_mbase, desc, part, part4, head, tail, tk, tv,
+      bytes;
   uint64_t mt_cap;
 };
 
@@ -118,6 +119,9 @@ SegLayout seg_layout(uint64_t nseg, uint64_t n_total) {
   L.large_mbase = take(sizeof(int64_t) * nseg);
   L.desc = take(sizeof(int4) * L.mt_cap);
   L.part = take(sizeof(int64_t) * L.mt_cap);
+  L.part4 = take(sizeof(int64_t) * 4 * L.mt_cap);
+  L.head = take(sizeof(K) * L.mt_cap);
+  L.tail = take(sizeof(K) * L.mt_cap);
   L.tk = take(sizeof(K) * n_total);
   L.tv = take(vb * n_total);
   L.bytes = o;
@@ -141,6 +145,9 @@ ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint6
   st.large_mbase = reinterpret_cast<int64_t*>(w + L.large_mbase);
   st.desc = reinterpret_cast<int4*>(w + L.desc);
   st.part = reinterpret_cast<int64_t*>(w + L.part);
+  st.part4 = reinterpret_cast<int64_t*>(w + L.part4);
+  st.head = w + L.head;
+  st.tail = w + L.tail;
   st.keys_sel = keys_sel;
   K* tk = reinterpret_cast<K*>(w + L.tk);
   V* tv = reinterpret_cast<V*>(w + L.tv);
@@ -168,21 +175,28 @@ ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint6
   if (max_len > uint64_t(S::cls_max(S::NCLS - 1))) {
     using TS = TileSort<K, V, S::LWG, S::LIPT, P::BS_PAD>;
     using MT = MergeTile<K, V, P::MG_WG, P::MG_IPT, P::MG_PAD>;
+    using M4 = Merge4Tile<K, V, P::MG_WG, P::MG_IPT, P::M4_PAD, P::M4_REUSE>;
     static const hipError_t lds_ok = [] {
       hipError_t a = seg_allow_lds(&seg_large_tile_kernel<K, V, S::LWG, S::LIPT, P::BS_PAD>, TS::LDS_BYTES);
       hipError_t b = seg_allow_lds(&seg_merge_kernel<K, V, P::MG_WG, P::MG_IPT, P::MG_PAD>, MT::LDS_BYTES);
-      return a != hipSuccess ? a : b;
+      hipError_t c = seg_allow_lds(&seg_merge4_kernel<K, V, P::MG_WG, P::MG_IPT, P::M4_PAD, P::M4_REUSE>,
+                                   M4::LDS_BYTES);
+      return a != hipSuccess ? a : (b != hipSuccess ? b : c);
     }();
     if (lds_ok != hipSuccess) return hip_fail(lds_ok, "LDS size attribute");
     // one workgroup per reserved (merge) tile up to the host-side bound
     const uint64_t tiles_cap = L.mt_cap / S::C;
     seg_large_tile_kernel<K, V, S::LWG, S::LIPT, P::BS_PAD>
         <<<dim3(unsigned(tiles_cap)), dim3(S::LWG), TS::LDS_BYTES, s>>>(keys, vals, tk, tv, st);
-    const int passes = plan_passes(max_len, S::TILE);
-    for (int p = 0; p < passes; ++p) {
-      seg_partition_kernel<K, V><<<dim3(unsigned(ceil_div(L.mt_cap, 256))), dim3(256), 0, s>>>(keys, tk, st, p);
-      seg_merge_kernel<K, V, P::MG_WG, P::MG_IPT, P::MG_PAD>
-          <<<dim3(unsigned(L.mt_cap)), dim3(P::MG_WG), MT::LDS_BYTES, s>>>(keys, vals, tk, tv, st, p);
+    const int steps = plan_hbm_passes(plan_passes(max_len, S::TILE), true);
+    for (int j = 0; j < steps; ++j) {
+      seg_partition_kernel<K, V><<<dim3(unsigned(ceil_div(L.mt_cap, 256))), dim3(256), 0, s>>>(keys, tk, st, j);
+      seg_partition4_kernel<K, V><<<dim3(unsigned(ceil_div(L.mt_cap, 256))), dim3(256), 0, s>>>(keys, tk, st, j);
+      if (j == 0)  // two-run steps occur only first
+        seg_merge_kernel<K, V, P::MG_WG, P::MG_IPT, P::MG_PAD>
+            <<<dim3(unsigned(L.mt_cap)), dim3(P::MG_WG), MT::LDS_BYTES, s>>>(keys, vals, tk, tv, st, j);
+      seg_merge4_kernel<K, V, P::MG_WG, P::MG_IPT, P::M4_PAD, P::M4_REUSE>
+          <<<dim3(unsigned(L.mt_cap)), dim3(P::MG_WG), M4::LDS_BYTES, s>>>(keys, vals, tk, tv, st, j);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "large-segment launch");

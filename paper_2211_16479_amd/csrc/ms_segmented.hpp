@@ -15,9 +15,11 @@
 //      entirely in LDS (the tile sort of ms_block_sort.hpp with the class's
 //      workgroup size and items per thread, picked by the autotuner);
 //   5. large segments: the tile sort on each tile, then merge passes bounded
-//      to the segment (runs never cross a segment end).  Segments finish after
-//      different numbers of passes, so each one picks its own buffer parity
-//      so that its last pass lands in the caller's buffer.
+//      to the segment (runs never cross a segment end): an odd level count
+//      starts with one two-run pass, the other levels go two at a time as
+//      fused four-run passes.  Segments finish after different numbers of
+//      passes, so each one picks its own buffer parity so that its last pass
+//      lands in the caller's buffer.
 #pragma once
 #include "ms_block_sort.hpp"
 #include "ms_merge.hpp"
@@ -38,6 +40,9 @@ struct SegState {
   int64_t* large_mbase;  // [nseg] first reserved merge tile per large slot
   int4* desc;            // [mt_cap] per reserved merge tile: segment base (lo, hi), length, tile index
   int64_t* part;         // [mt_cap] merge-path splits of the current pass
+  int64_t* part4;        // [4 * mt_cap] fused passes: four start offsets per merge tile
+  void* head;            // [mt_cap] keys (K) at the splits (fused passes)
+  void* tail;            // [mt_cap] keys (K) just before the splits (fused passes)
   void* const* keys_sel; // if non-null, small classes sort the key array *keys_sel (chosen on the device)
 };
 
@@ -65,6 +70,12 @@ __device__ __forceinline__ int seg_passes(uint64_t L, uint64_t T) {
   const uint64_t runs = (L + T - 1) / T;
   return 64 - __builtin_clzll(runs - 1);
 }
+
+// HBM passes of a segment with P merge levels: an odd level first as a
+// two-run pass, then the levels two at a time as fused four-run passes.
+// Step j of a segment is two-run when j < P % 2, else fused over levels
+// lv = P % 2 + 2 (j - P % 2) and lv + 1.
+__device__ __forceinline__ int seg_steps(int P) { return P / 2 + P % 2; }
 
 // Size classes of one (key, value) family: small classes have upper bounds
 // 256, 1024, 4096, 16384 (capped at the large-segment tile), larger segments
@@ -226,7 +237,7 @@ __global__ __launch_bounds__(WG) void seg_large_tile_kernel(K* __restrict__ keys
   if (j * S::TILE >= d.L) return;  // reserved but past the segment end
   const uint64_t rem = d.L - j * S::TILE;
   const uint32_t len = rem < uint64_t(S::TILE) ? uint32_t(rem) : uint32_t(S::TILE);
-  const bool to_caller = (seg_passes(d.L, S::TILE) & 1) == 0;
+  const bool to_caller = (seg_steps(seg_passes(d.L, S::TILE)) & 1) == 0;
   const uint64_t o = uint64_t(d.base) + j * S::TILE;
   if constexpr (TS::PAIRS) {
     TS::run(keys + o, vals + o, (to_caller ? keys : tk) + o, (to_caller ? vals : tv) + o, len, smem);
@@ -235,26 +246,55 @@ __global__ __launch_bounds__(WG) void seg_large_tile_kernel(K* __restrict__ keys
   }
 }
 
-// Large segments, pass p: partition (one thread per reserved merge tile).
+// Large segments, step j: partition (one thread per reserved merge tile):
+// the two-run split of a two-run step, or the samples (split, head and tail
+// keys) of a fused step.  Each segment's arrays start at its first reserved
+// merge tile.
 template <class K, class V>
 __global__ __launch_bounds__(256) void seg_partition_kernel(const K* __restrict__ keys, const K* __restrict__ tk,
-                                                            SegState st, int p) {
+                                                            SegState st, int j) {
   using S = SegCfg<K, V>;
   const uint64_t g = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (g >= ((*st.large_ctr) & SEG_TILE_MASK)) return;
   const SegTile d = seg_tile(st.desc, g);
-  const int P = seg_passes(d.L, S::TILE);
-  if (p >= P) return;
+  const int P = seg_passes(d.L, S::TILE), H = seg_steps(P), first = P & 1;
+  if (j >= H) return;
   const uint64_t g0 = d.lt * S::MTILE;
   if (g0 >= d.L) return;
-  const K* src = (((P - p) & 1) == 0 ? keys : tk) + d.base;
-  const uint64_t W = uint64_t(S::TILE) << p;
-  const PassGeom q = pass_geom(g0, d.L, W);
-  st.part[g] = int64_t(q.pb + merge_path_split(src + q.pb, q.a_end - q.pb, src + q.a_end, q.b_end - q.a_end,
-                                                g0 - q.pb));
+  const K* src = (((H - j) & 1) == 0 ? keys : tk) + d.base;
+  const uint64_t mb = g - d.lt;
+  if (j < first) {
+    const uint64_t W = uint64_t(S::TILE);
+    const PassGeom q = pass_geom(g0, d.L, W);
+    st.part[g] = int64_t(q.pb + merge_path_split(src + q.pb, q.a_end - q.pb, src + q.a_end, q.b_end - q.a_end,
+                                                  g0 - q.pb));
+  } else {
+    const uint64_t W = uint64_t(S::TILE) << (first + 2 * (j - first));
+    partition_tile(src, d.L, W, uint32_t(S::MTILE), d.lt, DevCtl{nullptr, nullptr, nullptr}, st.part + mb,
+                   static_cast<K*>(st.head) + mb, static_cast<K*>(st.tail) + mb);
+  }
 }
 
-// Large segments, pass p: merge (one workgroup per reserved merge tile).
+// Large segments, fused step j: the four-way partition of each output tile.
+template <class K, class V>
+__global__ __launch_bounds__(256) void seg_partition4_kernel(const K* __restrict__ keys, const K* __restrict__ tk,
+                                                             SegState st, int j) {
+  using S = SegCfg<K, V>;
+  const uint64_t g = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= ((*st.large_ctr) & SEG_TILE_MASK)) return;
+  const SegTile d = seg_tile(st.desc, g);
+  const int P = seg_passes(d.L, S::TILE), H = seg_steps(P), first = P & 1;
+  if (j >= H || j < first) return;
+  if (d.lt * S::MTILE >= d.L) return;
+  const K* src = (((H - j) & 1) == 0 ? keys : tk) + d.base;
+  const uint64_t mb = g - d.lt;
+  const uint64_t W = uint64_t(S::TILE) << (first + 2 * (j - first));
+  partition4_tile(src, d.L, W, uint32_t(S::MTILE), d.lt, st.part + mb, static_cast<const K*>(st.head) + mb,
+                  static_cast<const K*>(st.tail) + mb, st.part4 + 4 * mb);
+}
+
+// Large segments, two-run step p (p = 0 of an odd level count): merge (one
+// workgroup per reserved merge tile).
 template <class K, class V, int WG, int IPT, int PAD>
 __global__ __launch_bounds__(WG) void seg_merge_kernel(K* __restrict__ keys, V* __restrict__ vals,
                                                        K* __restrict__ tk, V* __restrict__ tv, SegState st, int p) {
@@ -269,15 +309,15 @@ __global__ __launch_bounds__(WG) void seg_merge_kernel(K* __restrict__ keys, V* 
   // that turn out not to be needed are ignored
   const int64_t part0 = st.part[g], part1 = st.part[g + 1];
   const SegTile d = seg_tile(st.desc, g);
-  const int P = seg_passes(d.L, S::TILE);
-  if (p >= P) return;
+  const int P = seg_passes(d.L, S::TILE), H = seg_steps(P);
+  if (p >= (P & 1)) return;  // two-run steps only (the first step of an odd level count)
   const uint64_t g0 = d.lt * S::MTILE;
   if (g0 >= d.L) return;
-  const bool from_caller = ((P - p) & 1) == 0;
+  const bool from_caller = ((H - p) & 1) == 0;
   K* sk = (from_caller ? keys : tk) + d.base;
   K* dk = (from_caller ? tk : keys) + d.base;
   const uint64_t g1 = g0 + S::MTILE < d.L ? g0 + S::MTILE : d.L;
-  const uint64_t W = uint64_t(S::TILE) << p;
+  const uint64_t W = uint64_t(S::TILE);
   const PassGeom q = pass_geom(g0, d.L, W);
   const uint64_t i0 = uint64_t(part0);
   const uint64_t j0 = q.a_end + (g0 - q.pb) - (i0 - q.pb);
@@ -295,6 +335,36 @@ __global__ __launch_bounds__(WG) void seg_merge_kernel(K* __restrict__ keys, V* 
     MT::run(sk, sv, dk, dv, i0, uint32_t(i1 - i0), j0, uint32_t(j1 - j0), g0, smem);
   } else {
     MT::template run<int>(sk, nullptr, dk, nullptr, i0, uint32_t(i1 - i0), j0, uint32_t(j1 - j0), g0, smem);
+  }
+}
+
+// Large segments, fused step j: one workgroup per reserved merge tile.
+template <class K, class V, int WG, int IPT, int PAD, int REUSE>
+__global__ __launch_bounds__(WG) void seg_merge4_kernel(K* __restrict__ keys, V* __restrict__ vals,
+                                                        K* __restrict__ tk, V* __restrict__ tv, SegState st, int j) {
+  using S = SegCfg<K, V>;
+  using MT = Merge4Tile<K, V, WG, IPT, PAD, REUSE>;
+  using VV = typename MT::VV;
+  static_assert(MT::TM == S::MTILE, "large-segment fused merge tile");
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint64_t g = blockIdx.x;
+  if (g >= ((*st.large_ctr) & SEG_TILE_MASK)) return;
+  const SegTile d = seg_tile(st.desc, g);
+  const int P = seg_passes(d.L, S::TILE), H = seg_steps(P), first = P & 1;
+  if (j >= H || j < first) return;  // workgroup-uniform
+  if (d.lt * S::MTILE >= d.L) return;
+  const bool from_caller = ((H - j) & 1) == 0;
+  const uint64_t mb = g - d.lt;
+  const uint64_t W = uint64_t(S::TILE) << (first + 2 * (j - first));
+  K* sk = (from_caller ? keys : tk) + d.base;
+  K* dk = (from_caller ? tk : keys) + d.base;
+  if constexpr (MT::PAIRS) {
+    V* sv = (from_caller ? vals : tv) + d.base;
+    V* dv = (from_caller ? tv : vals) + d.base;
+    merge4_tile<MT>(sk, sv, dk, dv, d.L, W, d.lt, st.part4 + 4 * mb, smem);
+  } else {
+    merge4_tile<MT>(sk, static_cast<const VV*>(nullptr), dk, static_cast<VV*>(nullptr), d.L, W, d.lt,
+                    st.part4 + 4 * mb, smem);
   }
 }
 
