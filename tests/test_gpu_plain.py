@@ -130,3 +130,27 @@ def test_full_uniform_u32_2p27_keys(gpu):
     ref = torch.sort(as_i64(a)).values
     assert bool((as_i64(o) == ref).all())
     check_sampled_ranks(a.cpu().numpy(), o.cpu().numpy(), samples=12, seed=3)
+
+
+@pytest.mark.parametrize("kdt,vdt", [(np.uint32, None), (np.uint32, np.uint32), (np.int64, None)],
+                         ids=["u32", "u32_pairs", "i64"])
+def test_fused_pass_run_counts(gpu, kdt, vdt):
+    """Run counts m after the tile sort that exercise every shape of the
+    fused four-run passes: full quads, a last quad of 1, 2 or 3 runs, a short
+    last run, an odd level count (one two-run pass first) and an even one."""
+    kt = {np.dtype(np.uint32): msort.MS_KEY_U32, np.dtype(np.int64): msort.MS_KEY_I64}[np.dtype(kdt)]
+    T = msort.ms_plan_query(1 << 20, kt, 0 if vdt is None else 4)["tile"]
+    rng = np.random.default_rng(31)
+    for m in (2, 3, 4, 5, 6, 7, 8, 9, 16, 17):
+        for delta in (0, 1, T // 2):
+            n = T * (m - 1) + (delta if delta else T)
+            k = keys_fill(n, kdt, "few" if m % 2 else "uniform", rng)
+            if vdt is None:
+                assert_equal_arrays(gpu_sort(k, gpu), oracle.sort(k), f"m={m} n={n}")
+            else:
+                v = np.arange(n, dtype=vdt)
+                gk, gv = gpu_sort_pairs(k, v, gpu)
+                ek, ev = oracle.sort_pairs(k, v)
+                assert_equal_arrays(gk, ek, f"keys m={m} n={n}")
+                assert_equal_arrays(gv, ev, f"values m={m} n={n}")
+
