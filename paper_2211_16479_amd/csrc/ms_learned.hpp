@@ -376,22 +376,37 @@ struct LsBins {
 // gets the sum.  Whole workgroup; ends with a barrier.
 __device__ __forceinline__ void ls_block_scan(const uint32_t* cnt, uint32_t* off, uint32_t nb, uint32_t* tmp,
                                               uint32_t* total) {
-  const int tid = threadIdx.x;
+  // each thread sums two entries; inclusive scan of those sums inside each
+  // wavefront by lane shuffles, then of the wavefront totals by the first
+  // wavefront (three barriers in all)
+  constexpr int NWV = LS_WG / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const uint32_t i0 = 2u * tid, i1 = i0 + 1;
   const uint32_t a = i0 < nb ? cnt[i0] : 0u, b = i1 < nb ? cnt[i1] : 0u;
   const uint32_t s = a + b;
-  tmp[tid] = s;
-  __syncthreads();
-  for (int d = 1; d < LS_WG; d <<= 1) {
-    const uint32_t v = tid >= d ? tmp[tid - d] : 0u;
-    __syncthreads();
-    tmp[tid] += v;
-    __syncthreads();
+  uint32_t x = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
   }
-  const uint32_t ex = tmp[tid] - s;
+  if (lane == 63) tmp[wid] = x;
+  __syncthreads();
+  if (wid == 0) {
+    uint32_t t = lane < NWV ? tmp[lane] : 0u;
+#pragma unroll
+    for (int d = 1; d < NWV; d <<= 1) {
+      const uint32_t y = __shfl_up(t, d, 64);
+      if (lane >= d) t += y;
+    }
+    if (lane < NWV) tmp[NWV + lane] = t;
+  }
+  __syncthreads();
+  const uint32_t incl = (wid ? tmp[NWV + wid - 1] : 0u) + x;
+  const uint32_t ex = incl - s;
   if (i0 < nb) off[i0] = ex;
   if (i1 < nb) off[i1] = ex + a;
-  if (tid == LS_WG - 1) *total = tmp[tid];
+  if (tid == LS_WG - 1) *total = incl;
   __syncthreads();
 }
 
