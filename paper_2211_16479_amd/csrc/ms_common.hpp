@@ -134,10 +134,10 @@ __device__ __forceinline__ Key64Pos xor_lane(const Key64Pos& v) {
 // ---------------------------------------------------- small helpers
 __host__ __device__ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
 
-// LDS index with one pad slot every 32 elements.  Merge-path threads read
-// positions about IPT/2 apart, and blocked writes are IPT apart; with power-of-
-// two strides those land in a few of the 64 LDS banks.  The pad spreads them.
 // LDS index with one pad slot every 2^S elements (S = 0: no padding).
+// Merge-path threads read positions about IPT/2 apart, and blocked writes are
+// IPT apart; with power-of-two strides those land in a few of the 64 LDS
+// banks.  The pad spreads them.
 template <int S>
 __host__ __device__ constexpr uint32_t lds_pad(uint32_t e) {
   return S ? e + (e >> S) : e;
@@ -207,6 +207,19 @@ struct DevCtl {
 };
 
 __device__ __forceinline__ bool gated_off(const DevCtl& c) { return c.gate && *c.gate == 0; }
+
+// A value the caller knows to be the same in every lane of the wavefront
+// (a tile's offsets, read at a workgroup-uniform address), moved to scalar
+// registers: the arithmetic on it then runs on the scalar unit, and branches
+// on it are uniform rather than exec-masked.
+__device__ __forceinline__ uint64_t wave_uniform(uint64_t x) {
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(x))));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(x >> 32))));
+  return (uint64_t(hi) << 32) | lo;
+}
+__device__ __forceinline__ uint32_t wave_uniform(uint32_t x) {
+  return uint32_t(__builtin_amdgcn_readfirstlane(int(x)));
+}
 __device__ __forceinline__ uint64_t live_n(const DevCtl& c, uint64_t n_host) {
   return c.n_dev ? *c.n_dev : n_host;
 }

@@ -26,9 +26,12 @@ struct PassGeom {
   uint64_t pb, a_end, b_end;  // pair base, end of run A, end of run B
 };
 
+// W, the run width of a pass, is the tile size times 2^level: a power of two
+// (a merge of two runs of arbitrary length goes through the device-side
+// split below instead).
 __device__ __forceinline__ PassGeom pass_geom(uint64_t g, uint64_t n, uint64_t W) {
   PassGeom q;
-  q.pb = (g / (2 * W)) * (2 * W);
+  q.pb = g & ~(2 * W - 1);
   q.a_end = q.pb + W < n ? q.pb + W : n;
   q.b_end = q.pb + 2 * W < n ? q.pb + 2 * W : n;
   return q;
@@ -151,6 +154,59 @@ __global__ __launch_bounds__(256) void partition_kernel(const K* __restrict__ sr
   }
 }
 
+// Stage 0 of a merge tile made of NP pieces laid back to back in the tile:
+// element e (0 <= e < c[NP]) is src[D[p] + e] for c[p] <= e < c[p+1]
+// (c[0] = 0; D[p] = piece start - c[p], unsigned wrap-around intended).
+// Thread tid stages elements e = tid + r*WG into LDS slot e.  The 64
+// consecutive elements a wavefront loads in one step usually lie in one
+// piece: the piece is then picked once per wavefront, in scalar registers,
+// and the loads are base[lane]; only a chunk that crosses a piece boundary
+// or the tile's end picks the piece per lane.  All IPT loads of a thread are
+// issued before the first LDS write waits on them.  Slots at or past c[NP]
+// receive unspecified values and are never read.
+template <int NP, int WG, int IPT, int PAD, bool PAIRS, class K, class VV>
+__device__ __forceinline__ void stage_pieces(const K* __restrict__ src_k, const VV* __restrict__ src_v,
+                                             const uint64_t (&D)[NP], const uint32_t (&c)[NP + 1],
+                                             K* __restrict__ sk, VV* __restrict__ sv) {
+  static_assert(WG % 64 == 0, "whole wavefronts");
+  const uint32_t tid = threadIdx.x, lane = tid & 63u;
+  const uint32_t wbase = wave_uniform(tid & ~63u);
+  K kv[IPT];
+  VV vv[PAIRS ? IPT : 1];
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const uint32_t cb = wbase + uint32_t(r) * WG;  // the wavefront's first element of this step
+    uint32_t pend = c[1];
+    uint64_t Dp = D[0];
+#pragma unroll
+    for (int k = 1; k < NP; ++k) {
+      if (cb >= c[k]) {
+        pend = c[k + 1];
+        Dp = D[k];
+      }
+    }
+    if (cb + 63u < pend) {  // wavefront-uniform: the chunk is inside one piece
+      kv[r] = (src_k + (Dp + cb))[lane];
+      if constexpr (PAIRS) vv[r] = (src_v + (Dp + cb))[lane];
+    } else {
+      const uint32_t e = cb + lane;
+      if (e < c[NP]) {
+        uint64_t De = D[0];
+#pragma unroll
+        for (int k = 1; k < NP; ++k) De = e >= c[k] ? D[k] : De;
+        kv[r] = src_k[De + e];
+        if constexpr (PAIRS) vv[r] = src_v[De + e];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const uint32_t e = tid + uint32_t(r) * WG;
+    sk[lds_pad<PAD>(e)] = kv[r];
+    if constexpr (PAIRS) sv[lds_pad<PAD>(e)] = vv[r];
+  }
+}
+
 template <class K, class V, int WG, int IPT, int PAD>
 struct MergeTile {
   static constexpr bool PAIRS = HasVal<V>::value;
@@ -170,44 +226,11 @@ struct MergeTile {
     K* sk = reinterpret_cast<K*>(smem);
     VV* sv = reinterpret_cast<VV*>(smem + LDS_KEYS);
     const uint32_t total = la + lb;
-    // coalesced staging of both pieces, A then B: all IPT loads of a thread
-    // are issued before any of them is waited on
-    if (total == uint32_t(TM)) {  // full tile (workgroup-uniform): no predicates
-      K kv[IPT];
-      VV vv[PAIRS ? IPT : 1];
-#pragma unroll
-      for (int r = 0; r < IPT; ++r) {
-        const uint32_t e = uint32_t(tid) + uint32_t(r) * WG;
-        const uint64_t g = e < la ? a0 + e : b0 + (e - la);
-        kv[r] = src_k[g];
-        if constexpr (PAIRS) vv[r] = src_v[g];
-      }
-#pragma unroll
-      for (int r = 0; r < IPT; ++r) {
-        const uint32_t e = uint32_t(tid) + uint32_t(r) * WG;
-        sk[lds_pad<PAD>(e)] = kv[r];
-        if constexpr (PAIRS) sv[lds_pad<PAD>(e)] = vv[r];
-      }
-    } else {
-      K kv[IPT];
-      VV vv[PAIRS ? IPT : 1];
-#pragma unroll
-      for (int r = 0; r < IPT; ++r) {
-        const uint32_t e = uint32_t(tid) + uint32_t(r) * WG;
-        if (e < total) {
-          const uint64_t g = e < la ? a0 + e : b0 + (e - la);
-          kv[r] = src_k[g];
-          if constexpr (PAIRS) vv[r] = src_v[g];
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < IPT; ++r) {
-        const uint32_t e = uint32_t(tid) + uint32_t(r) * WG;
-        if (e < total) {
-          sk[lds_pad<PAD>(e)] = kv[r];
-          if constexpr (PAIRS) sv[lds_pad<PAD>(e)] = vv[r];
-        }
-      }
+    // coalesced staging of both pieces, A then B
+    {
+      const uint64_t D[2] = {a0, b0 - la};
+      const uint32_t c[3] = {0u, la, total};
+      stage_pieces<2, WG, IPT, PAD, PAIRS>(src_k, src_v, D, c, sk, sv);
     }
     __syncthreads();
     const uint32_t d = uint32_t(tid) * IPT;
@@ -277,14 +300,14 @@ __global__ __launch_bounds__(WG) void merge_kernel(const K* __restrict__ src_k, 
     const uint64_t g0 = k * MT::TM;
     const uint64_t g1 = g0 + MT::TM < n ? g0 + MT::TM : n;
     const PassGeom q = pass_geom(g0, n, W, ctl);
-    const uint64_t i0 = uint64_t(part[k]);
+    const uint64_t i0 = wave_uniform(uint64_t(part[k]));
     const uint64_t j0 = q.a_end + (g0 - q.pb) - (i0 - q.pb);
     uint64_t i1, j1;
     if (g1 == q.b_end) {
       i1 = q.a_end;
       j1 = q.b_end;
     } else {
-      i1 = uint64_t(part[k + 1]);
+      i1 = wave_uniform(uint64_t(part[k + 1]));
       j1 = q.a_end + (g1 - q.pb) - (i1 - q.pb);
     }
     if constexpr (MT::PAIRS) {
@@ -321,7 +344,7 @@ struct QuadGeom {
 
 __device__ __forceinline__ QuadGeom quad_geom(uint64_t g, uint64_t n, uint64_t W) {
   QuadGeom q;
-  q.qb = (g / (4 * W)) * (4 * W);
+  q.qb = g & ~(4 * W - 1);  // W is a power of two
   q.r1 = q.qb + W < n ? q.qb + W : n;
   q.r2 = q.qb + 2 * W < n ? q.qb + 2 * W : n;
   q.r3 = q.qb + 3 * W < n ? q.qb + 3 * W : n;
@@ -366,52 +389,85 @@ __device__ __forceinline__ uint64_t split_at_sample(const int64_t* __restrict__ 
   return d >= L ? lp : uint64_t(part[(p0 + d) / Tm]) - p0;
 }
 
+// G lanes (a power of two dividing 64) share one search: in every round the
+// group probes positions of its interval [lo, lo + len) -- all of them when
+// len <= G, otherwise G evenly spaced ones -- and a ballot gives the first
+// probe whose predicate holds.  probe_pos is lane q's position; the group
+// helpers below are called by every lane of the group at the same time.
+template <int G>
+__device__ __forceinline__ uint64_t probe_pos(uint64_t lo, uint64_t len, uint32_t q) {
+  return len <= uint64_t(G) ? lo + q : lo + ((uint64_t(q) + 1) * len) / (G + 1);
+}
+template <int G>
+__device__ __forceinline__ uint64_t group_ballot(bool pred, uint32_t gshift) {
+  return (__ballot(pred) >> gshift) & (G == 64 ? ~0ull : ((1ull << G) - 1));
+}
+__device__ __forceinline__ uint64_t lane_value(uint64_t v, uint32_t src_lane) {
+  return uint64_t(__shfl(static_cast<unsigned long long>(v), int(src_lane), 64));
+}
+
 // For every output tile k (start g = k*Tm < n) of the fused pass at width
 // W: the start offsets of its pieces of R0..R3, written as four global
-// indices to part4[4k .. 4k+3].  One thread per tile.  x = the number of
-// X elements among the first dl outputs of merge(X, Y) is the first m with
-// Y[dl-1-m] < X[m] (X wins ties).
-//   coarse: a binary search over the sample diagonals m = j*Tm, where X[m]
-//           and Y[dl-m-1] are the recorded head and tail keys (one load
-//           each);
-//   fine:   a binary search inside the remaining sample interval; each
-//           probe finds the R0/R1 split at m and the R2/R3 split at dl - m
-//           by searches bounded by the exact splits at the current interval
-//           ends (brackets), which shrink with the interval.
-template <class K>
-__device__ __forceinline__ void partition4_tile(const K* __restrict__ src, uint64_t n, uint64_t W, uint32_t Tm,
-                                                uint64_t k, const int64_t* __restrict__ part,
-                                                const K* __restrict__ head, const K* __restrict__ tail,
-                                                int64_t* __restrict__ part4) {
+// indices to part4[4k .. 4k+3].  A group of G lanes per tile (lane q,
+// group's first lane gshift).  x = the number of X elements among the first
+// dl outputs of merge(X, Y) is the first m with Y[dl-1-m] < X[m] (X wins
+// ties).
+//   coarse: over the sample diagonals m = j*Tm, where X[m] and Y[dl-m-1]
+//           are the recorded head and tail keys (one load each per probe);
+//   fine:   inside the remaining sample interval; a probe at m finds the
+//           R0/R1 split at m and the R2/R3 split at dl - m by searches
+//           bounded by the exact splits at the interval ends (brackets);
+//           the splits found at the probes next to the chosen
+//           sub-interval become its brackets, so later searches are short.
+template <class K, int G>
+__device__ __forceinline__ void partition4_group(const K* __restrict__ src, uint64_t n, uint64_t W, uint32_t Tm,
+                                                 uint64_t k, uint32_t q, uint32_t gshift,
+                                                 const int64_t* __restrict__ part, const K* __restrict__ head,
+                                                 const K* __restrict__ tail, int64_t* __restrict__ part4) {
   const QuadGeom Q = quad_geom(k * Tm, n, W);
   const uint64_t la = Q.r1 - Q.qb, lb = Q.r2 - Q.r1, lc = Q.r3 - Q.r2, ld = Q.end - Q.r3;
   const uint64_t lx = la + lb, ly = lc + ld;
   const uint64_t dl = k * Tm - Q.qb;
   uint64_t lo = dl > ly ? dl - ly : 0, hi = dl < lx ? dl : lx;
-  // coarse
+  // coarse: J = the first sample index j in [j0, j1) whose predicate holds
+  // (j1 if none); then x lies in ((J-1)*Tm, J*Tm] clipped to [lo, hi]
   {
-    uint64_t jlo = (lo + Tm - 1) / Tm, jhi = (hi + Tm - 1) / Tm;
-    const uint64_t j0 = jlo, j1 = jhi;
+    const uint64_t j0 = (lo + Tm - 1) / Tm, j1 = (hi + Tm - 1) / Tm;
+    uint64_t jlo = j0, jhi = j1;
     while (jlo < jhi) {
-      const uint64_t j = (jlo + jhi) >> 1;
-      const uint64_t m = j * Tm, p = dl - m;  // 1 <= p <= ly
-      const K xk = head[(Q.qb + m) / Tm];
-      K yk;
-      if (p < ly) {
-        yk = tail[(Q.r2 + p) / Tm];
-      } else {  // the last element of Y
-        const K c = src[lc ? Q.r3 - 1 : Q.end - 1];
-        const K e = src[ld ? Q.end - 1 : Q.r3 - 1];
-        yk = c < e ? e : c;
+      const uint64_t len = jhi - jlo;
+      const uint64_t j = probe_pos<G>(jlo, len, q);
+      bool pred = false;
+      if (len > uint64_t(G) || q < len) {
+        const uint64_t m = j * Tm, p = dl - m;  // lo <= m < hi, so 1 <= p <= ly
+        const K xk = head[(Q.qb + m) / Tm];
+        K yk;
+        if (p < ly) {
+          yk = tail[(Q.r2 + p) / Tm];
+        } else {  // the last element of Y
+          const K c = src[lc ? Q.r3 - 1 : Q.end - 1];
+          const K e = src[ld ? Q.end - 1 : Q.r3 - 1];
+          yk = c < e ? e : c;
+        }
+        pred = yk < xk;
       }
-      if (yk < xk) jhi = j; else jlo = j + 1;
+      const uint64_t gm = group_ballot<G>(pred, gshift);
+      if (len <= uint64_t(G)) {
+        jlo = jhi = gm ? jlo + uint64_t(__builtin_ctzll(gm)) : jhi;
+      } else if (gm == 0) {
+        jlo = probe_pos<G>(jlo, len, G - 1) + 1;
+      } else {
+        const uint32_t f = uint32_t(__builtin_ctzll(gm));
+        jhi = probe_pos<G>(jlo, len, f);
+        jlo = f ? probe_pos<G>(jlo, len, f - 1) + 1 : jlo;
+      }
     }
     const uint64_t wlo = jlo > j0 ? (jlo - 1) * Tm + 1 : lo;
     const uint64_t whi = jlo < j1 ? jlo * Tm : hi;
     lo = wlo;
     hi = whi;
   }
-  // fine: [lo, hi] lies inside [k0*Tm, k0*Tm + Tm]
+  // fine: [lo, hi] lies inside [mL, mL + Tm]
   const uint64_t mL = (lo / Tm) * Tm;
   const uint64_t mR = mL + Tm < lx ? mL + Tm : lx;
   Bracket bx{mL, split_at_sample(part, Q.qb, la, lx, Tm, mL), mR, split_at_sample(part, Q.qb, la, lx, Tm, mR)};
@@ -419,33 +475,63 @@ __device__ __forceinline__ void partition4_tile(const K* __restrict__ src, uint6
   const uint64_t pL = dl > mL + Tm ? dl - mL - Tm : 0;
   Bracket by{pL, split_at_sample(part, Q.r2, lc, ly, Tm, pL), pR, split_at_sample(part, Q.r2, lc, ly, Tm, pR)};
   while (lo < hi) {
-    const uint64_t m = (lo + hi) >> 1, p = dl - m;
-    uint64_t a0, a1, c0, c1;
-    bx.bounds(m, la, lb, &a0, &a1);
-    by.bounds(p, lc, ld, &c0, &c1);
-    const uint64_t sx = split_in(src, Q.qb, Q.r1, m, a0, a1);
-    const uint64_t ty = split_in(src, Q.r2, Q.r3, p, c0, c1);
-    // X[m]: the smaller next element; Y[p-1]: the larger last taken one
-    const bool xa = sx < la, xb = m - sx < lb;
-    const K ka = src[xa ? Q.qb + sx : Q.r1 + (m - sx)];
-    const K kb = src[xb ? Q.r1 + (m - sx) : Q.qb + sx];
-    const K xk = kb < ka ? kb : ka;
-    const bool yc = ty >= 1, yd = p - ty >= 1;
-    const K kc = src[yc ? Q.r2 + ty - 1 : Q.r3 + (p - ty) - 1];
-    const K kd = src[yd ? Q.r3 + (p - ty) - 1 : Q.r2 + ty - 1];
-    const K yk = kc < kd ? kd : kc;
-    if (yk < xk) {
-      hi = m;
-      bx.dR = m;
-      bx.fR = sx;
-      by.dL = p;
-      by.fL = ty;
+    const uint64_t len = hi - lo;
+    const uint64_t m = probe_pos<G>(lo, len, q);
+    uint64_t sx = 0, ty = 0;
+    bool pred = false;
+    if (len > uint64_t(G) || q < len) {
+      const uint64_t p = dl - m;
+      uint64_t a0, a1, c0, c1;
+      bx.bounds(m, la, lb, &a0, &a1);
+      by.bounds(p, lc, ld, &c0, &c1);
+      sx = split_in(src, Q.qb, Q.r1, m, a0, a1);
+      ty = split_in(src, Q.r2, Q.r3, p, c0, c1);
+      // X[m]: the smaller next element; Y[p-1]: the larger last taken one
+      const bool xa = sx < la, xb = m - sx < lb;
+      const K ka = src[xa ? Q.qb + sx : Q.r1 + (m - sx)];
+      const K kb = src[xb ? Q.r1 + (m - sx) : Q.qb + sx];
+      const K xk = kb < ka ? kb : ka;
+      const bool yc = ty >= 1, yd = p - ty >= 1;
+      const K kc = src[yc ? Q.r2 + ty - 1 : Q.r3 + (p - ty) - 1];
+      const K kd = src[yd ? Q.r3 + (p - ty) - 1 : Q.r2 + ty - 1];
+      const K yk = kc < kd ? kd : kc;
+      pred = yk < xk;
+    }
+    const uint64_t gm = group_ballot<G>(pred, gshift);
+    // the probe chosen as the new right end (first true), and the one
+    // before it as the new left end (last true: the last probe)
+    const uint32_t f = gm ? uint32_t(__builtin_ctzll(gm)) : uint32_t(G);
+    const uint32_t fr = f < G ? f : G - 1;
+    const uint32_t fl = f ? f - 1 : 0;
+    const uint64_t sxr = lane_value(sx, gshift + fr), tyr = lane_value(ty, gshift + fr);
+    const uint64_t sxl = lane_value(sx, gshift + fl), tyl = lane_value(ty, gshift + fl);
+    if (len <= uint64_t(G)) {
+      // every position was probed: x is the first true one, else hi
+      if (gm) {
+        const uint64_t x = lo + f;
+        bx = Bracket{x, sxr, x, sxr};
+        by = Bracket{dl - x, tyr, dl - x, tyr};
+        lo = hi = x;
+      } else {
+        lo = hi;
+      }
     } else {
-      lo = m + 1;
-      bx.dL = m;
-      bx.fL = sx;
-      by.dR = p;
-      by.fR = ty;
+      if (gm) {
+        const uint64_t mr = probe_pos<G>(lo, len, f);
+        bx.dR = mr;
+        bx.fR = sxr;
+        by.dL = dl - mr;
+        by.fL = tyr;
+        hi = mr;
+      }
+      if (f) {
+        const uint64_t ml = probe_pos<G>(lo, len, fl);
+        bx.dL = ml;
+        bx.fL = sxl;
+        by.dR = dl - ml;
+        by.fR = tyl;
+        lo = ml + 1;
+      }
     }
   }
   const uint64_t x = lo;
@@ -454,39 +540,33 @@ __device__ __forceinline__ void partition4_tile(const K* __restrict__ src, uint6
   by.bounds(dl - x, lc, ld, &c0, &c1);
   const uint64_t a = split_in(src, Q.qb, Q.r1, x, a0, a1);
   const uint64_t c = split_in(src, Q.r2, Q.r3, dl - x, c0, c1);
-  part4[4 * k + 0] = int64_t(Q.qb + a);
-  part4[4 * k + 1] = int64_t(Q.r1 + (x - a));
-  part4[4 * k + 2] = int64_t(Q.r2 + c);
-  part4[4 * k + 3] = int64_t(Q.r3 + (dl - x - c));
+  if (q == 0) {
+    part4[4 * k + 0] = int64_t(Q.qb + a);
+    part4[4 * k + 1] = int64_t(Q.r1 + (x - a));
+    part4[4 * k + 2] = int64_t(Q.r2 + c);
+    part4[4 * k + 3] = int64_t(Q.r3 + (dl - x - c));
+  }
 }
 
-template <class K>
+// G lanes per output tile; the loop keeps a wavefront's lanes together so
+// that the group ballots see every lane of the group.
+template <class K, int G>
 __global__ __launch_bounds__(256) void partition4_kernel(const K* __restrict__ src, uint64_t n_host, DevCtl ctl,
                                                          uint64_t W, uint32_t Tm, uint64_t num_tiles,
                                                          const int64_t* __restrict__ part,
                                                          const K* __restrict__ head, const K* __restrict__ tail,
                                                          int64_t* __restrict__ part4) {
+  static_assert(G >= 1 && G <= 64 && (64 % G) == 0, "group size");
   if (gated_off(ctl)) return;
   const uint64_t n = live_n(ctl, n_host);
-  for (uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < num_tiles;
-       k += uint64_t(gridDim.x) * blockDim.x) {
-    if (k * Tm >= n) return;
-    partition4_tile(src, n, W, Tm, k, part, head, tail, part4);
+  const uint32_t q = threadIdx.x % G, gshift = (__lane_id() / G) * G;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t base = uint64_t(blockIdx.x) * blockDim.x; base < num_tiles * G; base += stride) {
+    const uint64_t k = (base + threadIdx.x) / G;
+    if (k < num_tiles && k * Tm < n) partition4_group<K, G>(src, n, W, Tm, k, q, gshift, part, head, tail, part4);
   }
 }
 
-// One output tile of a fused pass: pieces P0..P3 of R0..R3 (total <= TM)
-// merged as merge(merge(P0, P1), merge(P2, P3)) in LDS.
-//   stage 0: coalesced load of P0|P1|P2|P3 into buffer 1;
-//   stage 1: each thread produces IPT consecutive positions of
-//            [merge(P0, P1) | merge(P2, P3)] (a thread whose positions
-//            straddle the boundary restarts on the second merge); for
-//            pairs, each result also records where its key sits in
-//            buffer 1.  REUSE = 0 writes them to a second key buffer;
-//            REUSE = 1 holds them in registers across a barrier and writes
-//            them over buffer 1's keys (less LDS, one more barrier);
-//   stage 2: the two halves merged as in MergeTile, stored to HBM (values
-//            fetched from buffer 1 through the recorded index).
 template <class K, class V, int WG, int IPT, int PAD, int REUSE>
 struct Merge4Tile {
   static constexpr bool PAIRS = HasVal<V>::value;
@@ -510,28 +590,11 @@ struct Merge4Tile {
     K* k2 = reinterpret_cast<K*>(smem + (REUSE ? K1_OFF : K2_OFF));  // stage-1 results
     uint16_t* i2 = reinterpret_cast<uint16_t*>(smem + I2_OFF);
     const uint32_t c1 = l[0], c2 = c1 + l[1], c3 = c2 + l[2], total = c3 + l[3];
-    // stage 0 (a full tile, the usual case, needs no bounds predicates)
+    // stage 0: P0|P1|P2|P3 into buffer 1
     {
-      K kv[IPT];
-      VV vv[PAIRS ? IPT : 1];
-      const bool full = total == uint32_t(TM);
-#pragma unroll
-      for (int r = 0; r < IPT; ++r) {
-        const uint32_t e = tid + uint32_t(r) * WG;
-        if (full || e < total) {
-          const uint64_t g = e < c1 ? s[0] + e : e < c2 ? s[1] + (e - c1) : e < c3 ? s[2] + (e - c2) : s[3] + (e - c3);
-          kv[r] = src_k[g];
-          if constexpr (PAIRS) vv[r] = src_v[g];
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < IPT; ++r) {
-        const uint32_t e = tid + uint32_t(r) * WG;
-        if (full || e < total) {
-          k1[lds_pad<PAD>(e)] = kv[r];
-          if constexpr (PAIRS) v1[lds_pad<PAD>(e)] = vv[r];
-        }
-      }
+      const uint64_t D[4] = {s[0], s[1] - c1, s[2] - c2, s[3] - c3};
+      const uint32_t c[5] = {0u, c1, c2, c3, total};
+      stage_pieces<4, WG, IPT, PAD, PAIRS>(src_k, src_v, D, c, k1, v1);
     }
     __syncthreads();
     const uint32_t e0 = tid * IPT;
@@ -662,7 +725,7 @@ __device__ __forceinline__ void merge4_tile(const K* __restrict__ src_k, const V
   const QuadGeom Q = quad_geom(g0, n, W);
   uint64_t s[4], e[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) s[r] = uint64_t(part4[4 * k + r]);
+  for (int r = 0; r < 4; ++r) s[r] = wave_uniform(uint64_t(part4[4 * k + r]));
   if (g1 == Q.end) {
     e[0] = Q.r1;
     e[1] = Q.r2;
@@ -670,7 +733,7 @@ __device__ __forceinline__ void merge4_tile(const K* __restrict__ src_k, const V
     e[3] = Q.end;
   } else {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) e[r] = uint64_t(part4[4 * (k + 1) + r]);
+    for (int r = 0; r < 4; ++r) e[r] = wave_uniform(uint64_t(part4[4 * (k + 1) + r]));
   }
   // offsets that do not describe four in-run pieces filling the tile are
   // never dereferenced (the tile is skipped); exact partitions always pass

@@ -99,8 +99,9 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
       partition_samples(W, C::M4TILE);
       {
         ProfScope ps(PK_PARTITION4, s);
-        partition4_kernel<K><<<dim3(unsigned(std::min(ceil_div(mt4, 256), cap))), dim3(256), 0, s>>>(
-            cur_k, n, ctl, W, C::M4TILE, mt4, part, head, tail, part4);
+        partition4_kernel<K, MS_PART4_G>
+            <<<dim3(unsigned(std::min(ceil_div(mt4 * MS_PART4_G, 256), cap))), dim3(256), 0, s>>>(
+                cur_k, n, ctl, W, C::M4TILE, mt4, part, head, tail, part4);
       }
       {
         ProfScope ps(PK_MERGE4, s);
@@ -134,6 +135,12 @@ ms_status merge_two_runs(const K* src, K* dst, uint64_t n, DevCtl ctl, int64_t* 
   using C = PlainCfg<K, V>;
   using MT = MergeTile<K, V, C::MG_WG, C::MG_IPT, C::MG_PAD>;
   static_assert(!C::PAIRS, "keys only");
+  // the run boundary comes from the device (pass widths are powers of two
+  // everywhere else, and the kernels' pass geometry relies on that)
+  if (!ctl.split_dev) {
+    set_error("two-run merge needs a device-side split");
+    return MS_ERR_INVALID_ARG;
+  }
   if (n == 0) return MS_OK;
   const uint64_t mtiles = ceil_div(n, C::MTILE);
   const uint64_t cap = max_grid ? max_grid : ~uint64_t(0);

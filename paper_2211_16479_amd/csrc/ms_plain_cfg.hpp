@@ -15,6 +15,9 @@ namespace ms {
 #ifndef MS_PART_G
 #define MS_PART_G 1  // lanes per partition search (1 = binary search)
 #endif
+#ifndef MS_PART4_G
+#define MS_PART4_G 1  // lanes per fused-pass (four-run) partition search
+#endif
 #ifndef MS_BS_WG_K
 #define MS_BS_WG_K 1024
 #endif

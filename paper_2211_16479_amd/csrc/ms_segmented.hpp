@@ -62,6 +62,16 @@ __device__ __forceinline__ SegTile seg_tile(const int4* desc, uint64_t g) {
   return t;
 }
 
+// The same for a tile index that is one per workgroup (g the same in every
+// lane): the fields go to scalar registers.
+__device__ __forceinline__ SegTile seg_tile_wg(const int4* desc, uint64_t g) {
+  SegTile t = seg_tile(desc, g);
+  t.base = int64_t(wave_uniform(uint64_t(t.base)));
+  t.L = wave_uniform(t.L);
+  t.lt = wave_uniform(t.lt);
+  return t;
+}
+
 constexpr unsigned long long SEG_SLOT_SHIFT = 40;
 constexpr unsigned long long SEG_TILE_MASK = (1ull << SEG_SLOT_SHIFT) - 1;
 
@@ -276,12 +286,13 @@ __global__ __launch_bounds__(256) void seg_partition_kernel(const K* __restrict_
 }
 
 // Large segments, fused step j: the four-way partition of each output tile.
-template <class K, class V>
+template <class K, class V, int G>
 __global__ __launch_bounds__(256) void seg_partition4_kernel(const K* __restrict__ keys, const K* __restrict__ tk,
                                                              SegState st, int j) {
   using S = SegCfg<K, V>;
-  const uint64_t g = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (g >= ((*st.large_ctr) & SEG_TILE_MASK)) return;
+  const uint64_t g = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) / G;  // one tile per group of G lanes
+  const uint32_t q = threadIdx.x % G, gshift = (__lane_id() / G) * G;
+  if (g >= ((*st.large_ctr) & SEG_TILE_MASK)) return;  // group-uniform
   const SegTile d = seg_tile(st.desc, g);
   const int P = seg_passes(d.L, S::TILE), H = seg_steps(P), first = P & 1;
   if (j >= H || j < first) return;
@@ -289,8 +300,9 @@ __global__ __launch_bounds__(256) void seg_partition4_kernel(const K* __restrict
   const K* src = (((H - j) & 1) == 0 ? keys : tk) + d.base;
   const uint64_t mb = g - d.lt;
   const uint64_t W = uint64_t(S::TILE) << (first + 2 * (j - first));
-  partition4_tile(src, d.L, W, uint32_t(S::MTILE), d.lt, st.part + mb, static_cast<const K*>(st.head) + mb,
-                  static_cast<const K*>(st.tail) + mb, st.part4 + 4 * mb);
+  partition4_group<K, G>(src, d.L, W, uint32_t(S::MTILE), d.lt, q, gshift, st.part + mb,
+                         static_cast<const K*>(st.head) + mb, static_cast<const K*>(st.tail) + mb,
+                         st.part4 + 4 * mb);
 }
 
 // Large segments, two-run step p (p = 0 of an odd level count): merge (one
@@ -308,7 +320,7 @@ __global__ __launch_bounds__(WG) void seg_merge_kernel(K* __restrict__ keys, V* 
   // inside the scratch arrays: g + 1 < reserved tiles + C <= mt_cap); values
   // that turn out not to be needed are ignored
   const int64_t part0 = st.part[g], part1 = st.part[g + 1];
-  const SegTile d = seg_tile(st.desc, g);
+  const SegTile d = seg_tile_wg(st.desc, g);
   const int P = seg_passes(d.L, S::TILE), H = seg_steps(P);
   if (p >= (P & 1)) return;  // two-run steps only (the first step of an odd level count)
   const uint64_t g0 = d.lt * S::MTILE;
@@ -319,14 +331,14 @@ __global__ __launch_bounds__(WG) void seg_merge_kernel(K* __restrict__ keys, V* 
   const uint64_t g1 = g0 + S::MTILE < d.L ? g0 + S::MTILE : d.L;
   const uint64_t W = uint64_t(S::TILE);
   const PassGeom q = pass_geom(g0, d.L, W);
-  const uint64_t i0 = uint64_t(part0);
+  const uint64_t i0 = wave_uniform(uint64_t(part0));
   const uint64_t j0 = q.a_end + (g0 - q.pb) - (i0 - q.pb);
   uint64_t i1, j1;
   if (g1 == q.b_end) {
     i1 = q.a_end;
     j1 = q.b_end;
   } else {
-    i1 = uint64_t(part1);
+    i1 = wave_uniform(uint64_t(part1));
     j1 = q.a_end + (g1 - q.pb) - (i1 - q.pb);
   }
   if constexpr (MT::PAIRS) {
@@ -349,7 +361,7 @@ __global__ __launch_bounds__(WG) void seg_merge4_kernel(K* __restrict__ keys, V*
   extern __shared__ __align__(16) unsigned char smem[];
   const uint64_t g = blockIdx.x;
   if (g >= ((*st.large_ctr) & SEG_TILE_MASK)) return;
-  const SegTile d = seg_tile(st.desc, g);
+  const SegTile d = seg_tile_wg(st.desc, g);
   const int P = seg_passes(d.L, S::TILE), H = seg_steps(P), first = P & 1;
   if (j >= H || j < first) return;  // workgroup-uniform
   if (d.lt * S::MTILE >= d.L) return;
