@@ -25,7 +25,16 @@ namespace ms {
 #define MS_BS_IPT_K 32
 #endif
 #ifndef MS_BS_PAD_K
-#define MS_BS_PAD_K 0
+#define MS_BS_PAD_K 5
+#endif
+// LDS pad of the batched segmented sort's tile sorts for 32-bit keys only
+// (small-segment classes, then the large-segment tile), tuned apart from the
+// plain sort's 1024 x 32 tile
+#ifndef MS_SEG_PAD_K
+#define MS_SEG_PAD_K 0
+#endif
+#ifndef MS_SEG_LPAD_K
+#define MS_SEG_LPAD_K 0
 #endif
 #ifndef MS_MG_WG_K
 #define MS_MG_WG_K 256
@@ -116,6 +125,8 @@ struct PlainCfg {
   static constexpr int BS_WG = WIDE ? MS_BS_WG_W : (PAIRS ? MS_BS_WG_P : MS_BS_WG_K);
   static constexpr int BS_IPT = WIDE ? (PAIRS ? 8 : MS_BS_IPT_W) : (PAIRS ? MS_BS_IPT_P : MS_BS_IPT_K);
   static constexpr int BS_PAD = WIDE ? MS_PAD_W : (PAIRS ? MS_BS_PAD_P : MS_BS_PAD_K);
+  static constexpr int SEG_PAD = WIDE ? MS_PAD_W : (PAIRS ? MS_BS_PAD_P : MS_SEG_PAD_K);
+  static constexpr int SEG_LPAD = WIDE ? MS_PAD_W : (PAIRS ? MS_BS_PAD_P : MS_SEG_LPAD_K);
   static constexpr int MG_WG = WIDE ? MS_MG_WG_W : (PAIRS ? MS_MG_WG_P : MS_MG_WG_K);
   static constexpr int MG_IPT = WIDE ? MS_MG_IPT_W : (PAIRS ? MS_MG_IPT_P : MS_MG_IPT_K);
   static constexpr int MG_PAD = WIDE ? MS_PAD_W : (PAIRS ? MS_MG_PAD_P : MS_MG_PAD_K);

@@ -22,7 +22,7 @@ int device_cu_count();
 template <class K, class V, int WG, int IPT>
 static hipError_t launch_small(K* keys, V* vals, const int64_t* off, SegState st, int cls, uint64_t nseg,
                                hipStream_t s) {
-  constexpr int PAD = PlainCfg<K, V>::BS_PAD;
+  constexpr int PAD = PlainCfg<K, V>::SEG_PAD;
   using TS = TileSort<K, V, WG, IPT, PAD>;
   static const hipError_t ok = seg_allow_lds(&seg_small_kernel<K, V, WG, IPT, PAD>, TS::LDS_BYTES);
   if (ok != hipSuccess) return ok;
@@ -173,11 +173,11 @@ ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint6
   // segments longer than the last small class take the large path (a tile
   // sort, then merge passes when they span several tiles)
   if (max_len > uint64_t(S::cls_max(S::NCLS - 1))) {
-    using TS = TileSort<K, V, S::LWG, S::LIPT, P::BS_PAD>;
+    using TS = TileSort<K, V, S::LWG, S::LIPT, P::SEG_LPAD>;
     using MT = MergeTile<K, V, P::MG_WG, P::MG_IPT, P::MG_PAD>;
     using M4 = Merge4Tile<K, V, P::MG_WG, P::MG_IPT, P::M4_PAD, P::M4_REUSE>;
     static const hipError_t lds_ok = [] {
-      hipError_t a = seg_allow_lds(&seg_large_tile_kernel<K, V, S::LWG, S::LIPT, P::BS_PAD>, TS::LDS_BYTES);
+      hipError_t a = seg_allow_lds(&seg_large_tile_kernel<K, V, S::LWG, S::LIPT, P::SEG_LPAD>, TS::LDS_BYTES);
       hipError_t b = seg_allow_lds(&seg_merge_kernel<K, V, P::MG_WG, P::MG_IPT, P::MG_PAD>, MT::LDS_BYTES);
       hipError_t c = seg_allow_lds(&seg_merge4_kernel<K, V, P::MG_WG, P::MG_IPT, P::M4_PAD, P::M4_REUSE>,
                                    M4::LDS_BYTES);
@@ -186,7 +186,7 @@ ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint6
     if (lds_ok != hipSuccess) return hip_fail(lds_ok, "LDS size attribute");
     // one workgroup per reserved (merge) tile up to the host-side bound
     const uint64_t tiles_cap = L.mt_cap / S::C;
-    seg_large_tile_kernel<K, V, S::LWG, S::LIPT, P::BS_PAD>
+    seg_large_tile_kernel<K, V, S::LWG, S::LIPT, P::SEG_LPAD>
         <<<dim3(unsigned(tiles_cap)), dim3(S::LWG), TS::LDS_BYTES, s>>>(keys, vals, tk, tv, st);
     const int steps = plan_hbm_passes(plan_passes(max_len, S::TILE), true);
     for (int j = 0; j < steps; ++j) {
