@@ -652,12 +652,29 @@ struct Merge4Tile {
     }
     if constexpr (REUSE) {
       __syncthreads();  // every stage-1 read of buffer 1's keys is done
+      if (PAD == 0 && (IPT * sizeof(K)) % 16 == 0 && IPT % 8 == 0 && e0 + uint32_t(IPT) <= total) {
+        // unpadded: a thread's IPT results are consecutive, written as 16-byte
+        // vectors (scalar writes at a stride of IPT words conflict on banks)
+        store_run<K, IPT>(k2 + e0, ko1);
+        if constexpr (PAIRS) {
 #pragma unroll
-      for (int r = 0; r < IPT; ++r)
-        if (e0 + uint32_t(r) < total) {
-          k2[lds_pad<PAD>(e0 + r)] = ko1[r];
-          if constexpr (PAIRS) i2[lds_pad<PAD>(e0 + r)] = io1[r];
+          for (int r = 0; r < IPT; r += 8) {
+            uint4 w;
+            w.x = uint32_t(io1[r]) | (uint32_t(io1[r + 1]) << 16);
+            w.y = uint32_t(io1[r + 2]) | (uint32_t(io1[r + 3]) << 16);
+            w.z = uint32_t(io1[r + 4]) | (uint32_t(io1[r + 5]) << 16);
+            w.w = uint32_t(io1[r + 6]) | (uint32_t(io1[r + 7]) << 16);
+            *reinterpret_cast<uint4*>(i2 + e0 + r) = w;
+          }
         }
+      } else {
+#pragma unroll
+        for (int r = 0; r < IPT; ++r)
+          if (e0 + uint32_t(r) < total) {
+            k2[lds_pad<PAD>(e0 + r)] = ko1[r];
+            if constexpr (PAIRS) i2[lds_pad<PAD>(e0 + r)] = io1[r];
+          }
+      }
     }
     __syncthreads();
     // stage 2: A = k2[0, c2), B = k2[c2, total)

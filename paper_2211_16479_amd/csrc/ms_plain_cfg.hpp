@@ -99,7 +99,7 @@ namespace ms {
 #define MS_M4_IPT_P 8
 #endif
 #ifndef MS_M4_PAD_P
-#define MS_M4_PAD_P 5
+#define MS_M4_PAD_P 0
 #endif
 #ifndef MS_M4_WG_W
 #define MS_M4_WG_W 512
