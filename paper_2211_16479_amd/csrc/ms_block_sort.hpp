@@ -270,8 +270,6 @@ struct TileSort {
   }
 };
 
-// Tiles [t*TILE, min(n, (t+1)*TILE)); workgroup b takes tiles b, b + grid, ...
-// (one tile each when the grid covers them all).
 // Waves per SIMD the tile sort is compiled for.  32-bit keys with values
 // would otherwise take 196 VGPRs (2 waves per SIMD); capped at 168 they run
 // 3 waves with a few spilled registers, which measured faster.  The other
@@ -283,10 +281,12 @@ template <class K, class V>
 constexpr int bs_waves_per_eu() {
   return (HasVal<V>::value && sizeof(K) == 4) ? MS_BS_WAVES_P : (HasVal<V>::value ? 3 : 4);
 }
+
+// Tiles [t*TILE, min(n, (t+1)*TILE)); workgroup b takes tiles b, b + grid, ...
+// (one tile each when the grid covers them all).
 template <class K, class V, int WG, int IPT, int PAD>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(bs_waves_per_eu<K, V>())))
-void block_sort_kernel(const K* in_k, const V* in_v, K* out_k, V* out_v,
-                                                        uint64_t n_host, DevCtl ctl) {
+void block_sort_kernel(const K* in_k, const V* in_v, K* out_k, V* out_v, uint64_t n_host, DevCtl ctl) {
   using TS = TileSort<K, V, WG, IPT, PAD>;
   extern __shared__ __align__(16) unsigned char smem[];
   if (gated_off(ctl)) return;
