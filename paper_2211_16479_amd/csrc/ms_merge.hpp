@@ -59,44 +59,89 @@ __device__ __forceinline__ uint64_t merge_path_split(const K* A, uint64_t la, co
   return lo;
 }
 
-// One search per merge tile.  G = 1: one thread runs the binary search.
-// G > 1: G lanes cooperate on one diagonal; each round they probe G evenly
-// spaced positions of the remaining interval [lo, hi) and a ballot picks the
-// sub-interval holding the split, so the interval shrinks by G + 1 per round
-// (fewer dependent global loads).  Both use the same predicate:
-// split <= m  iff  B[d-1-m] < A[m].
-//
-// With head/tail non-null (G == 1), the kernel also records the keys around
-// each split: head[k] = the pair's merged output at diagonal d (the smaller
-// of the two next elements), tail[k] = the output just before it (the larger
-// of the two last taken; undefined at d = 0).
-// The split of merge tile k (start g = k*Tm < n) of its pair, and with
-// head / tail non-null the keys around it (see partition_kernel).
+// G lanes (a power of two dividing 64) share one search: in every round the
+// group probes positions of its interval [lo, lo + len) -- all of them when
+// len <= G, otherwise G evenly spaced ones -- and a ballot gives the first
+// probe whose predicate holds.  probe_pos is lane q's position; the group
+// helpers below are called by every lane of the group at the same time.
+template <int G>
+__device__ __forceinline__ uint64_t probe_pos(uint64_t lo, uint64_t len, uint32_t q) {
+  return len <= uint64_t(G) ? lo + q : lo + ((uint64_t(q) + 1) * len) / (G + 1);
+}
+template <int G>
+__device__ __forceinline__ uint64_t group_ballot(bool pred, uint32_t gshift) {
+  return (__ballot(pred) >> gshift) & (G == 64 ? ~0ull : ((1ull << G) - 1));
+}
+__device__ __forceinline__ uint64_t lane_value(uint64_t v, uint32_t src_lane) {
+  return uint64_t(__shfl(static_cast<unsigned long long>(v), int(src_lane), 64));
+}
+
+// The keys around a two-run split i at diagonal d of pair q (merge tile k):
+// head[k] = the pair's merged output at d (the smaller of the two next
+// elements), tail[k] = the output just before it (the larger of the two last
+// taken; left unwritten at d = 0).  d < the pair's length, so at least one
+// next element exists; the index fallbacks only ever name existing elements.
 template <class K>
-__device__ __forceinline__ void partition_tile(const K* __restrict__ src, uint64_t n, uint64_t W, uint32_t Tm,
-                                               uint64_t k, const DevCtl& ctl, int64_t* __restrict__ part,
-                                               K* __restrict__ head, K* __restrict__ tail) {
-  const uint64_t g = k * Tm;
-  const PassGeom q = pass_geom(g, n, W, ctl);
-  const uint64_t la = q.a_end - q.pb, lb = q.b_end - q.a_end, d = g - q.pb;
-  const uint64_t i = merge_path_split(src + q.pb, la, src + q.a_end, lb, d);
-  part[k] = int64_t(q.pb + i);
-  if (head) {
-    // d < la + lb, so at least one next element exists; the index
-    // fallbacks below only ever name an existing element
-    const bool na = i < la, nb = d - i < lb;
-    const K x0 = src[na ? q.pb + i : q.a_end + (d - i)];
-    const K x1 = src[nb ? q.a_end + (d - i) : q.pb + i];
-    head[k] = x1 < x0 ? x1 : x0;
-    const bool pa = i >= 1, pbv = d - i >= 1;
-    if (pa || pbv) {
-      const K y0 = src[pa ? q.pb + i - 1 : q.a_end + (d - i) - 1];
-      const K y1 = src[pbv ? q.a_end + (d - i) - 1 : q.pb + i - 1];
-      tail[k] = y0 < y1 ? y1 : y0;
-    }
+__device__ __forceinline__ void record_split_keys(const K* __restrict__ src, const PassGeom& q, uint64_t d,
+                                                  uint64_t i, uint64_t k, K* __restrict__ head,
+                                                  K* __restrict__ tail) {
+  const uint64_t la = q.a_end - q.pb, lb = q.b_end - q.a_end;
+  const bool na = i < la, nb = d - i < lb;
+  const K x0 = src[na ? q.pb + i : q.a_end + (d - i)];
+  const K x1 = src[nb ? q.a_end + (d - i) : q.pb + i];
+  head[k] = x1 < x0 ? x1 : x0;
+  const bool pa = i >= 1, pbv = d - i >= 1;
+  if (pa || pbv) {
+    const K y0 = src[pa ? q.pb + i - 1 : q.a_end + (d - i) - 1];
+    const K y1 = src[pbv ? q.a_end + (d - i) - 1 : q.pb + i - 1];
+    tail[k] = y0 < y1 ? y1 : y0;
   }
 }
 
+// The split of merge tile k (start g = k*Tm < n) of its pair, written to
+// part[k], and with head / tail non-null the keys around it.  A group of G
+// lanes (lane q, group's first lane gshift) shares the search: each round
+// probes G positions of the remaining interval (all of them once it is at
+// most G long) and a ballot picks the sub-interval holding the split, which
+// is the first m with B[d-1-m] < A[m].  G = 1 is the binary search.
+template <class K, int G>
+__device__ __forceinline__ void partition_group(const K* __restrict__ src, uint64_t n, uint64_t W, uint32_t Tm,
+                                                uint64_t k, const DevCtl& ctl, uint32_t q, uint32_t gshift,
+                                                int64_t* __restrict__ part, K* __restrict__ head,
+                                                K* __restrict__ tail) {
+  const uint64_t g = k * Tm;
+  const PassGeom geo = pass_geom(g, n, W, ctl);
+  const uint64_t la = geo.a_end - geo.pb, lb = geo.b_end - geo.a_end, d = g - geo.pb;
+  const K* A = src + geo.pb;
+  const K* B = src + geo.a_end;
+  uint64_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
+  if constexpr (G == 1) {
+    lo = merge_path_split(A, la, B, lb, d);
+  } else {
+    while (lo < hi) {  // the same bounds in every lane of the group
+      const uint64_t len = hi - lo;
+      const uint64_t m = probe_pos<G>(lo, len, q);  // lo <= m < hi
+      const bool pred = (len > uint64_t(G) || q < len) && (B[d - 1 - m] < A[m]);
+      const uint64_t gm = group_ballot<G>(pred, gshift);
+      if (len <= uint64_t(G)) {
+        lo = hi = gm ? lo + uint64_t(__builtin_ctzll(gm)) : hi;
+      } else if (gm == 0) {
+        lo = probe_pos<G>(lo, len, G - 1) + 1;
+      } else {
+        const uint32_t f = uint32_t(__builtin_ctzll(gm));
+        hi = probe_pos<G>(lo, len, f);
+        lo = f ? probe_pos<G>(lo, len, f - 1) + 1 : lo;
+      }
+    }
+  }
+  if (q == 0) {
+    part[k] = int64_t(geo.pb + lo);
+    if (head) record_split_keys(src, geo, d, lo, k, head, tail);
+  }
+}
+
+// One search per merge tile, G lanes each; the loop keeps a wavefront's
+// lanes together so that the group ballots see every lane of the group.
 template <class K, int G>
 __global__ __launch_bounds__(256) void partition_kernel(const K* __restrict__ src, uint64_t n_host, DevCtl ctl,
                                                         uint64_t W, uint32_t Tm, uint64_t num_tiles,
@@ -105,52 +150,11 @@ __global__ __launch_bounds__(256) void partition_kernel(const K* __restrict__ sr
   static_assert(G >= 1 && G <= 64 && (64 % G) == 0, "group size");
   if (gated_off(ctl)) return;
   const uint64_t n = live_n(ctl, n_host);
-  const uint64_t gid = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const uint64_t k = gid / G;
-  if constexpr (G == 1) {
-    for (uint64_t kk = gid; kk < num_tiles; kk += uint64_t(gridDim.x) * blockDim.x) {
-      if (kk * Tm >= n) return;
-      partition_tile(src, n, W, Tm, kk, ctl, part, head, tail);
-    }
-  } else {
-    const uint32_t q = uint32_t(gid % G);
-    const uint32_t gshift = (__lane_id() / G) * G;
-    const bool valid = k < num_tiles && k * Tm < n;
-    uint64_t lo = 0, hi = 0, d = 0;
-    const K* A = src;
-    const K* B = src;
-    PassGeom geo{0, 0, 0};
-    if (valid) {
-      geo = pass_geom(k * Tm, n, W, ctl);
-      const uint64_t la = geo.a_end - geo.pb, lb = geo.b_end - geo.a_end;
-      d = k * Tm - geo.pb;
-      A = src + geo.pb;
-      B = src + geo.a_end;
-      lo = d > lb ? d - lb : 0;
-      hi = d < la ? d : la;
-    }
-    while (true) {
-      const bool active = valid && lo < hi;
-      if (!__any(active)) break;
-      const uint64_t len = hi - lo;
-      const bool small = len <= G;
-      const uint64_t m = small ? lo + q : lo + ((q + 1) * len) / (G + 1);
-      const bool probe = active && (!small || q < len);
-      const bool pred = probe && (B[d - 1 - m] < A[m]);
-      const uint32_t gm = uint32_t((__ballot(pred) >> gshift) & ((G == 64) ? ~0ull : ((1ull << G) - 1)));
-      if (active) {
-        if (small) {
-          lo = hi = lo + (gm ? uint64_t(__builtin_ctz(gm)) : len);
-        } else if (gm == 0) {
-          lo = lo + (uint64_t(G) * len) / (G + 1) + 1;
-        } else {
-          const uint32_t f = __builtin_ctz(gm);
-          hi = lo + ((f + 1) * len) / (G + 1);
-          lo = f ? lo + (uint64_t(f) * len) / (G + 1) + 1 : lo;
-        }
-      }
-    }
-    if (valid && q == 0) part[k] = int64_t(geo.pb + lo);
+  const uint32_t q = threadIdx.x % G, gshift = (__lane_id() / G) * G;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t base = uint64_t(blockIdx.x) * blockDim.x; base < num_tiles * G; base += stride) {
+    const uint64_t k = (base + threadIdx.x) / G;
+    if (k < num_tiles && k * Tm < n) partition_group<K, G>(src, n, W, Tm, k, ctl, q, gshift, part, head, tail);
   }
 }
 
@@ -387,23 +391,6 @@ struct Bracket {
 __device__ __forceinline__ uint64_t split_at_sample(const int64_t* __restrict__ part, uint64_t p0, uint64_t lp,
                                                     uint64_t L, uint32_t Tm, uint64_t d) {
   return d >= L ? lp : uint64_t(part[(p0 + d) / Tm]) - p0;
-}
-
-// G lanes (a power of two dividing 64) share one search: in every round the
-// group probes positions of its interval [lo, lo + len) -- all of them when
-// len <= G, otherwise G evenly spaced ones -- and a ballot gives the first
-// probe whose predicate holds.  probe_pos is lane q's position; the group
-// helpers below are called by every lane of the group at the same time.
-template <int G>
-__device__ __forceinline__ uint64_t probe_pos(uint64_t lo, uint64_t len, uint32_t q) {
-  return len <= uint64_t(G) ? lo + q : lo + ((uint64_t(q) + 1) * len) / (G + 1);
-}
-template <int G>
-__device__ __forceinline__ uint64_t group_ballot(bool pred, uint32_t gshift) {
-  return (__ballot(pred) >> gshift) & (G == 64 ? ~0ull : ((1ull << G) - 1));
-}
-__device__ __forceinline__ uint64_t lane_value(uint64_t v, uint32_t src_lane) {
-  return uint64_t(__shfl(static_cast<unsigned long long>(v), int(src_lane), 64));
 }
 
 // For every output tile k (start g = k*Tm < n) of the fused pass at width

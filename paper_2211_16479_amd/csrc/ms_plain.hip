@@ -28,6 +28,26 @@ void plain_geometry(int* tile, int* merge_tile, int* merge4_tile, int* fused) {
   *fused = PlainCfg<K, V>::FUSED ? 1 : 0;
 }
 
+// Lanes per partition search.  With few searches, groups of G lanes fill the
+// chip and each search takes fewer dependent rounds; with many, one lane
+// each, since a group multiplies the scattered line fetches that bound the
+// kernels there.  Measured best on MI355X: the largest G of 1, 4, 16, 64
+// that keeps a launch at or below 2^16 lanes (2^20 u32 keys: four-way
+// partition 60 -> 15 us; 2^27: one lane).
+static int search_group(uint64_t searches) {
+  const uint64_t lanes = uint64_t(1) << 16;
+  return searches * 64 <= lanes ? 64 : searches * 16 <= lanes ? 16 : searches * 4 <= lanes ? 4 : 1;
+}
+template <class F>
+static void with_search_group(int g, F&& f) {
+  switch (g) {
+    case 64: f(std::integral_constant<int, 64>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    default: f(std::integral_constant<int, 1>{}); break;
+  }
+}
+
 template <class K, class V>
 size_t plain_temp_bytes(uint64_t n) {
   using C = PlainCfg<K, V>;
@@ -74,17 +94,15 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "tile sort launch");
-  auto partition = [&](uint64_t W, uint32_t Tm) {
+  // splits at every Tm outputs of each pair; with_keys: the keys around them too
+  auto partition = [&](uint64_t W, uint32_t Tm, bool with_keys) {
     const uint64_t nt = ceil_div(n, Tm);
     ProfScope ps(PK_PARTITION, s);
-    partition_kernel<K, MS_PART_G><<<dim3(unsigned(std::min(ceil_div(nt * MS_PART_G, 256), cap))), dim3(256), 0,
-                                     s>>>(cur_k, n, ctl, W, Tm, nt, part);
-  };
-  auto partition_samples = [&](uint64_t W, uint32_t Tm) {  // splits plus head/tail keys
-    const uint64_t nt = ceil_div(n, Tm);
-    ProfScope ps(PK_PARTITION, s);
-    partition_kernel<K, 1><<<dim3(unsigned(std::min(ceil_div(nt, 256), cap))), dim3(256), 0, s>>>(
-        cur_k, n, ctl, W, Tm, nt, part, head, tail);
+    with_search_group(search_group(nt), [&](auto gc) {
+      constexpr int G = decltype(gc)::value;
+      partition_kernel<K, G><<<dim3(unsigned(std::min(ceil_div(nt * G, 256), cap))), dim3(256), 0, s>>>(
+          cur_k, n, ctl, W, Tm, nt, part, with_keys ? head : nullptr, with_keys ? tail : nullptr);
+    });
   };
   // levels p (width W = T * 2^p): an odd level count starts with one two-run
   // pass, then every fused pass takes two levels
@@ -96,12 +114,14 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
     const bool fuse = C::FUSED && (P - p) % 2 == 0;
     if (fuse) {
       const uint64_t mt4 = ceil_div(n, C::M4TILE);
-      partition_samples(W, C::M4TILE);
+      partition(W, C::M4TILE, true);
       {
         ProfScope ps(PK_PARTITION4, s);
-        partition4_kernel<K, MS_PART4_G>
-            <<<dim3(unsigned(std::min(ceil_div(mt4 * MS_PART4_G, 256), cap))), dim3(256), 0, s>>>(
-                cur_k, n, ctl, W, C::M4TILE, mt4, part, head, tail, part4);
+        with_search_group(search_group(mt4), [&](auto gc) {
+          constexpr int G = decltype(gc)::value;
+          partition4_kernel<K, G><<<dim3(unsigned(std::min(ceil_div(mt4 * G, 256), cap))), dim3(256), 0, s>>>(
+              cur_k, n, ctl, W, C::M4TILE, mt4, part, head, tail, part4);
+        });
       }
       {
         ProfScope ps(PK_MERGE4, s);
@@ -112,7 +132,7 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
       p += 2;
     } else {
       const uint64_t mtiles = ceil_div(n, C::MTILE);
-      partition(W, C::MTILE);
+      partition(W, C::MTILE, false);
       {
         ProfScope ps(PK_MERGE, s);
         merge_kernel<K, V, C::MG_WG, C::MG_IPT, C::MG_PAD>
@@ -144,8 +164,11 @@ ms_status merge_two_runs(const K* src, K* dst, uint64_t n, DevCtl ctl, int64_t* 
   if (n == 0) return MS_OK;
   const uint64_t mtiles = ceil_div(n, C::MTILE);
   const uint64_t cap = max_grid ? max_grid : ~uint64_t(0);
-  partition_kernel<K, MS_PART_G><<<dim3(unsigned(std::min(ceil_div(mtiles * MS_PART_G, 256), cap))), dim3(256), 0,
-                                   s>>>(src, n, ctl, n, C::MTILE, mtiles, part);
+  with_search_group(search_group(mtiles), [&](auto gc) {
+    constexpr int G = decltype(gc)::value;
+    partition_kernel<K, G><<<dim3(unsigned(std::min(ceil_div(mtiles * G, 256), cap))), dim3(256), 0, s>>>(
+        src, n, ctl, n, C::MTILE, mtiles, part);
+  });
   merge_kernel<K, V, C::MG_WG, C::MG_IPT, C::MG_PAD>
       <<<dim3(unsigned(std::min(mtiles, cap))), dim3(C::MG_WG), MT::LDS_BYTES, s>>>(src, nullptr, dst, nullptr, n,
                                                                                   ctl, n, part);

@@ -12,12 +12,6 @@ namespace ms {
 // building with -D overrides; the defaults are the fastest shapes measured
 // on MI355X.  Suffixes: K = 32-bit keys only, P = 32-bit keys with values,
 // W = 64-bit keys.
-#ifndef MS_PART_G
-#define MS_PART_G 1  // lanes per partition search (1 = binary search)
-#endif
-#ifndef MS_PART4_G
-#define MS_PART4_G 1  // lanes per fused-pass (four-run) partition search
-#endif
 #ifndef MS_BS_WG_K
 #define MS_BS_WG_K 1024
 #endif

@@ -191,8 +191,8 @@ ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint6
     const int steps = plan_hbm_passes(plan_passes(max_len, S::TILE), true);
     for (int j = 0; j < steps; ++j) {
       seg_partition_kernel<K, V><<<dim3(unsigned(ceil_div(L.mt_cap, 256))), dim3(256), 0, s>>>(keys, tk, st, j);
-      seg_partition4_kernel<K, V, MS_PART4_G>
-          <<<dim3(unsigned(ceil_div(L.mt_cap * MS_PART4_G, 256))), dim3(256), 0, s>>>(keys, tk, st, j);
+      seg_partition4_kernel<K, V, 1>  // one lane per tile: batches hold many tiles
+          <<<dim3(unsigned(ceil_div(L.mt_cap, 256))), dim3(256), 0, s>>>(keys, tk, st, j);
       if (j == 0)  // two-run steps occur only first
         seg_merge_kernel<K, V, P::MG_WG, P::MG_IPT, P::MG_PAD>
             <<<dim3(unsigned(L.mt_cap)), dim3(P::MG_WG), MT::LDS_BYTES, s>>>(keys, vals, tk, tv, st, j);

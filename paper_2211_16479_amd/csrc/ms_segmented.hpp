@@ -280,8 +280,8 @@ __global__ __launch_bounds__(256) void seg_partition_kernel(const K* __restrict_
                                                   g0 - q.pb));
   } else {
     const uint64_t W = uint64_t(S::TILE) << (first + 2 * (j - first));
-    partition_tile(src, d.L, W, uint32_t(S::MTILE), d.lt, DevCtl{nullptr, nullptr, nullptr}, st.part + mb,
-                   static_cast<K*>(st.head) + mb, static_cast<K*>(st.tail) + mb);
+    partition_group<K, 1>(src, d.L, W, uint32_t(S::MTILE), d.lt, DevCtl{nullptr, nullptr, nullptr}, 0u, 0u,
+                          st.part + mb, static_cast<K*>(st.head) + mb, static_cast<K*>(st.tail) + mb);
   }
 }
 
