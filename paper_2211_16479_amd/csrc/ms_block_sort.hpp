@@ -66,10 +66,16 @@ __device__ __forceinline__ void register_sort(T (&v)[N]) {
 template <class IT, int SL, int N, class T>
 __device__ __forceinline__ void lane_half_clean(T (&v)[N], int lane) {
   const bool lower = (lane & SL) == 0;
+  if constexpr (IT::MED3) {
+    const T sd = IT::side(lower);
 #pragma unroll
-  for (int r = 0; r < N; ++r) {
-    T p = xor_lane<SL>(v[r]);
-    v[r] = lower ? IT::vmin(v[r], p) : IT::vmax(v[r], p);
+    for (int r = 0; r < N; ++r) v[r] = IT::keep(v[r], xor_lane<SL>(v[r]), sd);
+  } else {
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      T p = xor_lane<SL>(v[r]);
+      v[r] = lower ? IT::vmin(v[r], p) : IT::vmax(v[r], p);
+    }
   }
   if constexpr (SL > 1) lane_half_clean<IT, SL / 2>(v, lane);
 }
@@ -84,8 +90,14 @@ __device__ __forceinline__ void wave_merge_level(T (&v)[N], int lane) {
     T p[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) p[r] = xor_lane<L2 - 1>(v[N - 1 - r]);
+    if constexpr (IT::MED3) {
+      const T sd = IT::side(lower);
 #pragma unroll
-    for (int r = 0; r < N; ++r) v[r] = lower ? IT::vmin(v[r], p[r]) : IT::vmax(v[r], p[r]);
+      for (int r = 0; r < N; ++r) v[r] = IT::keep(v[r], p[r], sd);
+    } else {
+#pragma unroll
+      for (int r = 0; r < N; ++r) v[r] = lower ? IT::vmin(v[r], p[r]) : IT::vmax(v[r], p[r]);
+    }
   }
   if constexpr (L2 >= 4) lane_half_clean<IT, L2 / 4>(v, lane);
   // remaining half cleaners inside each lane's registers

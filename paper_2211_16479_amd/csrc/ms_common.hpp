@@ -48,10 +48,35 @@ struct Key64Pos {
 template <class K, bool PAIRS, bool WIDE = (sizeof(K) == 8)>
 struct Item;
 
+// Median of three 32-bit integers (v_med3): with c the smallest key it is
+// min(a, b), with c the largest max(a, b) -- one instruction for the
+// lane-dependent min-or-max of a bitonic exchange.
+__device__ __forceinline__ uint32_t med3_u32(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+__device__ __forceinline__ int32_t med3_i32(int32_t a, int32_t b, int32_t c) {
+  int32_t r;
+  asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
 // keys only: the key
 template <class K, bool WIDE>
 struct Item<K, false, WIDE> {
   using T = K;
+  // 32-bit keys: keep(v, p, side(lower)) = lower ? min(v, p) : max(v, p)
+  static constexpr bool MED3 = sizeof(K) == 4;
+  static __device__ __forceinline__ T side(bool lower) {  // the smallest or the largest key
+    if constexpr (sizeof(K) == 4 && K(0) < K(-1)) return lower ? K(0) : key_max<K>();
+    else return lower ? K(-key_max<K>() - 1) : key_max<K>();
+  }
+  static __device__ __forceinline__ T keep(const T& v, const T& p, const T& sd) {
+    if constexpr (sizeof(K) == 4 && K(0) < K(-1)) return T(med3_u32(uint32_t(v), uint32_t(p), uint32_t(sd)));
+    else if constexpr (sizeof(K) == 4) return T(med3_i32(int32_t(v), int32_t(p), int32_t(sd)));
+    else return v;  // unused: MED3 is false
+  }
   static __device__ __forceinline__ T make(K k, uint32_t) { return k; }
   static __device__ __forceinline__ T pad(uint32_t) { return key_max<K>(); }
   static __device__ __forceinline__ K key(const T& t) { return t; }
@@ -65,6 +90,7 @@ struct Item<K, false, WIDE> {
 template <class K>
 struct Item<K, true, false> {
   using T = uint64_t;
+  static constexpr bool MED3 = false;
   static __device__ __forceinline__ T make(K k, uint32_t p) { return (uint64_t(KeyBits<K>::ord(k)) << 32) | p; }
   static __device__ __forceinline__ T pad(uint32_t p) { return (0xFFFFFFFFull << 32) | p; }
   static __device__ __forceinline__ K key(const T& t) { return KeyBits<K>::unord(uint32_t(t >> 32)); }
@@ -78,6 +104,7 @@ struct Item<K, true, false> {
 template <class K>
 struct Item<K, true, true> {
   using T = Key64Pos;
+  static constexpr bool MED3 = false;
   static __device__ __forceinline__ T make(K k, uint32_t p) { T t; t.k = uint64_t(k); t.pos = p; t.pad = 0; return t; }
   static __device__ __forceinline__ T pad(uint32_t p) { return make(key_max<K>(), p); }
   static __device__ __forceinline__ K key(const T& t) { return K(t.k); }
