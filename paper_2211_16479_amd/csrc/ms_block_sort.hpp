@@ -22,14 +22,16 @@
 // Lanes spanned by the runs that the bitonic wavefront merges build before
 // LDS merge-path levels take over: 32-bit keys alone stay on lane exchanges
 // up to the whole wavefront; pairs and 64-bit keys (wider items, costlier
-// exchanges) switch to LDS after the quad-permute levels.  Measured on
-// MI355X: 32-bit keys 1.00 ms (64) vs 1.11 ms (4) per 2^27; Zipf pairs
-// 1.59 vs 1.42 ms; 2^28 int64 2.46 vs 1.87 ms.
+// exchanges) switch to LDS after 16 lanes.  Measured on MI355X: 32-bit keys
+// 1.00 ms (64) vs 1.11 ms (4) per 2^27; Zipf pairs 1.59 (64) vs 1.42 ms (4)
+// with a min-and-max exchange, and with the compare-and-select exchange
+// 1.16 (4), 1.12 (8, 16), 1.17 (32), 2.14 ms (64); 2^28 int64 2.46 (64)
+// vs 1.87 ms (4), then 1.84 (4), 1.78 (16) ms.
 #ifndef MS_TS_LANES_K
 #define MS_TS_LANES_K 64
 #endif
 #ifndef MS_TS_LANES_PW
-#define MS_TS_LANES_PW 4
+#define MS_TS_LANES_PW 16
 #endif
 
 namespace ms {
@@ -71,10 +73,13 @@ __device__ __forceinline__ void lane_half_clean(T (&v)[N], int lane) {
 #pragma unroll
     for (int r = 0; r < N; ++r) v[r] = IT::keep(v[r], xor_lane<SL>(v[r]), sd);
   } else {
+    // the lower lane keeps the smaller, the upper one the larger: take the
+    // partner's item when it is smaller, for the lower lane, or else when
+    // it is not (equal items are interchangeable)
 #pragma unroll
     for (int r = 0; r < N; ++r) {
-      T p = xor_lane<SL>(v[r]);
-      v[r] = lower ? IT::vmin(v[r], p) : IT::vmax(v[r], p);
+      const T p = xor_lane<SL>(v[r]);
+      v[r] = (IT::less(p, v[r]) == lower) ? p : v[r];
     }
   }
   if constexpr (SL > 1) lane_half_clean<IT, SL / 2>(v, lane);
@@ -96,7 +101,7 @@ __device__ __forceinline__ void wave_merge_level(T (&v)[N], int lane) {
       for (int r = 0; r < N; ++r) v[r] = IT::keep(v[r], p[r], sd);
     } else {
 #pragma unroll
-      for (int r = 0; r < N; ++r) v[r] = lower ? IT::vmin(v[r], p[r]) : IT::vmax(v[r], p[r]);
+      for (int r = 0; r < N; ++r) v[r] = (IT::less(p[r], v[r]) == lower) ? p[r] : v[r];
     }
   }
   if constexpr (L2 >= 4) lane_half_clean<IT, L2 / 4>(v, lane);
