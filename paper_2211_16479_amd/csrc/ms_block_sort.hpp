@@ -17,6 +17,8 @@
 // Bitonic stages compare (key, input position) items for pairs, a strict
 // total order, so they produce exactly the stable order.
 #pragma once
+#include <type_traits>
+
 #include "ms_common.hpp"
 
 // Lanes spanned by the runs that the bitonic wavefront merges build before
@@ -72,7 +74,7 @@ __device__ __forceinline__ void lane_half_clean(T (&v)[N], int lane) {
     const T sd = IT::side(lower);
 #pragma unroll
     for (int r = 0; r < N; ++r) v[r] = IT::keep(v[r], xor_lane<SL>(v[r]), sd);
-  } else {
+  } else if constexpr (std::is_integral<T>::value) {
     // the lower lane keeps the smaller, the upper one the larger: take the
     // partner's item when it is smaller, for the lower lane, or else when
     // it is not (equal items are interchangeable)
@@ -80,6 +82,12 @@ __device__ __forceinline__ void lane_half_clean(T (&v)[N], int lane) {
     for (int r = 0; r < N; ++r) {
       const T p = xor_lane<SL>(v[r]);
       v[r] = (IT::less(p, v[r]) == lower) ? p : v[r];
+    }
+  } else {  // (key, position) records: this form keeps them in registers
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      const T p = xor_lane<SL>(v[r]);
+      v[r] = lower ? IT::vmin(v[r], p) : IT::vmax(v[r], p);
     }
   }
   if constexpr (SL > 1) lane_half_clean<IT, SL / 2>(v, lane);
@@ -99,9 +107,12 @@ __device__ __forceinline__ void wave_merge_level(T (&v)[N], int lane) {
       const T sd = IT::side(lower);
 #pragma unroll
       for (int r = 0; r < N; ++r) v[r] = IT::keep(v[r], p[r], sd);
-    } else {
+    } else if constexpr (std::is_integral<T>::value) {
 #pragma unroll
       for (int r = 0; r < N; ++r) v[r] = (IT::less(p[r], v[r]) == lower) ? p[r] : v[r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < N; ++r) v[r] = lower ? IT::vmin(v[r], p[r]) : IT::vmax(v[r], p[r]);
     }
   }
   if constexpr (L2 >= 4) lane_half_clean<IT, L2 / 4>(v, lane);
@@ -189,7 +200,9 @@ struct TileSort {
   static_assert((IPT & (IPT - 1)) == 0 && IPT >= 2 && IPT <= 32, "IPT");
   // lane-exchange (bitonic) merges build runs spanning LANES lanes; LDS
   // merge-path levels take them from there to the whole tile
-  static constexpr int LANES = (PAIRS || sizeof(K) == 8) ? MS_TS_LANES_PW : MS_TS_LANES_K;
+  // (64-bit keys with values, (key, position) records, keep 4 lanes)
+  static constexpr int LANES =
+      (PAIRS && sizeof(K) == 8) ? 4 : ((PAIRS || sizeof(K) == 8) ? MS_TS_LANES_PW : MS_TS_LANES_K);
   static_assert(LANES >= 1 && LANES <= 64 && (LANES & (LANES - 1)) == 0, "LANES");
   static constexpr bool USE_LDS = NW > 1 || LANES < 64;
   static constexpr size_t LDS_ITEMS = USE_LDS ? (sizeof(T) * lds_padded_size<PAD>(TILE) + 15) / 16 * 16 : 0;
