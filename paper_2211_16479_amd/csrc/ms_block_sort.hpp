@@ -173,14 +173,17 @@ __device__ __forceinline__ void lds_merge_level(T (&v)[N], T* lds, int R, uint32
       if (IT::less(lds[lds_pad<PAD>(b0 + d - 1 - m)], lds[lds_pad<PAD>(a0 + m)])) hi = m; else lo = m + 1;
     }
     int i = lo, j = d - lo;
-    T a = lds[lds_pad<PAD>(a0 + (i < R ? i : R - 1))], b = lds[lds_pad<PAD>(b0 + (j < R ? j : R - 1))];
+    // i, j <= R throughout (a thread emits at most 2R - d items), so a read
+    // one past a run lands in the next run or in the spare slot after the
+    // tile; such a value is never taken (that run is exhausted)
+    T a = lds[lds_pad<PAD>(a0 + i)], b = lds[lds_pad<PAD>(b0 + j)];
 #pragma unroll
     for (int r = 0; r < N; ++r) {
       const bool take_b = (j < R) && (i >= R || IT::less(b, a));
       v[r] = take_b ? b : a;
       i += take_b ? 0 : 1;
       j += take_b ? 1 : 0;
-      const uint32_t nx = take_b ? b0 + (j < R ? j : R - 1) : a0 + (i < R ? i : R - 1);
+      const uint32_t nx = take_b ? b0 + j : a0 + i;
       const T x = lds[lds_pad<PAD>(nx)];
       a = take_b ? a : x;
       b = take_b ? x : b;
@@ -205,7 +208,8 @@ struct TileSort {
       (PAIRS && sizeof(K) == 8) ? 4 : ((PAIRS || sizeof(K) == 8) ? MS_TS_LANES_PW : MS_TS_LANES_K);
   static_assert(LANES >= 1 && LANES <= 64 && (LANES & (LANES - 1)) == 0, "LANES");
   static constexpr bool USE_LDS = NW > 1 || LANES < 64;
-  static constexpr size_t LDS_ITEMS = USE_LDS ? (sizeof(T) * lds_padded_size<PAD>(TILE) + 15) / 16 * 16 : 0;
+  // one spare slot past the tile (reads one past the last run)
+  static constexpr size_t LDS_ITEMS = USE_LDS ? (sizeof(T) * (lds_padded_size<PAD>(TILE) + 1) + 15) / 16 * 16 : 0;
   static constexpr size_t LDS_VALS = PAIRS ? sizeof(typename std::conditional<PAIRS, V, int>::type) * TILE : 0;
   static constexpr size_t LDS_BYTES = LDS_ITEMS + LDS_VALS;
 
