@@ -100,19 +100,30 @@ __device__ __forceinline__ void wave_merge_level(T (&v)[N], int lane) {
   // register N-1-r; the lower half of each block keeps the minimum.
   {
     const bool lower = (lane & (L2 / 2)) == 0;
-    T p[N];
+    [[maybe_unused]] T sd{};
+    if constexpr (IT::MED3) sd = IT::side(lower);
+    auto keep = [&](const T& own, const T& p) -> T {
+      if constexpr (IT::MED3) return IT::keep(own, p, sd);
+      else if constexpr (std::is_integral<T>::value) return (IT::less(p, own) == lower) ? p : own;
+      else return lower ? IT::vmin(own, p) : IT::vmax(own, p);
+    };
+    if constexpr (IT::WITH_POS) {
+      // registers r and N-1-r updated together from each other's partner
+      // items: two temporaries live instead of N (keeps pair tiles from
+      // spilling)
 #pragma unroll
-    for (int r = 0; r < N; ++r) p[r] = xor_lane<L2 - 1>(v[N - 1 - r]);
-    if constexpr (IT::MED3) {
-      const T sd = IT::side(lower);
-#pragma unroll
-      for (int r = 0; r < N; ++r) v[r] = IT::keep(v[r], p[r], sd);
-    } else if constexpr (std::is_integral<T>::value) {
-#pragma unroll
-      for (int r = 0; r < N; ++r) v[r] = (IT::less(p[r], v[r]) == lower) ? p[r] : v[r];
+      for (int r = 0; r < N / 2; ++r) {
+        const T pr = xor_lane<L2 - 1>(v[N - 1 - r]);  // partner's item for register r
+        const T pq = xor_lane<L2 - 1>(v[r]);          // and for register N-1-r
+        v[r] = keep(v[r], pr);
+        v[N - 1 - r] = keep(v[N - 1 - r], pq);
+      }
     } else {
+      T p[N];
 #pragma unroll
-      for (int r = 0; r < N; ++r) v[r] = lower ? IT::vmin(v[r], p[r]) : IT::vmax(v[r], p[r]);
+      for (int r = 0; r < N; ++r) p[r] = xor_lane<L2 - 1>(v[N - 1 - r]);
+#pragma unroll
+      for (int r = 0; r < N; ++r) v[r] = keep(v[r], p[r]);
     }
   }
   if constexpr (L2 >= 4) lane_half_clean<IT, L2 / 4>(v, lane);

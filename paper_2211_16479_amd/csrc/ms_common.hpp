@@ -68,6 +68,7 @@ struct Item<K, false, WIDE> {
   using T = K;
   // 32-bit keys: keep(v, p, side(lower)) = lower ? min(v, p) : max(v, p)
   static constexpr bool MED3 = sizeof(K) == 4;
+  static constexpr bool WITH_POS = false;
   static __device__ __forceinline__ T side(bool lower) {  // the smallest or the largest key
     if constexpr (sizeof(K) == 4 && K(0) < K(-1)) return lower ? K(0) : key_max<K>();
     else return lower ? K(-key_max<K>() - 1) : key_max<K>();
@@ -91,6 +92,7 @@ template <class K>
 struct Item<K, true, false> {
   using T = uint64_t;
   static constexpr bool MED3 = false;
+  static constexpr bool WITH_POS = true;
   static __device__ __forceinline__ T make(K k, uint32_t p) { return (uint64_t(KeyBits<K>::ord(k)) << 32) | p; }
   static __device__ __forceinline__ T pad(uint32_t p) { return (0xFFFFFFFFull << 32) | p; }
   static __device__ __forceinline__ K key(const T& t) { return KeyBits<K>::unord(uint32_t(t >> 32)); }
@@ -105,6 +107,7 @@ template <class K>
 struct Item<K, true, true> {
   using T = Key64Pos;
   static constexpr bool MED3 = false;
+  static constexpr bool WITH_POS = true;
   static __device__ __forceinline__ T make(K k, uint32_t p) { T t; t.k = uint64_t(k); t.pos = p; t.pad = 0; return t; }
   static __device__ __forceinline__ T pad(uint32_t p) { return make(key_max<K>(), p); }
   static __device__ __forceinline__ K key(const T& t) { return K(t.k); }
