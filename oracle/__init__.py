@@ -11,6 +11,11 @@ Contents
   (its step list and the mergesort figure, with the right half read as
   ``array[mid:]`` and ``merge`` taking the right head only when strictly
   smaller), in plain C (``msort_oracle.c``), single threaded.
+* :func:`sort` / :func:`sort_pairs` with ``threads > 1`` -- the same
+  recursion with its top ceil(log2(threads)) levels on threads (the paper's
+  section "Multiprocessing Merge Sort": independent chunk sorts, then a tree
+  of merges of adjacent runs); identical output, used to time the CPU
+  baseline on all host cores and to check full-size GPU outputs quickly.
 * :func:`rank_bounds` -- by-definition rank counts used to verify sampled
   positions of outputs too large to sort on the CPU within a test.
 * :mod:`oracle.mlp` -- the fp64 two-layer MLP CDF model (forward, analytic
@@ -38,6 +43,9 @@ def _load():
         lib.oracle_sort.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                     ctypes.c_int, ctypes.c_size_t]
         lib.oracle_sort.restype = ctypes.c_int
+        lib.oracle_sort_parallel.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                             ctypes.c_int, ctypes.c_size_t, ctypes.c_int]
+        lib.oracle_sort_parallel.restype = ctypes.c_int
         lib.oracle_segmented_sort.argtypes = [ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_void_p, ctypes.c_size_t,
                                               ctypes.c_int, ctypes.c_size_t]
@@ -57,24 +65,39 @@ def _kt(a: np.ndarray) -> int:
         raise TypeError(f"unsupported key dtype {a.dtype}") from None
 
 
-def sort(keys: np.ndarray) -> np.ndarray:
-    """Return the ascending (stable) merge sort of ``keys`` (a new array)."""
-    out = np.ascontiguousarray(keys).copy()
-    rc = _load().oracle_sort(out.ctypes.data, None, out.size, _kt(out), 0)
+def host_threads() -> int:
+    """Threads the parallel oracle uses by default: this host's cores, at
+    most 16."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _run(k: np.ndarray, v, threads: int) -> None:
+    L = _load()
+    vp = None if v is None else v.ctypes.data
+    vb = 0 if v is None else v.dtype.itemsize
+    if threads == 1:
+        rc = L.oracle_sort(k.ctypes.data, vp, k.size, _kt(k), vb)
+    else:
+        rc = L.oracle_sort_parallel(k.ctypes.data, vp, k.size, _kt(k), vb, int(threads))
     if rc:
-        raise RuntimeError(f"oracle_sort failed ({rc})")
+        raise RuntimeError(f"oracle sort failed ({rc})")
+
+
+def sort(keys: np.ndarray, threads: int = 1) -> np.ndarray:
+    """Return the ascending (stable) merge sort of ``keys`` (a new array).
+    threads > 1 runs the top recursion levels on threads (same output)."""
+    out = np.ascontiguousarray(keys).copy()
+    _run(out, None, threads)
     return out
 
 
-def sort_pairs(keys: np.ndarray, vals: np.ndarray):
+def sort_pairs(keys: np.ndarray, vals: np.ndarray, threads: int = 1):
     """Stable sort of (key, value) pairs: equal keys keep their input order."""
     k = np.ascontiguousarray(keys).copy()
     v = np.ascontiguousarray(vals).copy()
     if k.shape != v.shape or v.dtype.itemsize not in (4, 8):
         raise ValueError("keys/values shape or value width mismatch")
-    rc = _load().oracle_sort(k.ctypes.data, v.ctypes.data, k.size, _kt(k), v.dtype.itemsize)
-    if rc:
-        raise RuntimeError(f"oracle_sort failed ({rc})")
+    _run(k, v, threads)
     return k, v
 
 

@@ -14,7 +14,7 @@ def compile_oracle(force: bool = True) -> str:
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall",
-                               "-o", tmp, SRC])
+                               "-pthread", "-o", tmp, SRC])
         os.replace(tmp, LIB)
     return LIB
 

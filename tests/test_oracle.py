@@ -204,3 +204,32 @@ def test_rank_bounds_brute_force():
     lt, le = oracle.rank_bounds(k, s)
     r = np.arange(k.size)
     assert ((lt <= r) & (r < le)).all()
+
+
+@pytest.mark.parametrize("dtype,vdtype", [(np.uint32, None), (np.uint32, np.uint32), (np.int32, np.uint64),
+                                          (np.int64, None), (np.uint64, np.uint32), (np.int64, np.uint64)])
+def test_threaded_top_levels_equal_single_thread(dtype, vdtype):
+    """The threaded variant (top recursion levels on threads, sequential
+    merges of adjacent halves) gives the single-thread oracle's output, which
+    numpy's stable sort confirms: sizes below, at and above the thread count,
+    odd sizes, and tie-heavy keys with value = index (stability)."""
+    rng = np.random.default_rng(5)
+    info = np.iinfo(dtype)
+    for threads in (2, 3, 4, 7, 8, 16):
+        for n in (0, 1, 2, 3, 5, 15, 16, 17, 1000, 65_537, 300_001):
+            for hi in (3, None):
+                if hi is None:
+                    k = rng.integers(info.min, info.max, size=n, dtype=dtype, endpoint=True)
+                else:
+                    k = rng.integers(0, hi, size=n).astype(dtype)
+                if vdtype is None:
+                    got = oracle.sort(k, threads=threads)
+                    assert np.array_equal(got, oracle.sort(k)), (threads, n)
+                    assert np.array_equal(got, np.sort(k, kind="stable")), (threads, n)
+                else:
+                    v = np.arange(n, dtype=vdtype)
+                    gk, gv = oracle.sort_pairs(k, v, threads=threads)
+                    ek, ev = oracle.sort_pairs(k, v)
+                    assert np.array_equal(gk, ek) and np.array_equal(gv, ev), (threads, n)
+                    order = np.argsort(k, kind="stable")
+                    assert np.array_equal(gv, v[order]), (threads, n)
