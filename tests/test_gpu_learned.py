@@ -9,7 +9,7 @@ import torch
 import oracle
 import paper_2211_16479_amd as msort
 import workloads
-from gpu_helpers import as_i64, assert_equal_arrays, check_sampled_ranks
+from gpu_helpers import assert_equal_arrays
 from oracle import mlp
 
 pytestmark = pytest.mark.gpu
@@ -172,19 +172,18 @@ def test_graph_replay_on_new_data(gpu):
 
 
 def test_full_lognormal_2p29_learned_equals_plain(gpu):
-    """2^29 uint32 keys from the 8-lognormal mixture: learned and plain
-    outputs byte-identical; cross-checked against torch.sort and sampled
-    oracle ranks."""
+    """Configuration 5 at full size: 2^29 uint32 keys from the 8-lognormal
+    mixture; the learned-bucket output and the plain output both equal the
+    oracle's sort element by element (threaded oracle)."""
     k = workloads.lognormal_mix_u32(1 << 29, seed=0, device=gpu)
     a = k.clone()
     _, st = msort.ms_sort_ex(a, algo=msort.MS_ALGO_LEARNED_BUCKET)
+    torch.cuda.synchronize()
+    assert st["fallback_taken"] == 0
+    exp = oracle.sort(u32_np(k), threads=oracle.host_threads())
+    assert_equal_arrays(u32_np(a), exp, "2^29 learned")
+    del a
     b = k.clone()
     msort.ms_sort(b)
     torch.cuda.synchronize()
-    assert st["fallback_taken"] == 0
-    assert bool((a.view(torch.int32) == b.view(torch.int32)).all()), "learned != plain"
-    del b
-    ref = torch.sort(as_i64(k)).values
-    assert bool((as_i64(a) == ref).all())
-    del ref
-    check_sampled_ranks(u32_np(k), u32_np(a), samples=8, seed=7)
+    assert_equal_arrays(u32_np(b), exp, "2^29 plain")
