@@ -61,6 +61,11 @@ typedef enum ms_status {
 /* Library version as major * 10000 + minor * 100 + patch. */
 int ms_version(void);
 
+/* Number of hipGraphs captured so far by this process (the segmented and
+ * learned forms capture one per device, stream and size/option set and
+ * replay it on any buffers); for tests and diagnostics. */
+uint64_t ms_graph_captures(void);
+
 /* Static text for a status code; never NULL. */
 const char* ms_status_string(ms_status s);
 
@@ -101,21 +106,26 @@ ms_status ms_sort_pairs(void* d_keys, void* d_vals, size_t n, ms_key_type kt, si
  *                     d_offsets[num_segments] == n_total.  Empty segments are
  *                     allowed.  The library does not check these conditions
  *                     (they live on the device); violating them is undefined.
- *   max_segment_len : an upper bound on every segment's length, or 0 if
- *                     unknown (then n_total is used).  It only sets how many
- *                     merge passes the captured graph contains; a bound that
- *                     is too small gives unsorted output for longer segments.
+ *   max_segment_len : a hint: an upper bound on segment lengths, or 0 if
+ *                     unknown (then n_total).  Merge passes up to the hint
+ *                     run over every reserved tile at full width; the passes
+ *                     that longer segments (up to n_total) would need are in
+ *                     the graph too, with a small grid, and return at once
+ *                     unless the device finds such a segment.  A hint that is
+ *                     too small therefore costs time, never correctness.
  * Limits: fewer than 2^26 segments and n_total < 2^32 per call, otherwise
  * MS_ERR_UNSUPPORTED.
  * Segments are binned by length on the device into small classes, each sorted
  * by a persistent kernel entirely in LDS (per-class workgroup size and items
  * per thread from the tuning table), and a large class sorted by tiles plus
  * merge passes that stay inside the segment.  The whole pipeline is captured
- * once into a hipGraph (cached per device, stream, pointers, sizes and tuning
- * table; up to 8 graphs, each owning its scratch) and replayed with one
- * hipGraphLaunch on `stream`.  This is the batched form of the paper's
- * chunk-parallel sort (section "Multiprocessing Merge Sort"), with each
- * array a chunk.
+ * once into a hipGraph (cached per device, stream, num_segments, n_total,
+ * max_segment_len, key/value type and tuning table; up to 8 graphs, each
+ * owning its scratch of ms_temp_bytes_segmented bytes) and replayed with one
+ * hipGraphLaunch on `stream`, preceded by a one-thread kernel that binds this
+ * call's buffers: new buffers of the same sizes replay the same graph.  This
+ * is the batched form of the paper's chunk-parallel sort (section
+ * "Multiprocessing Merge Sort"), with each array a chunk.
  */
 ms_status ms_segmented_sort(void* d_keys, void* d_vals, const int64_t* d_offsets, size_t num_segments,
                             size_t n_total, size_t max_segment_len, ms_key_type kt, size_t val_bytes,
@@ -213,10 +223,13 @@ void ms_options_default(ms_options* opt);
  * ms_stats.  MS_ALGO_LEARNED_BUCKET requires MS_KEY_U32,
  * n >= 4 * 2^sample_log2 and n < 2^32 (else MS_ERR_UNSUPPORTED); invalid
  * options give MS_ERR_INVALID_ARG.  The learned pipeline is replayed from a
- * cached hipGraph (use_graph = 1) keyed by pointers, n and options.
+ * cached hipGraph (use_graph = 1) keyed by n, whether d_stats is NULL and the
+ * options (not by the buffers, which are bound per launch); the graph owns
+ * ms_temp_bytes_learned(n, opt) bytes of scratch.
  */
 ms_status ms_sort_ex(void* d_keys, size_t n, ms_key_type kt, const ms_options* opt, ms_stats* d_stats,
                      void* stream);
+size_t ms_temp_bytes_learned(size_t n, const ms_options* opt);
 
 /*
  * Steps of the learned form, for tests and inspection (all device pointers;
@@ -250,8 +263,16 @@ ms_status ms_learned_bucket_ids(const uint32_t* d_keys, size_t n, const float* d
  * ms_temp_bytes -- device scratch (bytes) that a plain sort of n keys with
  * values of val_bytes (0 = keys only) uses.  Host arithmetic only.
  * Returns 0 for an unsupported kt / val_bytes.
+ *
+ * ms_temp_bytes_segmented -- scratch that one ms_segmented_sort graph of
+ * num_segments segments and n_total keys owns (0 for an unsupported type).
+ *
+ * ms_temp_bytes_learned -- scratch that one ms_sort_ex learned-bucket graph
+ * of n uint32 keys owns under options opt (NULL = defaults); 0 if the
+ * options are invalid.  Host arithmetic only.
  */
 size_t ms_temp_bytes(size_t n, ms_key_type kt, size_t val_bytes);
+size_t ms_temp_bytes_segmented(size_t num_segments, size_t n_total, ms_key_type kt, size_t val_bytes);
 
 /*
  * ms_plan_query -- the plan ms_sort / ms_sort_pairs would use for n keys:

@@ -70,6 +70,9 @@ def _declare(lib):
         "ms_sort": (i32, [vp, sz, i32, vp]),
         "ms_sort_pairs": (i32, [vp, vp, sz, i32, sz, vp]),
         "ms_temp_bytes": (sz, [sz, i32, sz]),
+        "ms_temp_bytes_segmented": (sz, [sz, sz, i32, sz]),
+        "ms_temp_bytes_learned": (sz, [sz, c.POINTER(MsOptions)]),
+        "ms_graph_captures": (c.c_uint64, []),
         "ms_plan_query": (i32, [sz, i32, sz, c.POINTER(i32), c.POINTER(i32), c.POINTER(i32),
                                 c.POINTER(i32), c.POINTER(i32), c.POINTER(i32)]),
         "ms_release_workspace": (i32, []),
@@ -329,6 +332,24 @@ def ms_learned_bucket_ids(keys: torch.Tensor, theta: torch.Tensor, sample_sorted
 
 def ms_temp_bytes(n: int, key_type: int, val_bytes: int = 0) -> int:
     return int(lib().ms_temp_bytes(n, key_type, val_bytes))
+
+
+def ms_temp_bytes_segmented(num_segments: int, n_total: int, key_type: int, val_bytes: int = 0) -> int:
+    return int(lib().ms_temp_bytes_segmented(num_segments, n_total, key_type, val_bytes))
+
+
+def ms_temp_bytes_learned(n: int, **options) -> int:
+    o = ms_options_default()
+    for k, v in options.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return int(lib().ms_temp_bytes_learned(n, ctypes.byref(o)))
+
+
+def ms_graph_captures() -> int:
+    """hipGraphs captured so far by this process."""
+    return int(lib().ms_graph_captures())
 
 
 def ms_plan_query(n: int, key_type: int, val_bytes: int = 0) -> dict:

@@ -335,6 +335,8 @@ void block_sort_kernel(const K* in_k, const V* in_v, K* out_k, V* out_v, uint64_
   using TS = TileSort<K, V, WG, IPT, PAD>;
   extern __shared__ __align__(16) unsigned char smem[];
   if (gated_off(ctl)) return;
+  in_k = rebind(in_k, ctl.keys);
+  out_k = rebind(out_k, ctl.keys);
   const uint64_t n = live_n(ctl, n_host);
   for (uint64_t base = uint64_t(blockIdx.x) * TS::TILE; base < n; base += uint64_t(gridDim.x) * TS::TILE) {
     const uint64_t rem = n - base;

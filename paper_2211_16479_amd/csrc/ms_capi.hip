@@ -205,12 +205,30 @@ static ms_status with_types(ms_key_type kt, size_t vb, F&& f) {
 
 // ------------------------------------------------------------ graph cache
 // Pipelines whose launch sequence is fixed on the host are captured once into
-// a hipGraph (per device, stream, pointers, sizes and options) that owns its
-// scratch, and replayed with one hipGraphLaunch.
+// a hipGraph per (device, stream, sizes, options) and replayed with one
+// hipGraphLaunch.  A graph owns its scratch; its first 256 bytes are the
+// binding block: before every replay a one-thread kernel writes the call's
+// buffer pointers there, and the graph's kernels read the caller's buffers
+// from it, so new buffers of the same sizes replay the same graph (no
+// capture, instantiation or allocation).  An entry is evicted (least
+// recently used, at most 8) only after its last launch has completed, by
+// waiting on an event recorded after that launch.
 namespace {
+constexpr size_t BIND_BYTES = 256;
+constexpr int BIND_SLOTS = 4;
+
+struct BindArgs {
+  void* p[BIND_SLOTS];
+};
+
+__global__ void ms_bind_kernel(void** io, BindArgs a) {
+  if (threadIdx.x < BIND_SLOTS) io[threadIdx.x] = a.p[threadIdx.x];
+}
+
 struct GraphEntry {
   hipGraphExec_t exec = nullptr;
   void* ws = nullptr;
+  hipEvent_t done = nullptr;  // recorded after the entry's latest launch
   uint64_t last_use = 0;
 };
 std::mutex g_graph_mu;
@@ -221,19 +239,36 @@ struct CaptureStreams {
 };
 std::map<int, CaptureStreams> g_capture_streams;
 uint64_t g_graph_clock = 0;
+uint64_t g_graph_captures = 0;
 constexpr size_t GRAPH_CACHE_MAX = 8;
 
+// Destroys an entry whose launches have completed (or never ran).
 void drop_graph(GraphEntry& e) {
+  if (e.done) (void)hipEventSynchronize(e.done);
   if (e.exec) (void)hipGraphExecDestroy(e.exec);
   if (e.ws) (void)hipFree(e.ws);
+  if (e.done) (void)hipEventDestroy(e.done);
   e.exec = nullptr;
   e.ws = nullptr;
+  e.done = nullptr;
 }
 }  // namespace
 
-ms_status cached_graph_launch(std::vector<uint64_t> key, size_t ws_bytes,
-                              const std::function<ms_status(void* ws, hipStream_t cs, SegFork fork)>& enqueue,
+size_t graph_bind_bytes() { return BIND_BYTES; }
+
+uint64_t graph_capture_count() {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  return g_graph_captures;
+}
+
+ms_status cached_graph_launch(std::vector<uint64_t> key, size_t ws_bytes, const std::vector<void*>& bind,
+                              const std::function<ms_status(void* ws, void* const* io, hipStream_t cs, SegFork fork)>&
+                                  enqueue,
                               hipStream_t s) {
+  if (bind.size() > size_t(BIND_SLOTS)) {
+    set_error("too many bound buffers");
+    return MS_ERR_INTERNAL;
+  }
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -246,13 +281,14 @@ ms_status cached_graph_launch(std::vector<uint64_t> key, size_t ws_bytes,
       auto lru = g_graphs.begin();
       for (auto jt = g_graphs.begin(); jt != g_graphs.end(); ++jt)
         if (jt->second.last_use < lru->second.last_use) lru = jt;
-      (void)hipDeviceSynchronize();  // the evicted graph may still be running
-      drop_graph(lru->second);
+      drop_graph(lru->second);  // waits for that entry's last launch only
       g_graphs.erase(lru);
     }
     GraphEntry ent;
-    e = hipMalloc(&ent.ws, ws_bytes ? ws_bytes : 256);
+    e = hipMalloc(&ent.ws, BIND_BYTES + (ws_bytes ? ws_bytes : 256));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc (graph scratch)");
+    e = hipEventCreateWithFlags(&ent.done, hipEventDisableTiming);
+    if (e != hipSuccess) { drop_graph(ent); return hip_fail(e, "hipEventCreate"); }
     CaptureStreams& cap = g_capture_streams[dev];
     if (!cap.main) {
       e = hipStreamCreateWithFlags(&cap.main, hipStreamNonBlocking);
@@ -263,7 +299,9 @@ ms_status cached_graph_launch(std::vector<uint64_t> key, size_t ws_bytes,
     }
     e = hipStreamBeginCapture(cap.main, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) { drop_graph(ent); return hip_fail(e, "hipStreamBeginCapture"); }
-    ms_status st = enqueue(ent.ws, cap.main, SegFork{cap.side, cap.ev_fork, cap.ev_join});
+    void* const* io = static_cast<void* const*>(ent.ws);
+    ms_status st = enqueue(static_cast<char*>(ent.ws) + BIND_BYTES, io, cap.main,
+                           SegFork{cap.side, cap.ev_fork, cap.ev_join});
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(cap.main, &graph);
     if (st != MS_OK || e2 != hipSuccess) {
@@ -274,11 +312,20 @@ ms_status cached_graph_launch(std::vector<uint64_t> key, size_t ws_bytes,
     e = hipGraphInstantiate(&ent.exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) { drop_graph(ent); return hip_fail(e, "hipGraphInstantiate"); }
+    ++g_graph_captures;
     it = g_graphs.emplace(key, ent).first;
   }
-  it->second.last_use = ++g_graph_clock;
-  e = hipGraphLaunch(it->second.exec, s);
+  GraphEntry& ent = it->second;
+  ent.last_use = ++g_graph_clock;
+  BindArgs a{};
+  for (size_t i = 0; i < bind.size(); ++i) a.p[i] = bind[i];
+  ms_bind_kernel<<<1, 64, 0, s>>>(static_cast<void**>(ent.ws), a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "binding launch");
+  e = hipGraphLaunch(ent.exec, s);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  e = hipEventRecord(ent.done, s);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
   return MS_OK;
 }
 
@@ -290,18 +337,17 @@ static ms_status seg_run(void* d_keys, void* d_vals, const int64_t* d_off, uint6
     return MS_OK;
   });
   if (st != MS_OK) return st;
-  std::vector<uint64_t> key = {1, uint64_t(kt), vb, reinterpret_cast<uint64_t>(d_keys),
-                               reinterpret_cast<uint64_t>(d_vals), reinterpret_cast<uint64_t>(d_off), nseg, n_total,
-                               max_len, seg_tuning_generation()};
+  // buffers are bound per launch: the graph depends only on the sizes
+  std::vector<uint64_t> key = {1, uint64_t(kt), vb, nseg, n_total, max_len, seg_tuning_generation()};
   const int* tune = seg_tuning_row(kt, vb);
   return cached_graph_launch(
-      key, bytes,
-      [&](void* ws, hipStream_t cs, SegFork fork) -> ms_status {
+      key, bytes, {d_keys, d_vals, const_cast<int64_t*>(d_off)},
+      [&](void* ws, void* const* io, hipStream_t cs, SegFork fork) -> ms_status {
         return with_types(kt, vb, [&](auto kz, auto vz) -> ms_status {
           using K = decltype(kz);
           using V = decltype(vz);
           return seg_enqueue<K, V>(static_cast<K*>(d_keys), static_cast<V*>(d_vals), d_off, nseg, n_total, max_len,
-                                   ws, cs, tune, fork);
+                                   ws, cs, tune, fork, nullptr, io);
         });
       },
       s);
@@ -325,7 +371,9 @@ using namespace ms;
 
 extern "C" {
 
-int ms_version(void) { return 100; }
+int ms_version(void) { return 101; }
+
+uint64_t ms_graph_captures(void) { return graph_capture_count(); }
 
 const char* ms_status_string(ms_status s) {
   switch (s) {
@@ -388,6 +436,15 @@ size_t ms_temp_bytes(size_t n, ms_key_type kt, size_t val_bytes) {
       out = plain_temp_bytes<K, V>(n);
       return MS_OK;
     });
+  });
+  return st == MS_OK ? out : 0;
+}
+
+size_t ms_temp_bytes_segmented(size_t num_segments, size_t n_total, ms_key_type kt, size_t val_bytes) {
+  size_t out = 0;
+  ms_status st = with_types(kt, val_bytes, [&](auto kz, auto vz) -> ms_status {
+    out = graph_bind_bytes() + seg_temp_bytes<decltype(kz), decltype(vz)>(num_segments, n_total);
+    return MS_OK;
   });
   return st == MS_OK ? out : 0;
 }

@@ -227,13 +227,30 @@ __device__ __forceinline__ void load_run(const E* __restrict__ src, E (&v)[N]) {
   }
 }
 
+// A caller's buffer that a cached hipGraph sees at launch time.  The graph's
+// kernels keep the pointer of the call that captured them (`token`); before
+// every replay the library writes the current call's pointer to *cur, and a
+// kernel argument equal to the token is replaced by it.  cur == nullptr: no
+// rebinding (plain launches).
+struct Rebind {
+  const void* token;
+  void* const* cur;
+};
+
+template <class T>
+__device__ __forceinline__ T* rebind(T* p, const Rebind& r) {
+  return (r.cur && static_cast<const void*>(p) == r.token) ? static_cast<T*>(*r.cur) : p;
+}
+
 // Optional device-side controls shared by the sort kernels: an element count
-// that lives in device memory (set by an earlier kernel) and a gate flag that
-// lets a kernel return at once when its stage is not needed.
+// that lives in device memory (set by an earlier kernel), a gate flag that
+// lets a kernel return at once when its stage is not needed, and the
+// rebinding of the caller's key buffer under graph replay.
 struct DevCtl {
   const uint64_t* n_dev;      // if non-null, the element count (<= the host bound)
   const int* gate;            // if non-null and *gate == 0, the kernel does nothing
   const uint64_t* split_dev;  // if non-null: one merge of run [0, split) with [split, n)
+  Rebind keys = {nullptr, nullptr};  // key-buffer arguments equal to keys.token read *keys.cur
 };
 
 __device__ __forceinline__ bool gated_off(const DevCtl& c) { return c.gate && *c.gate == 0; }

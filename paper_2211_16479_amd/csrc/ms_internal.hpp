@@ -68,9 +68,13 @@ struct SegFork {
   hipStream_t side;
   hipEvent_t ev_fork, ev_join;
 };
+// keys_sel: if non-null the small classes sort *keys_sel (chosen on the
+// device); io: if non-null the caller's buffers are read from io[0..2]
+// (keys, values, offsets) at run time (graph replays on new buffers).
 template <class K, class V>
 ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint64_t n_total, uint64_t max_len,
-                      void* ws, hipStream_t s, const int* tune, SegFork fork, void* const* keys_sel = nullptr);
+                      void* ws, hipStream_t s, const int* tune, SegFork fork, void* const* keys_sel = nullptr,
+                      void* const* io = nullptr);
 template <class K, class V>
 size_t seg_temp_bytes(uint64_t nseg, uint64_t n_total);
 template <class K, class V>
@@ -84,8 +88,16 @@ int device_cu_count();
 
 // Capture `enqueue` once per key into a hipGraph that owns ws_bytes of
 // scratch, then launch it on s (cache of 8 graphs, least recently used out).
-ms_status cached_graph_launch(std::vector<uint64_t> key, size_t ws_bytes,
-                              const std::function<ms_status(void* ws, hipStream_t cs, SegFork fork)>& enqueue,
+// `bind` (at most 4 pointers) is written to the graph's binding block io
+// before every launch; enqueue must make the graph read the caller's
+// buffers from io, not from the pointers it was captured with.
+ms_status cached_graph_launch(std::vector<uint64_t> key, size_t ws_bytes, const std::vector<void*>& bind,
+                              const std::function<ms_status(void* ws, void* const* io, hipStream_t cs, SegFork fork)>&
+                                  enqueue,
                               hipStream_t s);
+// Graphs captured so far in this process (all devices).
+uint64_t graph_capture_count();
+// Bytes of a cached graph's scratch taken by its binding block.
+size_t graph_bind_bytes();
 
 }  // namespace ms

@@ -6,6 +6,7 @@
 
 #include "ms_internal.hpp"
 #include "ms_learned.hpp"
+#include "ms_plain_cfg.hpp"
 #include "ms_plan.hpp"
 #include "ms_tuning.hpp"
 
@@ -68,8 +69,9 @@ __global__ void ls_plain_stats_kernel(ms_stats* st) {
   st->algo_used = MS_ALGO_MERGE_PATH;
 }
 
-__global__ void ls_stats_kernel(const LsModel* md, ms_stats* st, uint64_t buckets) {
+__global__ void ls_stats_kernel(const LsModel* md, ms_stats* st, uint64_t buckets, Rebind rs) {
   if (threadIdx.x != 0) return;
+  st = rebind(st, rs);
   st->algo_used = md->fallback ? MS_ALGO_MERGE_PATH : MS_ALGO_LEARNED_BUCKET;
   st->fallback_taken = md->fallback;
   st->misordered = md->misordered;
@@ -119,7 +121,7 @@ static LsPlan ls_plan(uint64_t n, const ms_options& o) {
   P.bins_f_off[4] = take(sizeof(int64_t) * (P.B + 1));
   P.coarse = take(std::max<size_t>(sizeof(uint32_t) * n, plain_temp_bytes<uint32_t, NoVal>(n)));
   P.xr = take(sizeof(uint32_t) * n);
-  P.part = take(sizeof(int64_t) * (ceil_div(n, 2048) + 2));
+  P.part = take(sizeof(int64_t) * (ceil_div(n, PlainCfg<uint32_t, NoVal>::MTILE) + 2));  // merge_two_runs
   P.seg = take(seg_temp_bytes<uint32_t, NoVal>(P.B, o.bucket_capacity));
   P.bytes = off;
   return P;
@@ -150,8 +152,10 @@ static ms_status ls_train_enqueue(const uint32_t* sample, uint32_t S, LsModel* m
   return e == hipSuccess ? MS_OK : hip_fail(e, "training launch");
 }
 
+// io: if non-null, the caller's buffers of this launch are read from io[0]
+// (keys) and io[1] (stats) at run time (graph replays on new buffers).
 static ms_status learned_enqueue(uint32_t* keys, uint64_t n, const ms_options& o, ms_stats* d_stats, void* ws,
-                                 hipStream_t s) {
+                                 void* const* io, hipStream_t s) {
   const LsPlan P = ls_plan(n, o);
   char* w = static_cast<char*>(ws);
   LsModel* md = reinterpret_cast<LsModel*>(w + P.md);
@@ -163,10 +167,12 @@ static ms_status learned_enqueue(uint32_t* keys, uint64_t n, const ms_options& o
   int64_t* part = reinterpret_cast<int64_t*>(w + P.part);
   const LsBins bn = ls_bins(w, P);
   const DevCtl none{nullptr, nullptr, nullptr};
+  const Rebind rk{keys, io ? &io[0] : nullptr};
+  const Rebind rs{d_stats, io ? &io[1] : nullptr};
 
   ls_setup_kernel<<<1, 64, 0, s>>>(md, o.feature == MS_FEATURE_LOG ? 1 : 0, o.use_network ? 1 : 0, P.cb, P.fb);
   // sample, ranked by the plain merge sort
-  ls_sample_kernel<<<dim3(unsigned(ceil_div(P.S, 256))), 256, 0, s>>>(keys, n, P.S, o.seed, sample);
+  ls_sample_kernel<<<dim3(unsigned(ceil_div(P.S, 256))), 256, 0, s>>>(keys, n, P.S, o.seed, sample, rk);
   ms_status st = plain_sort<uint32_t, NoVal>(sample, nullptr, P.S, none, s, w + P.sample_tmp);
   if (st != MS_OK) return st;
   // train and compile the network
@@ -179,12 +185,12 @@ static ms_status learned_enqueue(uint32_t* keys, uint64_t n, const ms_options& o
   const unsigned chunks1 = unsigned(ceil_div(n, LS_CHK));
   {
     ProfScope ps(PK_LEARN_HIST, s);
-    ls_hist1_kernel<<<unsigned(ceil_div(chunks1, LS_H1)), LS_WG, 0, s>>>(keys, n, md, bn);
+    ls_hist1_kernel<<<unsigned(ceil_div(chunks1, LS_H1)), LS_WG, 0, s>>>(keys, n, md, bn, rk);
   }
   ls_plan1_kernel<<<1, LS_WG, 0, s>>>(md, bn);
   {
     ProfScope ps(PK_LEARN_SCATTER, s);
-    ls_scatter1_kernel<<<chunks1, LS_WG, 0, s>>>(keys, n, md, bn, coarse);
+    ls_scatter1_kernel<<<chunks1, LS_WG, 0, s>>>(keys, n, md, bn, coarse, rk);
   }
   // level 2
   {
@@ -192,7 +198,7 @@ static ms_status learned_enqueue(uint32_t* keys, uint64_t n, const ms_options& o
     ls_hist2_kernel<<<unsigned(P.chunk_cap), LS_WG, 0, s>>>(coarse, md, bn);
   }
   ls_totals_kernel<<<P.nbc, LS_WG, 0, s>>>(md, bn, o.bucket_capacity);
-  ls_plan2_kernel<<<1, LS_WG, 0, s>>>(md, bn, n, P.spill_cap, o.force_fallback, keys, xr);
+  ls_plan2_kernel<<<1, LS_WG, 0, s>>>(md, bn, n, P.spill_cap, o.force_fallback, keys, xr, rk);
   ls_offsets_kernel<<<P.nbc, LS_WG, 0, s>>>(md, bn, o.bucket_capacity);
   {
     ProfScope ps(PK_LEARN_SCATTER, s);
@@ -217,15 +223,15 @@ static ms_status learned_enqueue(uint32_t* keys, uint64_t n, const ms_options& o
     st = plain_sort<uint32_t, NoVal>(xr, nullptr, P.spill_cap, DevCtl{spilled, &md->do_repair, nullptr}, s, coarse,
                                      gated_grid);
     if (st != MS_OK) return st;
-    st = merge_two_runs<uint32_t, NoVal>(xr, keys, n, DevCtl{nullptr, &md->do_repair, spilled}, part, s,
+    st = merge_two_runs<uint32_t, NoVal>(xr, keys, n, DevCtl{nullptr, &md->do_repair, spilled, rk}, part, s,
                                          gated_grid);
     if (st != MS_OK) return st;
   }
   // fallback: the plain merge sort of the untouched input
-  st = plain_sort<uint32_t, NoVal>(keys, nullptr, n, DevCtl{nullptr, &md->fallback, nullptr}, s, coarse,
+  st = plain_sort<uint32_t, NoVal>(keys, nullptr, n, DevCtl{nullptr, &md->fallback, nullptr, rk}, s, coarse,
                                    gated_grid);
   if (st != MS_OK) return st;
-  if (d_stats) ls_stats_kernel<<<1, 64, 0, s>>>(md, d_stats, P.B);
+  if (d_stats) ls_stats_kernel<<<1, 64, 0, s>>>(md, d_stats, P.B, rs);
   e = hipGetLastError();
   return e == hipSuccess ? MS_OK : hip_fail(e, "learned sort launch");
 }
@@ -311,21 +317,37 @@ ms_status ms_sort_ex(void* d_keys, size_t n, ms_key_type kt, const ms_options* o
       void* ws = nullptr;
       ms_status st = get_workspace(s, P.bytes, &ws);
       if (st != MS_OK) return st;
-      return learned_enqueue(keys, n, o, d_stats, ws, s);
+      return learned_enqueue(keys, n, o, d_stats, ws, nullptr, s);
     }
     uint32_t lr_bits, th_bits;
     std::memcpy(&lr_bits, &o.learning_rate, 4);
     std::memcpy(&th_bits, &o.spill_threshold, 4);
-    std::vector<uint64_t> key = {2, reinterpret_cast<uint64_t>(d_keys), n, reinterpret_cast<uint64_t>(d_stats),
-                                 th_bits, o.bucket_capacity, o.bucket_fill, o.train_steps, lr_bits, o.sample_log2,
-                                 o.seed, uint64_t(o.feature), uint64_t(o.use_network), uint64_t(o.force_fallback),
-                                 seg_tuning_generation()};
+    // the graph does not depend on the buffers: keys and stats are rebound
+    // on every launch
+    std::vector<uint64_t> key = {2, n, d_stats ? 1u : 0u, th_bits, o.bucket_capacity, o.bucket_fill, o.train_steps,
+                                 lr_bits, o.sample_log2, o.seed, uint64_t(o.feature), uint64_t(o.use_network),
+                                 uint64_t(o.force_fallback), seg_tuning_generation()};
     return cached_graph_launch(
-        key, P.bytes, [&](void* ws, hipStream_t cs, SegFork) { return learned_enqueue(keys, n, o, d_stats, ws, cs); },
+        key, P.bytes, {d_keys, d_stats},
+        [&](void* ws, void* const* io, hipStream_t cs, SegFork) {
+          return learned_enqueue(keys, n, o, d_stats, ws, io, cs);
+        },
         s);
   } catch (...) {
     set_error("unexpected exception");
     return MS_ERR_INTERNAL;
+  }
+}
+
+size_t ms_temp_bytes_learned(size_t n, const ms_options* opt) {
+  ms_options o;
+  ms_options_default(&o);
+  if (opt) o = *opt;
+  if (check_options(o) != MS_OK || n == 0) return 0;
+  try {
+    return graph_bind_bytes() + ls_plan(n, o).bytes;
+  } catch (...) {
+    return 0;
   }
 }
 

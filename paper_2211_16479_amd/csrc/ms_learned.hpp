@@ -85,9 +85,10 @@ struct LsModel {
 
 // ------------------------------------------------------------ sampling
 __global__ __launch_bounds__(256) void ls_sample_kernel(const uint32_t* __restrict__ keys, uint64_t n, uint32_t S,
-                                                        uint64_t seed, uint32_t* __restrict__ out) {
+                                                        uint64_t seed, uint32_t* __restrict__ out, Rebind rk) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S) return;
+  keys = rebind(keys, rk);
   // splitmix64 of (seed, i), mapped to [0, n) by a 64x64 -> high-64 product
   uint64_t z = seed * 0x9E3779B97F4A7C15ull + (uint64_t(i) + 1) * 0xD1B54A32D192ED03ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -424,9 +425,10 @@ __global__ __launch_bounds__(256) void ls_clear_kernel(LsBins bn, uint32_t nb_c,
 // flush of LDS counts into the global counters per LS_H1 chunks, which
 // keeps the 1024 global counters from serialising the whole launch).
 __global__ __launch_bounds__(LS_WG) void ls_hist1_kernel(const uint32_t* __restrict__ keys, uint64_t n,
-                                                         const LsModel* md, LsBins bn) {
+                                                         const LsModel* md, LsBins bn, Rebind rk) {
   __shared__ LsTable tb;
   __shared__ uint32_t h[LS_MAX_BINS];
+  keys = rebind(keys, rk);
   ls_load_table(md, &tb);
   const uint32_t nbc = md->nbins_c;
   for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) h[i] = 0;
@@ -492,9 +494,11 @@ struct LsScatterLds {
 
 // Level 1 scatter: chunk blockIdx.x of the input into coarse buckets.
 __global__ __launch_bounds__(LS_WG) void ls_scatter1_kernel(const uint32_t* __restrict__ keys, uint64_t n,
-                                                            const LsModel* md, LsBins bn, uint32_t* __restrict__ out) {
+                                                            const LsModel* md, LsBins bn, uint32_t* __restrict__ out,
+                                                            Rebind rkeys) {
   __shared__ LsTable tb;
   __shared__ LsScatterLds L;
+  keys = rebind(keys, rkeys);
   ls_load_table(md, &tb);
   const uint32_t nbc = md->nbins_c;
   for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) L.cnt[i] = 0;
@@ -667,9 +671,11 @@ __global__ __launch_bounds__(LS_WG) void ls_totals_kernel(const LsModel* md, LsB
 // Decision (one workgroup): kept / spill bases, the order check across coarse
 // buckets, fallback and repair flags, where the kept buckets live.
 __global__ __launch_bounds__(LS_WG) void ls_plan2_kernel(LsModel* md, LsBins bn, uint64_t n, uint64_t spill_limit,
-                                                         int force_fallback, uint32_t* d_keys, uint32_t* xr) {
+                                                         int force_fallback, uint32_t* d_keys, uint32_t* xr,
+                                                         Rebind rk) {
   __shared__ uint32_t k[LS_MAX_BINS], sp[LS_MAX_BINS], kb[LS_MAX_BINS], sb[LS_MAX_BINS], tmp[LS_WG];
   __shared__ uint32_t ktot, stot;
+  d_keys = rebind(d_keys, rk);
   const uint32_t nbc = md->nbins_c;
   for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) {
     k[i] = bn.kept_tot[i];

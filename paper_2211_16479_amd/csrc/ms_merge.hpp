@@ -149,6 +149,7 @@ __global__ __launch_bounds__(256) void partition_kernel(const K* __restrict__ sr
                                                         K* __restrict__ tail = nullptr) {
   static_assert(G >= 1 && G <= 64 && (64 % G) == 0, "group size");
   if (gated_off(ctl)) return;
+  src = rebind(src, ctl.keys);
   const uint64_t n = live_n(ctl, n_host);
   const uint32_t q = threadIdx.x % G, gshift = (__lane_id() / G) * G;
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
@@ -298,6 +299,8 @@ __global__ __launch_bounds__(WG) void merge_kernel(const K* __restrict__ src_k, 
   using MT = MergeTile<K, V, WG, IPT, PAD>;
   extern __shared__ __align__(16) unsigned char smem[];
   if (gated_off(ctl)) return;
+  src_k = rebind(src_k, ctl.keys);
+  dst_k = rebind(dst_k, ctl.keys);
   const uint64_t n = live_n(ctl, n_host);
   // workgroup b merges tiles b, b + grid, ... (one each when the grid covers them)
   for (uint64_t k = blockIdx.x; k * MT::TM < n; k += gridDim.x) {
@@ -545,6 +548,7 @@ __global__ __launch_bounds__(256) void partition4_kernel(const K* __restrict__ s
                                                          int64_t* __restrict__ part4) {
   static_assert(G >= 1 && G <= 64 && (64 % G) == 0, "group size");
   if (gated_off(ctl)) return;
+  src = rebind(src, ctl.keys);
   const uint64_t n = live_n(ctl, n_host);
   const uint32_t q = threadIdx.x % G, gshift = (__lane_id() / G) * G;
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
@@ -765,6 +769,8 @@ __global__ __launch_bounds__(WG) void merge4_kernel(const K* __restrict__ src_k,
   using VV = typename MT::VV;
   extern __shared__ __align__(16) unsigned char smem[];
   if (gated_off(ctl)) return;
+  src_k = rebind(src_k, ctl.keys);
+  dst_k = rebind(dst_k, ctl.keys);
   const uint64_t n = live_n(ctl, n_host);
   for (uint64_t k = blockIdx.x; k * MT::TM < n; k += gridDim.x) {
     if constexpr (MT::PAIRS) {

@@ -98,7 +98,7 @@ struct SegCands {
 };
 
 struct SegLayout {
-  size_t cls_count, cls_work, large_ctr, queues, large_seg, large_mbase, desc, part, part4, head, tail, tk, tv,
+  size_t cls_count, cls_work, large_ctr, max_steps, queues, large_seg, large_mbase, desc, part, part4, head, tail, tk, tv,
       bytes;
   uint64_t mt_cap;
 };
@@ -114,6 +114,7 @@ SegLayout seg_layout(uint64_t nseg, uint64_t n_total) {
   L.cls_count = take(sizeof(uint32_t) * SEG_MAX_CLASSES);
   L.cls_work = take(sizeof(uint32_t) * SEG_MAX_CLASSES);
   L.large_ctr = take(sizeof(unsigned long long));
+  L.max_steps = take(sizeof(uint32_t));
   L.queues = take(sizeof(int32_t) * SEG_MAX_CLASSES * nseg);
   L.large_seg = take(sizeof(int32_t) * nseg);
   L.large_mbase = take(sizeof(int64_t) * nseg);
@@ -129,9 +130,15 @@ SegLayout seg_layout(uint64_t nseg, uint64_t n_total) {
 }
 
 // Enqueue the whole segmented pipeline on stream s (possibly capturing).
+// max_len is the caller's bound on segment lengths: merge steps up to that
+// bound are launched over every reserved merge tile; the steps that longer
+// segments (up to n_total) would need are launched too, with a small grid,
+// and return at once unless classify found such a segment, so a bound that
+// is too small costs time, never correctness.
 template <class K, class V>
 ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint64_t n_total, uint64_t max_len,
-                      void* ws, hipStream_t s, const int* tune, SegFork fork, void* const* keys_sel) {
+                      void* ws, hipStream_t s, const int* tune, SegFork fork, void* const* keys_sel,
+                      void* const* io) {
   using S = SegCfg<K, V>;
   using P = PlainCfg<K, V>;
   const SegLayout L = seg_layout<K, V>(nseg, n_total);
@@ -149,6 +156,8 @@ ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint6
   st.head = w + L.head;
   st.tail = w + L.tail;
   st.keys_sel = keys_sel;
+  st.io = io;
+  st.max_steps = reinterpret_cast<uint32_t*>(w + L.max_steps);
   K* tk = reinterpret_cast<K*>(w + L.tk);
   V* tv = reinterpret_cast<V*>(w + L.tv);
   const uint64_t cus = uint64_t(device_cu_count());
@@ -172,7 +181,7 @@ ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint6
   }
   // segments longer than the last small class take the large path (a tile
   // sort, then merge passes when they span several tiles)
-  if (max_len > uint64_t(S::cls_max(S::NCLS - 1))) {
+  if (n_total > uint64_t(S::cls_max(S::NCLS - 1))) {
     using TS = TileSort<K, V, S::LWG, S::LIPT, P::SEG_LPAD>;
     using MT = MergeTile<K, V, P::MG_WG, P::MG_IPT, P::MG_PAD>;
     using M4 = Merge4Tile<K, V, P::MG_WG, P::MG_IPT, P::M4_PAD, P::M4_REUSE>;
@@ -188,16 +197,21 @@ ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint6
     const uint64_t tiles_cap = L.mt_cap / S::C;
     seg_large_tile_kernel<K, V, S::LWG, S::LIPT, P::SEG_LPAD>
         <<<dim3(unsigned(tiles_cap)), dim3(S::LWG), TS::LDS_BYTES, s>>>(keys, vals, tk, tv, st);
-    const int steps = plan_hbm_passes(plan_passes(max_len, S::TILE), true);
-    for (int j = 0; j < steps; ++j) {
-      seg_partition_kernel<K, V><<<dim3(unsigned(ceil_div(L.mt_cap, 256))), dim3(256), 0, s>>>(keys, tk, st, j);
-      seg_partition4_kernel<K, V, 1>  // one lane per tile: batches hold many tiles
-          <<<dim3(unsigned(ceil_div(L.mt_cap, 256))), dim3(256), 0, s>>>(keys, tk, st, j);
+    const int steps_hint = max_len > uint64_t(S::cls_max(S::NCLS - 1))
+                               ? plan_hbm_passes(plan_passes(max_len, S::TILE), true) : 0;
+    const int steps_all = plan_hbm_passes(plan_passes(n_total, S::TILE), true);
+    const uint64_t small_grid = cus * 2;
+    for (int j = 0; j < steps_all; ++j) {
+      const bool full = j < steps_hint;
+      const uint64_t gm = full ? L.mt_cap : std::min<uint64_t>(L.mt_cap, small_grid);
+      const uint64_t gp = full ? ceil_div(L.mt_cap, 256) : std::min<uint64_t>(ceil_div(L.mt_cap, 256), small_grid);
+      seg_partition_kernel<K, V><<<dim3(unsigned(gp)), dim3(256), 0, s>>>(keys, tk, st, j);
+      seg_partition4_kernel<K, V><<<dim3(unsigned(gp)), dim3(256), 0, s>>>(keys, tk, st, j);
       if (j == 0)  // two-run steps occur only first
         seg_merge_kernel<K, V, P::MG_WG, P::MG_IPT, P::MG_PAD>
-            <<<dim3(unsigned(L.mt_cap)), dim3(P::MG_WG), MT::LDS_BYTES, s>>>(keys, vals, tk, tv, st, j);
+            <<<dim3(unsigned(gm)), dim3(P::MG_WG), MT::LDS_BYTES, s>>>(keys, vals, tk, tv, st, j);
       seg_merge4_kernel<K, V, P::MG_WG, P::MG_IPT, P::M4_PAD, P::M4_REUSE>
-          <<<dim3(unsigned(L.mt_cap)), dim3(P::MG_WG), M4::LDS_BYTES, s>>>(keys, vals, tk, tv, st, j);
+          <<<dim3(unsigned(gm)), dim3(P::MG_WG), M4::LDS_BYTES, s>>>(keys, vals, tk, tv, st, j);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "large-segment launch");
@@ -234,7 +248,7 @@ void seg_candidate(int cls, int idx, int* wg, int* ipt) {
 
 #define MS_SEG_INSTANTIATE(K, V)                                                                              \
   template ms_status seg_enqueue<K, V>(K*, V*, const int64_t*, uint64_t, uint64_t, uint64_t, void*, hipStream_t, \
-                                       const int*, SegFork, void* const*);                                    \
+                                       const int*, SegFork, void* const*, void* const*);                      \
   template size_t seg_temp_bytes<K, V>(uint64_t, uint64_t);                                                   \
   template int seg_num_classes<K, V>();                                                                       \
   template void seg_class_info<K, V>(int, uint32_t*, int*);                                                   \

@@ -44,7 +44,19 @@ struct SegState {
   void* head;            // [mt_cap] keys (K) at the splits (fused passes)
   void* tail;            // [mt_cap] keys (K) just before the splits (fused passes)
   void* const* keys_sel; // if non-null, small classes sort the key array *keys_sel (chosen on the device)
+  void* const* io;       // if non-null, this launch's caller buffers: io[0] keys, io[1] values,
+                         // io[2] offsets (written before each replay of a cached graph)
+  uint32_t* max_steps;   // [1] HBM merge steps of the longest large segment (set by classify)
 };
+
+// The caller's buffer in slot i of this launch (graph replays rebind them).
+template <class T>
+__device__ __forceinline__ T* seg_io(const SegState& st, int i, T* p) {
+  return st.io ? static_cast<T*>(st.io[i]) : p;
+}
+__device__ __forceinline__ const int64_t* seg_bind_off(const SegState& st, const int64_t* off) {
+  return st.io ? static_cast<const int64_t*>(st.io[2]) : off;
+}
 
 // A reserved merge tile of a large segment, unpacked from its descriptor.
 struct SegTile {
@@ -122,7 +134,10 @@ static __global__ void seg_init_kernel(SegState st) {
     st.cls_count[t] = 0;
     st.cls_work[t] = 0;
   }
-  if (t == 0) *st.large_ctr = 0;
+  if (t == 0) {
+    *st.large_ctr = 0;
+    *st.max_steps = 0;
+  }
 }
 
 // One thread per segment.  Slots are reserved in two steps so that a batch
@@ -140,6 +155,7 @@ __global__ __launch_bounds__(256) void seg_classify_kernel(const int64_t* __rest
   __shared__ uint32_t l_cnt[SEG_MAX_CLASSES];
   __shared__ uint32_t g_base[SEG_MAX_CLASSES];
   __shared__ unsigned long long l_large, g_large;
+  off = seg_bind_off(st, off);
   const uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (threadIdx.x < SEG_MAX_CLASSES) l_cnt[threadIdx.x] = 0;
   if (threadIdx.x == 0) l_large = 0;
@@ -158,6 +174,7 @@ __global__ __launch_bounds__(256) void seg_classify_kernel(const int64_t* __rest
       } else {
         const unsigned long long mt = ((L + S::TILE - 1) / S::TILE) * S::C;
         llocal = atomicAdd(&l_large, (1ull << SEG_SLOT_SHIFT) | mt);
+        atomicMax(st.max_steps, uint32_t(seg_steps(seg_passes(L, S::TILE))));
       }
     }
   }
@@ -181,6 +198,7 @@ __global__ __launch_bounds__(256) void seg_classify_kernel(const int64_t* __rest
 template <class K, class V>
 __global__ __launch_bounds__(256) void seg_owner_kernel(const int64_t* __restrict__ off, SegState st) {
   using S = SegCfg<K, V>;
+  off = seg_bind_off(st, off);
   const uint64_t nlarge = (*st.large_ctr) >> SEG_SLOT_SHIFT;
   for (uint64_t slot = blockIdx.x; slot < nlarge; slot += gridDim.x) {
     const int32_t s = st.large_seg[slot];
@@ -209,6 +227,9 @@ __global__ __launch_bounds__(WG) void seg_small_kernel(K* __restrict__ keys, V* 
   __shared__ uint32_t cur;
   const uint32_t count = st.cls_count[cls];
   const int32_t* q = st.queues + uint64_t(cls) * nseg;
+  keys = seg_io(st, 0, keys);
+  vals = seg_io(st, 1, vals);
+  off = seg_bind_off(st, off);
   if (st.keys_sel) keys = static_cast<K*>(*st.keys_sel);
   uint32_t c0 = blockIdx.x * chunk;
   while (c0 < count) {
@@ -242,6 +263,8 @@ __global__ __launch_bounds__(WG) void seg_large_tile_kernel(K* __restrict__ keys
   extern __shared__ __align__(16) unsigned char smem[];
   const uint64_t t = blockIdx.x;
   if (t >= ((*st.large_ctr) & SEG_TILE_MASK) / S::C) return;
+  keys = seg_io(st, 0, keys);
+  vals = seg_io(st, 1, vals);
   const SegTile d = seg_tile(st.desc, t * S::C);
   const uint64_t j = d.lt / S::C;
   if (j * S::TILE >= d.L) return;  // reserved but past the segment end
@@ -256,6 +279,11 @@ __global__ __launch_bounds__(WG) void seg_large_tile_kernel(K* __restrict__ keys
   }
 }
 
+// The merge steps below are launched for every step the host plans; a step
+// past the longest segment's (counted on the device by classify) returns at
+// once.  Each kernel loops over the reserved merge tiles with a grid stride,
+// so the host may launch the steps beyond its length bound with a small grid.
+
 // Large segments, step j: partition (one thread per reserved merge tile):
 // the two-run split of a two-run step, or the samples (split, head and tail
 // keys) of a fused step.  Each segment's arrays start at its first reserved
@@ -264,58 +292,65 @@ template <class K, class V>
 __global__ __launch_bounds__(256) void seg_partition_kernel(const K* __restrict__ keys, const K* __restrict__ tk,
                                                             SegState st, int j) {
   using S = SegCfg<K, V>;
-  const uint64_t g = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (g >= ((*st.large_ctr) & SEG_TILE_MASK)) return;
-  const SegTile d = seg_tile(st.desc, g);
-  const int P = seg_passes(d.L, S::TILE), H = seg_steps(P), first = P & 1;
-  if (j >= H) return;
-  const uint64_t g0 = d.lt * S::MTILE;
-  if (g0 >= d.L) return;
-  const K* src = (((H - j) & 1) == 0 ? keys : tk) + d.base;
-  const uint64_t mb = g - d.lt;
-  if (j < first) {
-    const uint64_t W = uint64_t(S::TILE);
-    const PassGeom q = pass_geom(g0, d.L, W);
-    st.part[g] = int64_t(q.pb + merge_path_split(src + q.pb, q.a_end - q.pb, src + q.a_end, q.b_end - q.a_end,
-                                                  g0 - q.pb));
-  } else {
-    const uint64_t W = uint64_t(S::TILE) << (first + 2 * (j - first));
-    partition_group<K, 1>(src, d.L, W, uint32_t(S::MTILE), d.lt, DevCtl{nullptr, nullptr, nullptr}, 0u, 0u,
-                          st.part + mb, static_cast<K*>(st.head) + mb, static_cast<K*>(st.tail) + mb);
+  if (j >= int(*st.max_steps)) return;
+  if (st.io) keys = static_cast<const K*>(st.io[0]);
+  const uint64_t reserved = (*st.large_ctr) & SEG_TILE_MASK;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t g = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < reserved; g += stride) {
+    const SegTile d = seg_tile(st.desc, g);
+    const int P = seg_passes(d.L, S::TILE), H = seg_steps(P), first = P & 1;
+    if (j >= H) continue;
+    const uint64_t g0 = d.lt * S::MTILE;
+    if (g0 >= d.L) continue;
+    const K* src = (((H - j) & 1) == 0 ? keys : tk) + d.base;
+    const uint64_t mb = g - d.lt;
+    if (j < first) {
+      const uint64_t W = uint64_t(S::TILE);
+      const PassGeom q = pass_geom(g0, d.L, W);
+      st.part[g] = int64_t(q.pb + merge_path_split(src + q.pb, q.a_end - q.pb, src + q.a_end, q.b_end - q.a_end,
+                                                    g0 - q.pb));
+    } else {
+      const uint64_t W = uint64_t(S::TILE) << (first + 2 * (j - first));
+      partition_group<K, 1>(src, d.L, W, uint32_t(S::MTILE), d.lt, DevCtl{nullptr, nullptr, nullptr}, 0u, 0u,
+                            st.part + mb, static_cast<K*>(st.head) + mb, static_cast<K*>(st.tail) + mb);
+    }
   }
 }
 
-// Large segments, fused step j: the four-way partition of each output tile.
-template <class K, class V, int G>
+// Large segments, fused step j: the four-way partition of each output tile,
+// one lane per tile.
+template <class K, class V>
 __global__ __launch_bounds__(256) void seg_partition4_kernel(const K* __restrict__ keys, const K* __restrict__ tk,
                                                              SegState st, int j) {
   using S = SegCfg<K, V>;
-  const uint64_t g = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) / G;  // one tile per group of G lanes
-  const uint32_t q = threadIdx.x % G, gshift = (__lane_id() / G) * G;
-  if (g >= ((*st.large_ctr) & SEG_TILE_MASK)) return;  // group-uniform
-  const SegTile d = seg_tile(st.desc, g);
-  const int P = seg_passes(d.L, S::TILE), H = seg_steps(P), first = P & 1;
-  if (j >= H || j < first) return;
-  if (d.lt * S::MTILE >= d.L) return;
-  const K* src = (((H - j) & 1) == 0 ? keys : tk) + d.base;
-  const uint64_t mb = g - d.lt;
-  const uint64_t W = uint64_t(S::TILE) << (first + 2 * (j - first));
-  partition4_group<K, G>(src, d.L, W, uint32_t(S::MTILE), d.lt, q, gshift, st.part + mb,
-                         static_cast<const K*>(st.head) + mb, static_cast<const K*>(st.tail) + mb,
-                         st.part4 + 4 * mb);
+  if (j >= int(*st.max_steps)) return;
+  if (st.io) keys = static_cast<const K*>(st.io[0]);
+  const uint64_t reserved = (*st.large_ctr) & SEG_TILE_MASK;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t g = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < reserved; g += stride) {
+    const SegTile d = seg_tile(st.desc, g);
+    const int P = seg_passes(d.L, S::TILE), H = seg_steps(P), first = P & 1;
+    if (j >= H || j < first) continue;
+    if (d.lt * S::MTILE >= d.L) continue;
+    const K* src = (((H - j) & 1) == 0 ? keys : tk) + d.base;
+    const uint64_t mb = g - d.lt;
+    const uint64_t W = uint64_t(S::TILE) << (first + 2 * (j - first));
+    // a group of one lane: the lane is its own group's first lane
+    partition4_group<K, 1>(src, d.L, W, uint32_t(S::MTILE), d.lt, 0u, __lane_id(), st.part + mb,
+                           static_cast<const K*>(st.head) + mb, static_cast<const K*>(st.tail) + mb,
+                           st.part4 + 4 * mb);
+  }
 }
 
-// Large segments, two-run step p (p = 0 of an odd level count): merge (one
-// workgroup per reserved merge tile).
+// Large segments, two-run step p (p = 0 of an odd level count): the merge of
+// reserved merge tile g by the whole workgroup.
 template <class K, class V, int WG, int IPT, int PAD>
-__global__ __launch_bounds__(WG) void seg_merge_kernel(K* __restrict__ keys, V* __restrict__ vals,
-                                                       K* __restrict__ tk, V* __restrict__ tv, SegState st, int p) {
+__device__ __forceinline__ void seg_merge_tile(K* __restrict__ keys, V* __restrict__ vals, K* __restrict__ tk,
+                                               V* __restrict__ tv, const SegState& st, int p, uint64_t g,
+                                               unsigned char* smem) {
   using S = SegCfg<K, V>;
   using MT = MergeTile<K, V, WG, IPT, PAD>;
   static_assert(MT::TM == S::MTILE, "large-segment merge tile");
-  extern __shared__ __align__(16) unsigned char smem[];
-  const uint64_t g = blockIdx.x;
-  if (g >= ((*st.large_ctr) & SEG_TILE_MASK)) return;
   // the splits are loaded together with the descriptor (both indices are
   // inside the scratch arrays: g + 1 < reserved tiles + C <= mt_cap); values
   // that turn out not to be needed are ignored
@@ -350,17 +385,29 @@ __global__ __launch_bounds__(WG) void seg_merge_kernel(K* __restrict__ keys, V* 
   }
 }
 
-// Large segments, fused step j: one workgroup per reserved merge tile.
+template <class K, class V, int WG, int IPT, int PAD>
+__global__ __launch_bounds__(WG) void seg_merge_kernel(K* __restrict__ keys, V* __restrict__ vals,
+                                                       K* __restrict__ tk, V* __restrict__ tv, SegState st, int p) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (p >= int(*st.max_steps)) return;
+  keys = seg_io(st, 0, keys);
+  vals = seg_io(st, 1, vals);
+  const uint64_t reserved = (*st.large_ctr) & SEG_TILE_MASK;
+  for (uint64_t g = blockIdx.x; g < reserved; g += gridDim.x) {
+    seg_merge_tile<K, V, WG, IPT, PAD>(keys, vals, tk, tv, st, p, g, smem);
+    __syncthreads();
+  }
+}
+
+// Large segments, fused step j: reserved merge tile g by the whole workgroup.
 template <class K, class V, int WG, int IPT, int PAD, int REUSE>
-__global__ __launch_bounds__(WG) void seg_merge4_kernel(K* __restrict__ keys, V* __restrict__ vals,
-                                                        K* __restrict__ tk, V* __restrict__ tv, SegState st, int j) {
+__device__ __forceinline__ void seg_merge4_tile(K* __restrict__ keys, V* __restrict__ vals, K* __restrict__ tk,
+                                                V* __restrict__ tv, const SegState& st, int j, uint64_t g,
+                                                unsigned char* smem) {
   using S = SegCfg<K, V>;
   using MT = Merge4Tile<K, V, WG, IPT, PAD, REUSE>;
   using VV = typename MT::VV;
   static_assert(MT::TM == S::MTILE, "large-segment fused merge tile");
-  extern __shared__ __align__(16) unsigned char smem[];
-  const uint64_t g = blockIdx.x;
-  if (g >= ((*st.large_ctr) & SEG_TILE_MASK)) return;
   const SegTile d = seg_tile_wg(st.desc, g);
   const int P = seg_passes(d.L, S::TILE), H = seg_steps(P), first = P & 1;
   if (j >= H || j < first) return;  // workgroup-uniform
@@ -377,6 +424,20 @@ __global__ __launch_bounds__(WG) void seg_merge4_kernel(K* __restrict__ keys, V*
   } else {
     merge4_tile<MT>(sk, static_cast<const VV*>(nullptr), dk, static_cast<VV*>(nullptr), d.L, W, d.lt,
                     st.part4 + 4 * mb, smem);
+  }
+}
+
+template <class K, class V, int WG, int IPT, int PAD, int REUSE>
+__global__ __launch_bounds__(WG) void seg_merge4_kernel(K* __restrict__ keys, V* __restrict__ vals,
+                                                        K* __restrict__ tk, V* __restrict__ tv, SegState st, int j) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (j >= int(*st.max_steps)) return;
+  keys = seg_io(st, 0, keys);
+  vals = seg_io(st, 1, vals);
+  const uint64_t reserved = (*st.large_ctr) & SEG_TILE_MASK;
+  for (uint64_t g = blockIdx.x; g < reserved; g += gridDim.x) {
+    seg_merge4_tile<K, V, WG, IPT, PAD, REUSE>(keys, vals, tk, tv, st, j, g, smem);
+    __syncthreads();
   }
 }
 

@@ -131,3 +131,17 @@ def test_tuning_set_get_load(tmp_path):
     bad.write_text("gfx950 u32 zero\n")
     with pytest.raises(msort.MSortError):
         msort.ms_tuning_load(str(bad), "gfx950")
+
+
+def test_temp_bytes_of_every_form():
+    """Scratch sizes are host arithmetic: positive, growing with the input,
+    0 for unsupported types or invalid options."""
+    seg = [msort.ms_temp_bytes_segmented(m, n, 0, 0) for m, n in ((10, 1 << 16), (10, 1 << 20), (1000, 1 << 20))]
+    assert 0 < seg[0] < seg[1] < seg[2]
+    assert msort.ms_temp_bytes_segmented(10, 1 << 20, 3, 8) > seg[1]
+    assert msort.ms_temp_bytes_segmented(10, 1 << 20, 7, 0) == 0
+    lrn = [msort.ms_temp_bytes_learned(n) for n in (1 << 20, 1 << 24, 1 << 29)]
+    assert 0 < lrn[0] < lrn[1] < lrn[2]
+    # the learned scratch holds two n-key arrays (bucketed copy and spill) at least
+    assert lrn[2] >= 8 * (1 << 29)
+    assert msort.ms_temp_bytes_learned(1 << 20, bucket_capacity=1000) == 0

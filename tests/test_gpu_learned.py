@@ -171,6 +171,29 @@ def test_graph_replay_on_new_data(gpu):
         assert_equal_arrays(u32_np(t), oracle.sort(keys), f"replay seed {seed}")
 
 
+@pytest.mark.parametrize("mode", ["learned", "spill_repair", "fallback"])
+def test_fresh_buffers_replay_one_graph(gpu, mode):
+    """20 calls, each on a freshly allocated key tensor and a fresh stats
+    tensor: one graph capture for the 20, every output equal to the oracle's.
+    The three option sets take the learned path, the spill sort + repair
+    merge into the caller's buffer, and the plain fallback on the caller's
+    buffer, so each way the graph reaches the caller's keys is rebound."""
+    opts = {"learned": {},
+            "spill_repair": dict(bucket_capacity=4096, bucket_fill=2048, spill_threshold=0.5, train_steps=0),
+            "fallback": dict(force_fallback=1)}[mode]
+    before = msort.ms_graph_captures()
+    for rep in range(20):
+        keys = u32_np(workloads.lognormal_mix_u32(1 << 20, seed=100 + rep))
+        t = dev_u32(keys, gpu)
+        _, st = msort.ms_sort_ex(t, algo=msort.MS_ALGO_LEARNED_BUCKET, **opts)
+        torch.cuda.synchronize()
+        assert_equal_arrays(u32_np(t), oracle.sort(keys), f"{mode} call {rep}")
+        assert st["fallback_taken"] == (1 if mode == "fallback" else 0)
+        assert st["repaired"] == (1 if mode == "spill_repair" else 0)
+        del t
+    assert msort.ms_graph_captures() - before == 1
+
+
 def test_full_lognormal_2p29_learned_equals_plain(gpu):
     """Configuration 5 at full size: 2^29 uint32 keys from the 8-lognormal
     mixture; the learned-bucket output and the plain output both equal the

@@ -128,3 +128,46 @@ def test_full_batched_10000(gpu):
     kout = out.view(torch.int32).cpu().numpy().view(np.uint32)
     exp = oracle_segmented_threaded(kin, on, oracle.host_threads())
     assert_equal_arrays(kout, exp, "10,000 segments")
+
+
+def test_fresh_buffers_replay_one_graph(gpu):
+    """20 calls, each on freshly allocated key, value and offset tensors of
+    the same sizes: one graph capture in all, every output equal to the
+    oracle's (the graph reads the buffers bound at each launch)."""
+    rng = np.random.default_rng(24)
+    lens = rng.integers(0, 40000, size=257)
+    off = offsets_of(lens)
+    n = int(off[-1])
+    before = msort.ms_graph_captures()
+    for rep in range(20):
+        k = keys_fill(n, np.uint32, "few" if rep % 2 else "uniform", rng)
+        v = np.arange(n, dtype=np.uint32)
+        kt, vt, ot = to_dev(k, gpu), to_dev(v, gpu), to_dev(off, gpu)
+        msort.ms_segmented_sort(kt, ot, vt, max_segment_len=40000)
+        torch.cuda.synchronize()
+        ek, ev = oracle.segmented_sort(k, off, v)
+        assert_equal_arrays(kt.cpu().numpy(), ek, f"call {rep} keys")
+        assert_equal_arrays(vt.cpu().numpy(), ev, f"call {rep} values")
+        del kt, vt, ot
+    assert msort.ms_graph_captures() - before == 1
+
+
+@pytest.mark.parametrize("hint", [1000, 20000, 70000])
+def test_too_small_length_hint_still_sorts(gpu, hint):
+    """A max_segment_len below the longest segment (at or below the small
+    classes, or a few merge levels short) still sorts every segment: the
+    merge steps beyond the hint run on the device when it finds a longer
+    segment."""
+    rng = np.random.default_rng(25)
+    lens = np.concatenate([[300_000, 5, 70_001, 16_385, 200_000], rng.integers(0, 3000, size=100)])
+    off = offsets_of(lens)
+    for kdt, vdt in ((np.uint32, None), (np.int64, np.uint32)):
+        k = keys_fill(int(off[-1]), kdt, "uniform", rng)
+        v = None if vdt is None else np.arange(off[-1], dtype=vdt)
+        gk, gv = run_seg(k, off, v, gpu, max_len=hint)
+        if v is None:
+            assert_equal_arrays(gk, oracle.segmented_sort(k, off), f"hint {hint} keys")
+        else:
+            ek, ev = oracle.segmented_sort(k, off, v)
+            assert_equal_arrays(gk, ek, f"hint {hint} pair keys")
+            assert_equal_arrays(gv, ev, f"hint {hint} pair values")
