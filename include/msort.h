@@ -287,6 +287,26 @@ size_t ms_temp_bytes_segmented(size_t num_segments, size_t n_total, ms_key_type 
 ms_status ms_plan_query(size_t n, ms_key_type kt, size_t val_bytes, int* tile, int* merge_tile,
                         int* passes, int* tile_sort_in_place, int* hbm_passes, int* merge4_tile);
 
+/*
+ * ms_sort_noalloc -- ms_sort that allocates nothing, for callers that cannot
+ * allocate device memory (code under hipGraph stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, result and
+ * kernels as ms_sort; its scratch is a fixed __device__ array of
+ * MS_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held from the
+ * first call on that GPU until the process ends (its address is looked up
+ * with hipGetSymbolAddress on that first call; no hipMalloc, hipFree or
+ * allocating routine runs, and the event profiler records nothing here).
+ * Limit: n with ms_temp_bytes(n, kt, 0) <= MS_NOALLOC_SCRATCH_BYTES (about
+ * 16.7 million 32-bit keys or 8.4 million 64-bit keys); larger n returns
+ * MS_ERR_INVALID_ARG and enqueues nothing.
+ * Every call on one GPU shares that GPU's array: calls that may overlap in
+ * time on one GPU (different streams, or host threads on one stream without
+ * ordering) race on it and give undefined results.  Calls ordered on one
+ * stream are safe; no part of the array needs to start at zero.
+ */
+#define MS_NOALLOC_SCRATCH_BYTES (64u << 20)
+ms_status ms_sort_noalloc(void* d_keys, size_t n, ms_key_type kt, void* stream);
+
 /* Free the library's scratch buffers and cached segmented-sort graphs of the
  * current device (all streams).  Synchronises the device first. */
 ms_status ms_release_workspace(void);

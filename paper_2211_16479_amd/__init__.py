@@ -69,6 +69,7 @@ def _declare(lib):
         "ms_last_error": (c.c_char_p, []),
         "ms_sort": (i32, [vp, sz, i32, vp]),
         "ms_sort_pairs": (i32, [vp, vp, sz, i32, sz, vp]),
+        "ms_sort_noalloc": (i32, [vp, sz, i32, vp]),
         "ms_temp_bytes": (sz, [sz, i32, sz]),
         "ms_temp_bytes_segmented": (sz, [sz, sz, i32, sz]),
         "ms_temp_bytes_learned": (sz, [sz, c.POINTER(MsOptions)]),
@@ -143,6 +144,18 @@ def ms_sort(keys: torch.Tensor, key_type=None) -> torch.Tensor:
     _check(lib().ms_sort(ctypes.c_void_p(keys.data_ptr()), keys.numel(), _key_type(keys, key_type),
                          _stream(keys)), "ms_sort")
     return keys
+
+
+def ms_sort_noalloc(keys: torch.Tensor, key_type=None) -> torch.Tensor:
+    """ms_sort with the library's fixed per-GPU scratch array (no device
+    allocation); n is limited by MS_NOALLOC_SCRATCH_BYTES.  Returns keys."""
+    _dev(keys, "keys")
+    _check(lib().ms_sort_noalloc(ctypes.c_void_p(keys.data_ptr()), keys.numel(), _key_type(keys, key_type),
+                                 _stream(keys)), "ms_sort_noalloc")
+    return keys
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def ms_sort_pairs(keys: torch.Tensor, vals: torch.Tensor, key_type=None):

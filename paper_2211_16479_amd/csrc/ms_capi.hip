@@ -109,10 +109,14 @@ bool g_prof_on = false;
 std::vector<ProfRec> g_prof_recs;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_pool;
 size_t g_prof_used = 0;
+thread_local int g_prof_suppress = 0;
 }  // namespace
 
+ProfSuppress::ProfSuppress() { ++g_prof_suppress; }
+ProfSuppress::~ProfSuppress() { --g_prof_suppress; }
+
 ProfScope::ProfScope(int k, hipStream_t s) : kernel(k), stream(s), slot(-1) {
-  if (!g_prof_on) return;
+  if (!g_prof_on || g_prof_suppress) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);

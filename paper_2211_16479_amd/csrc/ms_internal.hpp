@@ -38,6 +38,13 @@ struct ProfScope {
   int slot;
 };
 
+// While one of these lives on a thread, ProfScope records nothing there
+// (entry points that must not create HIP objects).
+struct ProfSuppress {
+  ProfSuppress();
+  ~ProfSuppress();
+};
+
 void set_error(const std::string& msg);
 ms_status hip_fail(hipError_t e, const char* what);
 
