@@ -314,12 +314,15 @@ ms_status ms_release_workspace(void);
 /*
  * Event profiler (measurement support).  While enabled, every kernel launch
  * of the library is bracketed by a pair of HIP events recorded on the launch
- * stream.  ms_profile_read() synchronises those events and returns, for the
- * kernel class `kernel` (0 tile sort, 1 partition, 2 merge, 3 segment
- * classify, 4 small-segment sort, 5 large-segment passes, 6 MLP training,
- * 7 learned histograms, 8 learned scatters, 9 bucket sort, 10 other learned
- * kernels, 11 four-way partition, 12 fused four-run merge), the number of launches and their summed duration in
- * milliseconds since the last ms_profile_reset().
+ * stream (launches recorded into a graph are not timed).  ms_profile_read()
+ * synchronises those events and returns, for the kernel class `kernel`
+ * (0 tile sort, 1 two-run partition, 2 two-run merge, 3 segment classify,
+ * 4 small-segment sort, 5 large-segment passes, 6 MLP training, 7 learned
+ * level-1 histogram, 8 learned level-1 scatter, 9 bucket sort, 10 other
+ * learned kernels, 11 four-way partition, 12 fused four-run merge,
+ * 13 learned level-2 histogram, 14 learned level-2 scatter, 15 the sampling
+ * two-run partition of a fused pass), the number of launches and their
+ * summed duration in milliseconds since the last ms_profile_reset().
  */
 ms_status ms_profile_enable(int on);
 ms_status ms_profile_reset(void);

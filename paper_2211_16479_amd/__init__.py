@@ -26,7 +26,8 @@ KEY_TYPES = {torch.uint32: MS_KEY_U32, torch.int32: MS_KEY_I32,
 PROFILE_KERNELS = {"tile_sort": 0, "partition": 1, "merge": 2, "seg_classify": 3,
                    "seg_small": 4, "seg_large": 5, "mlp_train": 6, "learned_hist": 7,
                    "learned_scatter": 8, "bucket_sort": 9, "learned_other": 10,
-                   "partition4": 11, "merge4": 12}
+                   "partition4": 11, "merge4": 12, "learned_hist2": 13, "learned_scatter2": 14,
+                   "partition_samples": 15}
 
 MS_ALGO_AUTO, MS_ALGO_MERGE_PATH, MS_ALGO_LEARNED_BUCKET = 0, 1, 2
 MS_FEATURE_LOG, MS_FEATURE_LINEAR = 0, 1

@@ -227,6 +227,17 @@ __device__ __forceinline__ void load_run(const E* __restrict__ src, E (&v)[N]) {
   }
 }
 
+// A device pointer read from memory.  Typed as a global-memory pointer, the
+// loads and stores through it stay global instructions; read as a plain
+// void*, it would make the compiler fall back to flat instructions for every
+// access that might use it (slower, and they wait on LDS traffic too).
+template <class T>
+__device__ __forceinline__ T* global_ptr(const void* const* slot) {
+  typedef __attribute__((address_space(1))) void* gvoid;
+  const gvoid p = *(const gvoid*)(slot);
+  return (T*)(__attribute__((address_space(1))) T*)p;
+}
+
 // A caller's buffer that a cached hipGraph sees at launch time.  The graph's
 // kernels keep the pointer of the call that captured them (`token`); before
 // every replay the library writes the current call's pointer to *cur, and a
@@ -239,7 +250,7 @@ struct Rebind {
 
 template <class T>
 __device__ __forceinline__ T* rebind(T* p, const Rebind& r) {
-  return (r.cur && static_cast<const void*>(p) == r.token) ? static_cast<T*>(*r.cur) : p;
+  return (r.cur && static_cast<const void*>(p) == r.token) ? global_ptr<T>(r.cur) : p;
 }
 
 // Optional device-side controls shared by the sort kernels: an element count
@@ -248,12 +259,18 @@ __device__ __forceinline__ T* rebind(T* p, const Rebind& r) {
 // rebinding of the caller's key buffer under graph replay.
 struct DevCtl {
   const uint64_t* n_dev;      // if non-null, the element count (<= the host bound)
-  const int* gate;            // if non-null and *gate == 0, the kernel does nothing
+  const int* gate;            // if non-null and bit 0 of *gate is clear, the kernel does nothing
   const uint64_t* split_dev;  // if non-null: one merge of run [0, split) with [split, n)
   Rebind keys = {nullptr, nullptr};  // key-buffer arguments equal to keys.token read *keys.cur
+  int swap_bit = 0;  // 1: bit 1 of *gate set means the pass reads the buffers the other way round
+  const void* other = nullptr;  // with swap_bit: the planned destination keys (a partition kernel's source then)
 };
 
-__device__ __forceinline__ bool gated_off(const DevCtl& c) { return c.gate && *c.gate == 0; }
+// The gate word, 1 (run, no swap) when there is none: one load per kernel.
+__device__ __forceinline__ int gate_word(const DevCtl& c) { return c.gate ? *c.gate : 1; }
+__device__ __forceinline__ bool swap_set(const DevCtl& c, int gw) { return c.swap_bit && (gw & 2); }
+
+__device__ __forceinline__ bool gated_off(const DevCtl& c) { return c.gate && (*c.gate & 1) == 0; }
 
 // A value the caller knows to be the same in every lane of the wavefront
 // (a tile's offsets, read at a workgroup-uniform address), moved to scalar

@@ -26,7 +26,10 @@ enum ProfKernel {
   PK_LEARN_OTHER = 10,
   PK_PARTITION4 = 11,
   PK_MERGE4 = 12,
-  PK_COUNT = 13
+  PK_LEARN_HIST2 = 13,
+  PK_LEARN_SCATTER2 = 14,
+  PK_PARTITION_SAMPLES = 15,
+  PK_COUNT = 16
 };
 
 // Records a start/stop event pair around a launch when profiling is on.

@@ -194,14 +194,14 @@ static ms_status learned_enqueue(uint32_t* keys, uint64_t n, const ms_options& o
   }
   // level 2
   {
-    ProfScope ps(PK_LEARN_HIST, s);
+    ProfScope ps(PK_LEARN_HIST2, s);
     ls_hist2_kernel<<<unsigned(P.chunk_cap), LS_WG, 0, s>>>(coarse, md, bn);
   }
   ls_totals_kernel<<<P.nbc, LS_WG, 0, s>>>(md, bn, o.bucket_capacity);
   ls_plan2_kernel<<<1, LS_WG, 0, s>>>(md, bn, n, P.spill_cap, o.force_fallback, keys, xr, rk);
   ls_offsets_kernel<<<P.nbc, LS_WG, 0, s>>>(md, bn, o.bucket_capacity);
   {
-    ProfScope ps(PK_LEARN_SCATTER, s);
+    ProfScope ps(PK_LEARN_SCATTER2, s);
     ls_scatter2_kernel<<<unsigned(P.chunk_cap), LS_WG, 0, s>>>(coarse, md, bn, o.bucket_capacity, xr);
   }
   hipError_t e = hipGetLastError();

@@ -798,7 +798,7 @@ __global__ __launch_bounds__(LS_WG) void ls_scatter2_kernel(const uint32_t* __re
     }
   }
   __syncthreads();
-  uint32_t* rk_arr = static_cast<uint32_t*>(md->r_keys);
+  uint32_t* rk_arr = global_ptr<uint32_t>(&md->r_keys);
   for (uint32_t i = threadIdx.x; i < L.total; i += LS_WG) {
     const uint32_t x = L.stage[i];
     const uint32_t b = LS_SBIN ? uint32_t(L.sbin[i]) : (ls_bucket(&tb, x) & fmask);

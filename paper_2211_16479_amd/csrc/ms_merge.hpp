@@ -148,8 +148,9 @@ __global__ __launch_bounds__(256) void partition_kernel(const K* __restrict__ sr
                                                         int64_t* __restrict__ part, K* __restrict__ head = nullptr,
                                                         K* __restrict__ tail = nullptr) {
   static_assert(G >= 1 && G <= 64 && (64 % G) == 0, "group size");
-  if (gated_off(ctl)) return;
-  src = rebind(src, ctl.keys);
+  const int gw = gate_word(ctl);
+  if ((gw & 1) == 0) return;
+  src = swap_set(ctl, gw) ? global_ptr<const K>(&ctl.other) : rebind(src, ctl.keys);
   const uint64_t n = live_n(ctl, n_host);
   const uint32_t q = threadIdx.x % G, gshift = (__lane_id() / G) * G;
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
@@ -298,9 +299,21 @@ __global__ __launch_bounds__(WG) void merge_kernel(const K* __restrict__ src_k, 
                                                    const int64_t* __restrict__ part) {
   using MT = MergeTile<K, V, WG, IPT, PAD>;
   extern __shared__ __align__(16) unsigned char smem[];
-  if (gated_off(ctl)) return;
+  const int gw = gate_word(ctl);
+  if ((gw & 1) == 0) return;
   src_k = rebind(src_k, ctl.keys);
   dst_k = rebind(dst_k, ctl.keys);
+  {
+    const K* sk0 = src_k;
+    K* dk0 = dst_k;
+    if (swap_set(ctl, gw)) {
+      src_k = dk0;
+      dst_k = const_cast<K*>(sk0);
+      const V* sv0 = src_v;
+      src_v = dst_v;
+      dst_v = const_cast<V*>(sv0);
+    }
+  }
   const uint64_t n = live_n(ctl, n_host);
   // workgroup b merges tiles b, b + grid, ... (one each when the grid covers them)
   for (uint64_t k = blockIdx.x; k * MT::TM < n; k += gridDim.x) {
@@ -547,8 +560,9 @@ __global__ __launch_bounds__(256) void partition4_kernel(const K* __restrict__ s
                                                          const K* __restrict__ head, const K* __restrict__ tail,
                                                          int64_t* __restrict__ part4) {
   static_assert(G >= 1 && G <= 64 && (64 % G) == 0, "group size");
-  if (gated_off(ctl)) return;
-  src = rebind(src, ctl.keys);
+  const int gw = gate_word(ctl);
+  if ((gw & 1) == 0) return;
+  src = swap_set(ctl, gw) ? global_ptr<const K>(&ctl.other) : rebind(src, ctl.keys);
   const uint64_t n = live_n(ctl, n_host);
   const uint32_t q = threadIdx.x % G, gshift = (__lane_id() / G) * G;
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
@@ -768,9 +782,21 @@ __global__ __launch_bounds__(WG) void merge4_kernel(const K* __restrict__ src_k,
   using MT = Merge4Tile<K, V, WG, IPT, PAD, REUSE>;
   using VV = typename MT::VV;
   extern __shared__ __align__(16) unsigned char smem[];
-  if (gated_off(ctl)) return;
+  const int gw = gate_word(ctl);
+  if ((gw & 1) == 0) return;
   src_k = rebind(src_k, ctl.keys);
   dst_k = rebind(dst_k, ctl.keys);
+  {
+    const K* sk0 = src_k;
+    K* dk0 = dst_k;
+    if (swap_set(ctl, gw)) {
+      src_k = dk0;
+      dst_k = const_cast<K*>(sk0);
+      const V* sv0 = src_v;
+      src_v = dst_v;
+      dst_v = const_cast<V*>(sv0);
+    }
+  }
   const uint64_t n = live_n(ctl, n_host);
   for (uint64_t k = blockIdx.x; k * MT::TM < n; k += gridDim.x) {
     if constexpr (MT::PAIRS) {

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "ms_adaptive.hpp"
 #include "ms_block_sort.hpp"
 #include "ms_internal.hpp"
 #include "ms_merge.hpp"
@@ -53,7 +54,7 @@ size_t plain_temp_bytes(uint64_t n) {
   using C = PlainCfg<K, V>;
   const int P = plan_passes(n, C::TILE);
   const size_t vb = C::PAIRS ? sizeof(typename std::conditional<C::PAIRS, V, int>::type) : 0;
-  return plain_layout(n, sizeof(K), vb, C::MTILE, C::M4TILE, P, C::FUSED).bytes;
+  return plain_layout(n, sizeof(K), vb, C::TILE, C::MTILE, C::M4TILE, P, C::FUSED).bytes;
 }
 
 template <class K, class V>
@@ -66,7 +67,7 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
   const int P = plan_passes(n, C::TILE);
   const int H = plan_hbm_passes(P, C::FUSED);
   const size_t vb = C::PAIRS ? sizeof(typename std::conditional<C::PAIRS, V, int>::type) : 0;
-  const PlainLayout L = plain_layout(n, sizeof(K), vb, C::MTILE, C::M4TILE, P, C::FUSED);
+  const PlainLayout L = plain_layout(n, sizeof(K), vb, C::TILE, C::MTILE, C::M4TILE, P, C::FUSED);
   char* w = static_cast<char*>(ws);
   K* tk = P ? reinterpret_cast<K*>(w + L.keys_off) : nullptr;
   V* tv = (P && C::PAIRS) ? reinterpret_cast<V*>(w + L.vals_off) : nullptr;
@@ -74,6 +75,10 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
   int64_t* part4 = P ? reinterpret_cast<int64_t*>(w + L.part4_off) : nullptr;
   K* head = P ? reinterpret_cast<K*>(w + L.head_off) : nullptr;
   K* tail = P ? reinterpret_cast<K*>(w + L.tail_off) : nullptr;
+  int* ctlw = P ? reinterpret_cast<int*>(w + L.ctl_off) : nullptr;
+  // run-adaptive pass skipping (ms_adaptive.hpp) for plain calls; sorts that
+  // are already gated or sized on the device keep every pass
+  const bool adaptive = P > 0 && !ctl.gate && !ctl.n_dev && !ctl.split_dev && !ctl.keys.cur;
 
   K* cur_k = tile_sort_in_place(H) ? keys : tk;
   V* cur_v = tile_sort_in_place(H) ? vals : tv;
@@ -94,50 +99,68 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "tile sort launch");
+  if (adaptive) {
+    const PassPlan pp = plan_pass_levels(P, C::FUSED);
+    const uint64_t groups = ceil_div(ceil_div(n, C::TILE), RUN_GROUP);
+    K* runs = reinterpret_cast<K*>(w + L.runs_off);
+    uint32_t* gmask = reinterpret_cast<uint32_t*>(runs + 4 * groups);
+    run_bounds_kernel<K><<<dim3(unsigned(groups)), dim3(RUN_GROUP), 0, s>>>(
+        keys, tk, n, uint32_t(C::TILE), P, pp.start_in_caller, runs, runs + groups, gmask);
+    run_decide_kernel<K><<<1, 1024, 0, s>>>(groups, pp, runs, runs + groups, runs + 2 * groups, runs + 3 * groups,
+                                            gmask, ctlw);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "run check launch");
+  }
   // splits at every Tm outputs of each pair; with_keys: the keys around them too
-  auto partition = [&](uint64_t W, uint32_t Tm, bool with_keys) {
+  auto partition = [&](const DevCtl& pc, uint64_t W, uint32_t Tm, bool with_keys) {
     const uint64_t nt = ceil_div(n, Tm);
-    ProfScope ps(PK_PARTITION, s);
+    ProfScope ps(with_keys ? PK_PARTITION_SAMPLES : PK_PARTITION, s);
     with_search_group(search_group(nt), [&](auto gc) {
       constexpr int G = decltype(gc)::value;
       partition_kernel<K, G><<<dim3(unsigned(std::min(ceil_div(nt * G, 256), cap))), dim3(256), 0, s>>>(
-          cur_k, n, ctl, W, Tm, nt, part, with_keys ? head : nullptr, with_keys ? tail : nullptr);
+          cur_k, n, pc, W, Tm, nt, part, with_keys ? head : nullptr, with_keys ? tail : nullptr);
     });
   };
   // levels p (width W = T * 2^p): an odd level count starts with one two-run
   // pass, then every fused pass takes two levels
-  int p = 0;
+  int p = 0, h = 0;
   while (p < P) {
     const uint64_t W = uint64_t(C::TILE) << p;
     K* nxt_k = (cur_k == keys) ? tk : keys;
     V* nxt_v = (cur_k == keys) ? tv : vals;
     const bool fuse = C::FUSED && (P - p) % 2 == 0;
+    DevCtl pc = ctl;  // this pass's controls: with run-adaptive skipping, a run flag and a swap flag
+    if (adaptive) {
+      pc.gate = ctlw + ctl_run(h);
+      pc.swap_bit = 1;
+      pc.other = nxt_k;
+    }
     if (fuse) {
       const uint64_t mt4 = ceil_div(n, C::M4TILE);
-      partition(W, C::M4TILE, true);
+      partition(pc, W, C::M4TILE, true);
       {
         ProfScope ps(PK_PARTITION4, s);
         with_search_group(search_group(mt4), [&](auto gc) {
           constexpr int G = decltype(gc)::value;
           partition4_kernel<K, G><<<dim3(unsigned(std::min(ceil_div(mt4 * G, 256), cap))), dim3(256), 0, s>>>(
-              cur_k, n, ctl, W, C::M4TILE, mt4, part, head, tail, part4);
+              cur_k, n, pc, W, C::M4TILE, mt4, part, head, tail, part4);
         });
       }
       {
         ProfScope ps(PK_MERGE4, s);
         merge4_kernel<K, V, C::M4_WG, C::M4_IPT, C::M4_PAD, C::M4_REUSE>
             <<<dim3(unsigned(std::min(mt4, cap))), dim3(C::M4_WG), M4::LDS_BYTES, s>>>(cur_k, cur_v, nxt_k, nxt_v, n,
-                                                                                     ctl, W, part4);
+                                                                                     pc, W, part4);
       }
       p += 2;
     } else {
       const uint64_t mtiles = ceil_div(n, C::MTILE);
-      partition(W, C::MTILE, false);
+      partition(pc, W, C::MTILE, false);
       {
         ProfScope ps(PK_MERGE, s);
         merge_kernel<K, V, C::MG_WG, C::MG_IPT, C::MG_PAD>
             <<<dim3(unsigned(std::min(mtiles, cap))), dim3(C::MG_WG), MT::LDS_BYTES, s>>>(cur_k, cur_v, nxt_k, nxt_v,
-                                                                                       n, ctl, W, part);
+                                                                                       n, pc, W, part);
       }
       p += 1;
     }
@@ -145,6 +168,13 @@ ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, vo
     if (e != hipSuccess) return hip_fail(e, "merge pass launch");
     cur_k = nxt_k;
     cur_v = nxt_v;
+    ++h;
+  }
+  if (adaptive) {
+    copy_back_kernel<K, V><<<dim3(unsigned(std::min<uint64_t>(ceil_div(n, 256), uint64_t(device_cu_count()) * 8))),
+                             dim3(256), 0, s>>>(tk, tv, keys, vals, n, ctlw);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "final copy launch");
   }
   return MS_OK;
 }

@@ -52,10 +52,10 @@ struct SegState {
 // The caller's buffer in slot i of this launch (graph replays rebind them).
 template <class T>
 __device__ __forceinline__ T* seg_io(const SegState& st, int i, T* p) {
-  return st.io ? static_cast<T*>(st.io[i]) : p;
+  return st.io ? global_ptr<T>(&st.io[i]) : p;
 }
 __device__ __forceinline__ const int64_t* seg_bind_off(const SegState& st, const int64_t* off) {
-  return st.io ? static_cast<const int64_t*>(st.io[2]) : off;
+  return st.io ? global_ptr<const int64_t>(&st.io[2]) : off;
 }
 
 // A reserved merge tile of a large segment, unpacked from its descriptor.
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(WG) void seg_small_kernel(K* __restrict__ keys, V* 
   keys = seg_io(st, 0, keys);
   vals = seg_io(st, 1, vals);
   off = seg_bind_off(st, off);
-  if (st.keys_sel) keys = static_cast<K*>(*st.keys_sel);
+  if (st.keys_sel) keys = global_ptr<K>(st.keys_sel);
   uint32_t c0 = blockIdx.x * chunk;
   while (c0 < count) {
     const uint32_t c1 = c0 + chunk < count ? c0 + chunk : count;
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(256) void seg_partition_kernel(const K* __restrict_
                                                             SegState st, int j) {
   using S = SegCfg<K, V>;
   if (j >= int(*st.max_steps)) return;
-  if (st.io) keys = static_cast<const K*>(st.io[0]);
+  keys = seg_io(st, 0, keys);
   const uint64_t reserved = (*st.large_ctr) & SEG_TILE_MASK;
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
   for (uint64_t g = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < reserved; g += stride) {
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) void seg_partition4_kernel(const K* __restrict
                                                              SegState st, int j) {
   using S = SegCfg<K, V>;
   if (j >= int(*st.max_steps)) return;
-  if (st.io) keys = static_cast<const K*>(st.io[0]);
+  keys = seg_io(st, 0, keys);
   const uint64_t reserved = (*st.large_ctr) & SEG_TILE_MASK;
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
   for (uint64_t g = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < reserved; g += stride) {
