@@ -2,19 +2,27 @@
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-A step is one whole sort (tile sort + every merge pass) of one fresh copy of
-the workload, already resident in HBM.  K + W distinct copies are generated
-on the GPU before timing, so no restore copy sits inside the timed region.
-The K timed steps are bracketed by torch.cuda.synchronize(); while they run
-the library's event profiler brackets every kernel launch with HIP events
-on the launch stream, which gives the dominant kernel's average duration.
+Default workload: 2^29 uint32 keys from the 8-lognormal mixture, sorted by
+the learned-bucket form (the headline: its Gkeys/s is `value`) and by the
+plain merge-path form beside it, with a byte-for-byte comparison of the two
+outputs.  A step is one whole sort of one fresh copy of the workload,
+already resident in HBM: K + W copies are made before timing, so nothing but
+the sorts runs in the timed region.  The K timed steps are bracketed by
+torch.cuda.synchronize() on both sides; while they run the library's event
+profiler brackets every kernel launch with HIP events on the launch stream,
+which gives each kernel class's average duration.
 
-Prints one JSON line.  `roofline` prices the dominant kernel (the merge pass)
-at its algorithmic bytes per launch (read + write of every key and value)
-against MI355X's 8 TB/s HBM peak; `cpu_baseline` times the CPU oracle
-(single-threaded C merge sort) on a bounded sample of the same workload.
+`roofline` prices the headline form's dominant kernel at its algorithmic
+bytes per launch against MI355X's 8 TB/s HBM peak; the plain form and the
+extra workloads (2^27 Zipf pairs, 2^27 uint32 keys) carry their own.
+`cpu_baseline` times the CPU oracle (the plain C merge sort) on a bounded
+sample of the same workload with every host core (threaded top levels), and
+on one core beside it.
+
+Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,9 +32,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "Gkeys/s and HBM GB/s vs peak, plain merge-path vs learned-bucket, bit-exact"
 
 WORKLOADS = {
     # name: (description, n, key bytes, value bytes, C-ABI key type)
+    "lognormal_u32_2p29": ("2^29 uint32 keys from an equal-weight mixture of 8 lognormals (mu ~ U(0,4), "
+                           "sigma ~ U(0.1,1), scaled and clipped to uint32): learned-bucket sort vs plain merge "
+                           "path", 1 << 29, 4, 0, 0),
     "zipf_pairs_u32_2p27": ("stable key/value sort of 2^27 pairs: uint32 keys Zipf(s=1.1) over 2^20 "
                             "distinct values, uint32 value = original index", 1 << 27, 4, 4, 0),
     "uniform_u32_2p27": ("merge sort of 2^27 uint32 keys uniform in [0, 2^32), keys only", 1 << 27, 4, 0, 0),
@@ -35,29 +47,25 @@ WORKLOADS = {
     "normal_i64_2p28": ("merge sort of 2^28 int64 keys round(N(0, 1) * 2^40), keys only", 1 << 28, 8, 0, 3),
     "nearly_sorted_i64_2p28": ("merge sort of the sorted 2^28 int64 normal array with 1% disjoint adjacent "
                                "swaps, keys only", 1 << 28, 8, 0, 3),
-    "lognormal_u32_2p29": ("2^29 uint32 keys from an equal-weight mixture of 8 lognormals (mu ~ U(0,4), "
-                           "sigma ~ U(0.1,1), scaled and clipped to uint32): learned-bucket sort vs plain merge "
-                           "path", 1 << 29, 4, 0, 0),
     "segments_u32_10000": ("batched segmented sort: 10,000 independent uint32 arrays, lengths log-uniform in "
                            "[16, 2^18], uniform keys, one graph launch, autotuned shape per size class",
                            None, 4, 0, 0),
 }
 
+KERNEL_SOURCES = ("ms_common.hpp", "ms_merge.hpp", "ms_plain_cfg.hpp", "ms_learned.hpp", "ms_segmented.hpp",
+                  "ms_block_sort.hpp")
 
-MERGE_KERNEL_SOURCES = ("ms_common.hpp", "ms_merge.hpp", "ms_plain_cfg.hpp")
 
-
-def merge_kernel_source_hash() -> str:
-    """sha256 over the sources that define the merge kernel and its shape."""
-    import hashlib
+def kernel_source_hash() -> str:
+    """sha256 over the sources that define the kernels and their shapes."""
     h = hashlib.sha256()
-    for f in MERGE_KERNEL_SOURCES:
+    for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2211_16479_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def profiled_traffic(workload: str, kernel: str = "merge_kernel"):
+def profiled_traffic(workload: str, kernel: str):
     """Calibrated HBM bytes per launch of `kernel` from the committed counter
     summary, or None when there is none or the kernel sources changed since."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
@@ -68,7 +76,7 @@ def profiled_traffic(workload: str, kernel: str = "merge_kernel"):
         if ":" in line and not line.startswith(("|", " ", "#")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    if fields.get("source_sha256") != merge_kernel_source_hash():
+    if fields.get("source_sha256") != kernel_source_hash():
         return None
     try:
         return int(fields["traffic_bytes_per_launch"])
@@ -76,27 +84,21 @@ def profiled_traffic(workload: str, kernel: str = "merge_kernel"):
         return None
 
 
-def make_inputs(name, copies, dev):
-    import torch
-    import workloads
-    if name == "zipf_pairs_u32_2p27":
-        k, v = workloads.zipf_pairs_u32(1 << 27, seed=0, device=dev)
-        return [(k.clone(), v.clone()) for _ in range(copies)], (k, v)
-    if name == "uniform_u32_2p27":
-        k = workloads.uniform_u32(1 << 27, seed=0, device=dev)
-        return [(k.clone(), None) for _ in range(copies)], (k, None)
-    if name == "uniform_u32_2p20":
-        k = workloads.uniform_u32(1 << 20, seed=0, device=dev)
-        return [(k.clone(), None) for _ in range(copies)], (k, None)
-    if name == "segments_u32_10000":
-        k, off = workloads.segments_u32(10000, seed=0, device=dev)
-        return [(k.clone(), off)], (k, off)
-    if name in ("normal_i64_2p28", "nearly_sorted_i64_2p28"):
-        k = workloads.normal_i64(1 << 28, seed=0, device=dev)
-        if name == "nearly_sorted_i64_2p28":
-            k = workloads.nearly_sorted(torch.sort(k).values, 0.01, seed=0)
-        return [(k.clone(), None) for _ in range(copies)], (k, None)
-    raise SystemExit(f"unknown workload {name}")
+def host_info() -> dict:
+    """Host cores and CPU model (the oracle's machine)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return {"nproc": os.cpu_count(), "affinity_cpus": affinity, "cpu_model": model}
 
 
 def _host(t):
@@ -108,129 +110,259 @@ def _host(t):
     return t.cpu().numpy()
 
 
-def cpu_baseline(name, pristine, budget_s=20.0):
-    """Time the CPU oracle on a bounded prefix of the workload: the largest
-    power-of-two prefix whose estimated single-threaded sort time fits the
-    budget (estimated from a small calibration sort)."""
+def sha256_of(*tensors) -> str:
+    h = hashlib.sha256()
+    for t in tensors:
+        h.update(memoryview(_host(t)).cast("B"))
+    return h.hexdigest()
+
+
+def make_pristine(name, dev):
+    """The workload's input on the device: (keys, values or None)."""
+    import torch
+    import workloads
+    n = WORKLOADS[name][1]
+    if name == "lognormal_u32_2p29":
+        return workloads.lognormal_mix_u32(n, seed=0, device=dev), None
+    if name == "zipf_pairs_u32_2p27":
+        return workloads.zipf_pairs_u32(n, seed=0, device=dev)
+    if name in ("uniform_u32_2p27", "uniform_u32_2p20"):
+        return workloads.uniform_u32(n, seed=0, device=dev), None
+    if name in ("normal_i64_2p28", "nearly_sorted_i64_2p28"):
+        k = workloads.normal_i64(n, seed=0, device=dev)
+        if name == "nearly_sorted_i64_2p28":
+            k = workloads.nearly_sorted(torch.sort(k).values, 0.01, seed=0)
+        return k, None
+    raise SystemExit(f"unknown workload {name}")
+
+
+def read_kernels(K: int) -> dict:
+    import paper_2211_16479_amd as msort
+    out = {}
+    for name in msort.PROFILE_KERNELS:
+        cnt, tot = msort.ms_profile_read(name)
+        if cnt:
+            out[name] = {"launches": cnt, "avg_us": round(tot / cnt * 1e3, 2), "ms_per_step": round(tot / K, 4)}
+    return out
+
+
+def timed_steps(step, K: int, W: int, events: bool, classes=None):
+    """W untimed steps, then exactly K steps between two synchronisations;
+    returns (ms per step, per-kernel-class event times of the K steps).
+    classes: the kernel classes bracketed by events (None: all)."""
+    import torch
+    import paper_2211_16479_amd as msort
+    for i in range(W):
+        step(i)
+    torch.cuda.synchronize()
+    msort.ms_profile_reset()
+    msort.ms_profile_select(classes)
+    msort.ms_profile_enable(events)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(W, W + K):
+        step(i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    msort.ms_profile_enable(False)
+    return (t1 - t0) * 1e3 / K, (read_kernels(K) if events else {})
+
+
+def hbm_entry(kernel: str, bytes_per_launch: int, avg_us: float, workload: str = None, trace_name: str = None):
+    achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": profiled_traffic(workload, trace_name) if workload and trace_name else None,
+            "kernel": kernel, "bytes_per_launch": int(bytes_per_launch), "avg_us": round(avg_us, 2)}
+
+
+MERGE4_TRACE = "merge4_kernel"
+
+
+def plain_roofline(name, n, kb, vb, kernels):
+    """The plain form's dominant kernel (the fused four-run merge, else the
+    two-run merge) and the whole fused pass (its sampling partition, four-way
+    partition and merge)."""
+    per = n * (kb + vb) * 2      # read + write of every key and value per pass
+    dom = max((k for k in ("merge", "merge4") if k in kernels), key=lambda k: kernels[k]["ms_per_step"],
+              default=None)
+    if dom is None:
+        return None, None
+    kname = "merge4_kernel" if dom == "merge4" else "merge_kernel"
+    roof = hbm_entry(kname, per, kernels[dom]["avg_us"], name, kname)
+    fused = None
+    if "merge4" in kernels and "partition4" in kernels and "partition_samples" in kernels:
+        m4 = kernels["merge4"]
+        if kernels["partition4"]["launches"] == m4["launches"] == kernels["partition_samples"]["launches"]:
+            us = sum(kernels[k]["avg_us"] for k in ("partition_samples", "partition4", "merge4"))
+            fused = hbm_entry("partition_kernel (samples) + partition4_kernel + merge4_kernel", per, us)
+            fused["share_of_pass"] = {k: round(kernels[k]["avg_us"] / us, 3)
+                                      for k in ("partition_samples", "partition4", "merge4")}
+    return roof, fused
+
+
+PLAIN_TIMED = ["tile_sort", "partition", "merge", "partition_samples", "partition4", "merge4"]
+
+
+def plain_form(name, K, W, dev, events=True):
+    """K timed plain sorts of fresh copies of workload `name`."""
+    import torch
+    import paper_2211_16479_amd as msort
+    desc, n, kb, vb, kt = WORKLOADS[name]
+    pk, pv = make_pristine(name, dev)
+    sha = sha256_of(pk) if pv is None else sha256_of(pk, pv)
+    bufs = [(pk.clone(), None if pv is None else pv.clone()) for _ in range(K + W)]
+    torch.cuda.synchronize()
+
+    def step(i):
+        k, v = bufs[i]
+        if v is None:
+            msort.ms_sort(k)
+        else:
+            msort.ms_sort_pairs(k, v)
+
+    ms, kernels = timed_steps(step, K, W, events, classes=PLAIN_TIMED)
+    plan = msort.ms_plan_query(n, kt, vb)
+    roof, fused = plain_roofline(name, n, kb, vb, kernels)
+    out = {"workload": desc, "n": n, "key_bytes": kb, "value_bytes": vb, "ms_per_step": round(ms, 4),
+           "Gkeys_s": round(n / (ms * 1e-3) / 1e9, 3),
+           "whole_sort_hbm_GBs": round(n * (kb + vb) * 2 * (1 + plan["hbm_passes"]) / (ms * 1e-3) / 1e9, 1),
+           "plan": plan, "input_sha256": sha, "kernels": kernels, "roofline": roof, "fused_pass": fused}
+    result = bufs[W][0]           # sorted output of the first timed step
+    del bufs
+    return out, pk, pv, result
+
+
+LEARNED_STAGES = {
+    # profiler class: (kernels, algorithmic bytes per key processed)
+    "learned_hist": ("ls_hist1_kernel", 4),       # read every key
+    "learned_scatter": ("ls_scatter1_kernel", 8),  # read and write every key
+    "learned_hist2": ("ls_hist2_kernel", 4),
+    "learned_scatter2": ("ls_scatter2_kernel", 8),
+    "bucket_sort": ("seg_init/classify/owner + seg_small_kernel per class", 8),  # kept keys, read + write
+}
+
+
+def learned_form(K, W, dev, pristine, use_graph):
+    """K timed learned-bucket sorts of fresh copies of the lognormal mixture."""
+    import torch
+    import paper_2211_16479_amd as msort
+    n = pristine.numel()
+    bufs = [pristine.clone() for _ in range(K + W)]
+    torch.cuda.synchronize()
+
+    def step(i):
+        msort.ms_sort_ex(bufs[i], algo=msort.MS_ALGO_LEARNED_BUCKET, stats=False, use_graph=1 if use_graph else 0)
+
+    # only the stages priced below are bracketed by events (the training
+    # steps and the small kernels would add an event pair per launch)
+    ms, kernels = timed_steps(step, K, W, events=not use_graph, classes=list(LEARNED_STAGES))
+    # device-side statistics of one more sort of the same input (untimed)
+    extra = pristine.clone()
+    _, st = msort.ms_sort_ex(extra, algo=msort.MS_ALGO_LEARNED_BUCKET, use_graph=1 if use_graph else 0)
+    torch.cuda.synchronize()
+    kept = n - int(st["spilled"]) if not st["fallback_taken"] else 0
+    stages = {}
+    for cls, (kname, bpk) in LEARNED_STAGES.items():
+        if cls in kernels:
+            keys = kept if cls == "bucket_sort" else n
+            stages[cls] = hbm_entry(kname, bpk * keys, kernels[cls]["avg_us"])
+            stages[cls]["ms_per_step"] = kernels[cls]["ms_per_step"]
+    dom = max(stages, key=lambda c: stages[c]["ms_per_step"], default=None)
+    roof = None
+    if dom:
+        roof = dict(stages[dom])
+        roof.pop("ms_per_step")
+        roof["traffic"] = profiled_traffic("lognormal_u32_2p29", roof["kernel"].split(" ")[0])
+    out = {"ms_per_step": round(ms, 4), "Gkeys_s": round(n / (ms * 1e-3) / 1e9, 3), "graph_replay": bool(use_graph),
+           "learned_stats": {k: (round(v, 8) if isinstance(v, float) else v) for k, v in st.items()},
+           "kernels": kernels, "stages": stages, "dominant": dom}
+    result = bufs[W]
+    del bufs
+    return out, roof, result, extra
+
+
+def cpu_baselines(name, keys, vals, budget_s=12.0):
+    """The CPU oracle on a bounded power-of-two prefix of the workload:
+    with every host core (the oracle's threaded top levels; the paper's
+    multiprocessing form) and with one core (its sequential form).  The
+    prefix is the largest whose single-core sort is estimated to fit the
+    budget (from a small calibration sort)."""
     import numpy as np
     import oracle
-    k, v = pristine
-    kn = _host(k)
-    vn = None if v is None else _host(v)
-    # calibration on 2^18 keys
+    kn = _host(keys)
+    vn = None if vals is None else _host(vals)
     m = min(kn.size, 1 << 18)
-    t0 = time.perf_counter()
-    if vn is None:
-        oracle.sort(kn[:m])
-    else:
-        oracle.sort_pairs(kn[:m], vn[:m])
-    t_cal = time.perf_counter() - t0
+
+    def run(s, threads):
+        t0 = time.perf_counter()
+        if vn is None:
+            oracle.sort(kn[:s], threads=threads)
+        else:
+            oracle.sort_pairs(kn[:s], vn[:s], threads=threads)
+        return time.perf_counter() - t0
+
+    t_cal = run(m, 1)
     per_key_level = t_cal / (m * max(1, np.log2(m)))
     s = m
     while s * 2 <= kn.size and per_key_level * (2 * s) * np.log2(2 * s) < budget_s:
         s *= 2
-    t0 = time.perf_counter()
-    if vn is None:
-        oracle.sort(kn[:s])
-    else:
-        oracle.sort_pairs(kn[:s], vn[:s])
-    dt = time.perf_counter() - t0
     what = "pairs" if vn is not None else "keys"
-    return {"value": s / dt / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-            "sample": f"first 2^{int(np.log2(s))} {what} of the workload, one single-threaded oracle "
-                      f"merge sort, {dt:.2f} s"}
+    threads = oracle.host_threads()
+    t_all = run(s, threads)
+    t_one = run(s, 1)
+    sample = f"first 2^{int(np.log2(s))} {what} of the workload"
+    return {"value": round(s / t_all / 1e9, 5), "unit": "Gkeys/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sample}, oracle merge sort with its top levels on {threads} threads, {t_all:.2f} s",
+            "single_core": {"value": round(s / t_one / 1e9, 5), "unit": "Gkeys/s", "cores": 1,
+                            "sample": f"{sample}, single-threaded oracle merge sort, {t_one:.2f} s"},
+            "host": host_info()}
 
 
-def time_restored(fn, work, pristine, steps, warmup):
-    """Mean event-timed duration (ms) of fn() over `steps` runs; before each
-    run the pristine input is copied into `work`, outside the event window."""
+def copy_ceiling(dev, nbytes=1 << 31, reps=5):
+    """torch's device-to-device copy of nbytes, event-timed: read + write
+    bytes per second (a practical HBM ceiling next to the 8 TB/s peak)."""
     import torch
-    stream = torch.cuda.current_stream()
-    for _ in range(warmup):
-        work.copy_(pristine)
-        fn()
+    a = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
     torch.cuda.synchronize()
-    total = 0.0
-    for _ in range(steps):
-        work.copy_(pristine)
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        a.record(stream)
-        fn()
-        b.record(stream)
-        torch.cuda.synchronize()
-        total += a.elapsed_time(b)
-    return total / steps
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": nbytes, "avg_us": round(ms * 1e3, 2),
+            "GBs_read_plus_write": round(2 * nbytes / (ms * 1e-3) / 1e9, 1),
+            "frac_of_peak": round(2 * nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
-def learned_vs_plain(steps=5, warmup=2):
-    """Both forms on the 2^29 lognormal-mixture workload, the same way:
-    Gkeys/s of each, the speedup, whether the two outputs are byte-identical,
-    and the learned run's device-side statistics."""
+def bench_segmented(args, dev):
+    """One step = one ms_segmented_sort (one graph launch) of all 10,000
+    arrays; a fresh copy of the keys per step."""
     import torch
     import paper_2211_16479_amd as msort
     import workloads
-    dev = torch.device("cuda:0")
-    n = 1 << 29
-    pristine = workloads.lognormal_mix_u32(n, seed=0, device=dev)
-    work = torch.empty_like(pristine)
-    t_plain = time_restored(lambda: msort.ms_sort(work), work, pristine, steps, warmup)
-    out_plain = work.clone()
-    t_learned = time_restored(lambda: msort.ms_sort_ex(work, algo=msort.MS_ALGO_LEARNED_BUCKET, stats=False),
-                              work, pristine, steps, warmup)
-    work.copy_(pristine)
-    _, st = msort.ms_sort_ex(work, algo=msort.MS_ALGO_LEARNED_BUCKET)
-    torch.cuda.synchronize()
-    same = bool((work.view(torch.int32) == out_plain.view(torch.int32)).all())
-    del out_plain, work, pristine
-    torch.cuda.empty_cache()
-    return {"workload": WORKLOADS["lognormal_u32_2p29"][0], "n": n,
-            "plain_ms": round(t_plain, 4), "plain_Gkeys_s": round(n / (t_plain * 1e-3) / 1e9, 3),
-            "learned_ms": round(t_learned, 4), "learned_Gkeys_s": round(n / (t_learned * 1e-3) / 1e9, 3),
-            "speedup": round(t_plain / t_learned, 3), "outputs_identical": same,
-            "learned_stats": {k: (round(v, 8) if isinstance(v, float) else v) for k, v in st.items()}}
-
-
-def bench_segmented(args, desc):
-    """One step = one ms_segmented_sort (one graph launch) of all 10,000
-    arrays.  The same buffers are reused so the cached graph is replayed; the
-    pristine keys are restored before each step, outside the event window,
-    and the K event-timed steps are summed."""
-    import torch
-    import paper_2211_16479_amd as msort
-    dev = torch.device("cuda:0")
+    desc = WORKLOADS["segments_u32_10000"][0]
     K, W = args.steps, args.warmup
-    [(work, off)], (pristine, _) = make_inputs(args.workload, 1, dev)
-    n = work.numel()
-    stream = torch.cuda.current_stream()
-    for _ in range(W):
-        work.copy_(pristine)
-        msort.ms_segmented_sort(work, off, max_segment_len=1 << 18)
+    keys, off = workloads.segments_u32(10000, seed=0, device=dev)
+    n = keys.numel()
+    bufs = [keys.clone() for _ in range(K + W)]
     torch.cuda.synchronize()
-    total_ms = 0.0
-    for _ in range(K):
-        work.copy_(pristine)
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        a.record(stream)
-        msort.ms_segmented_sort(work, off, max_segment_len=1 << 18)
-        b.record(stream)
-        torch.cuda.synchronize()
-        total_ms += a.elapsed_time(b)
-    ms_per_step = total_ms / K
+    ms, _ = timed_steps(lambda i: msort.ms_segmented_sort(bufs[i], off, max_segment_len=1 << 18), K, W, False)
     shapes = {f"class{c}(<={bd})": "x".join(map(str, msort.ms_tuning_get(0, 0, c)))
               for c, (bd, _) in enumerate(msort.ms_seg_classes(0, 0))}
-    out = {
-        "metric": "Gkeys/s and HBM GB/s vs peak, plain merge-path vs learned-bucket, bit-exact",
-        "value": round(n / (ms_per_step * 1e-3) / 1e9, 4),
-        "unit": "Gkeys/s", "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": desc, "n": n, "segments": off.numel() - 1, "class_shapes": shapes},
-        "roofline": None, "cpu_baseline": None,
-    }
-    print(json.dumps(out))
+    print(json.dumps({
+        "metric": METRIC, "value": round(n / (ms * 1e-3) / 1e9, 4), "unit": "Gkeys/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": desc, "n": n, "segments": off.numel() - 1, "class_shapes": shapes,
+                   "input_sha256": sha256_of(keys, off)},
+        "roofline": None, "cpu_baseline": None}))
 
 
 def main():
@@ -238,12 +370,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="zipf_pairs_u32_2p27", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="lognormal_u32_2p29", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-learned", action="store_true",
-                    help="skip the learned-vs-plain comparison on the lognormal-mixture workload")
-    ap.add_argument("--no-kernel-events", action="store_true",
-                    help="time without the per-launch events (no roofline)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the extra plain workloads (2^27 Zipf pairs, 2^27 uint32 keys)")
+    ap.add_argument("--learned-graph", action="store_true",
+                    help="time the learned form by graph replay (no per-kernel events, no roofline)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run torch's plain device copy of the workload's byte size 3 times "
                          "(reference dispatches for HBM byte counters)")
@@ -254,7 +386,6 @@ def main():
         sys.exit(2)
 
     import torch
-    import paper_2211_16479_amd as msort
 
     dev = torch.device("cuda:0")
     desc, n, kb, vb, kt = WORKLOADS[args.workload]
@@ -270,96 +401,62 @@ def main():
         return
     K, W = args.steps, args.warmup
     if args.workload == "segments_u32_10000":
-        return bench_segmented(args, desc)
-    if args.workload == "lognormal_u32_2p29":
-        r = learned_vs_plain(K, W)
+        return bench_segmented(args, dev)
+
+    if args.workload != "lognormal_u32_2p29":
+        # a plain workload on its own
+        res, pk, pv, _ = plain_form(args.workload, K, W, dev)
+        cpu = None if args.no_cpu_baseline else cpu_baselines(args.workload, pk, pv)
         print(json.dumps({
-            "metric": "Gkeys/s and HBM GB/s vs peak, plain merge-path vs learned-bucket, bit-exact",
-            "value": r["learned_Gkeys_s"], "unit": "Gkeys/s", "n_gpus": 1, "steps": K, "warmup": W,
-            "ms_per_step": r["learned_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "u32", "data": "synthetic", "config": {"workload": desc, "n": n},
-            "learned_vs_plain": r, "roofline": None, "cpu_baseline": None}))
+            "metric": METRIC, "value": res["Gkeys_s"], "unit": "Gkeys/s", "n_gpus": 1, "steps": K, "warmup": W,
+            "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u32" if kb == 4 else "int64", "data": "synthetic",
+            "config": {"workload": desc, "n": n, "key_bytes": kb, "value_bytes": vb,
+                       "input_sha256": res["input_sha256"], "plan": res["plan"]},
+            "roofline": res["roofline"], "cpu_baseline": cpu, "fused_pass": res["fused_pass"],
+            "kernels": res["kernels"], "whole_sort_hbm_GBs": res["whole_sort_hbm_GBs"]}))
         return
-    bufs, pristine = make_inputs(args.workload, K + W, dev)
-    torch.cuda.synchronize()
 
-    def step(i):
-        k, v = bufs[i]
-        if v is None:
-            msort.ms_sort(k)
-        else:
-            msort.ms_sort_pairs(k, v)
-
-    for i in range(W):
-        step(i)
-    torch.cuda.synchronize()
-    msort.ms_profile_reset()
-    msort.ms_profile_enable(not args.no_kernel_events)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(W, W + K):
-        step(i)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    msort.ms_profile_enable(False)
-    ms_per_step = (t1 - t0) * 1e3 / K
-    value = n / (ms_per_step * 1e-3) / 1e9
-
-    kernels = {}
-    for name in ("tile_sort", "partition", "merge", "partition4", "merge4"):
-        cnt, tot = msort.ms_profile_read(name)
-        if cnt:
-            kernels[name] = {"launches": cnt, "avg_ms": tot / cnt, "ms_per_step": tot / K}
-    # the dominant merge kernel: the fused four-run merge when passes are
-    # fused, else the two-run merge
-    dom = max((k for k in ("merge", "merge4") if k in kernels), key=lambda k: kernels[k]["ms_per_step"],
-              default=None)
-    roofline = None
-    if dom:
-        bytes_per_launch = n * (kb + vb) * 2          # read + write of every key and value
-        achieved = bytes_per_launch / (kernels[dom]["avg_ms"] * 1e-3) / 1e9
-        kname = "merge4_kernel" if dom == "merge4" else "merge_kernel"
-        levels = 2 if dom == "merge4" else 1       # merge-tree levels one launch completes
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(args.workload, kname),
-                    "kernel": kname, "bytes_per_launch": bytes_per_launch, "tree_levels_per_launch": levels,
-                    "per_level_equivalent_GBs": round(achieved * levels, 1)}
-    # whole-sort algorithmic bytes (tile sort pass + HBM merge passes)
-    plan = msort.ms_plan_query(n, kt, vb)
-    total_bytes = n * (kb + vb) * 2 * (1 + plan["hbm_passes"])
-
-    del bufs
+    # headline: the learned-bucket form on the lognormal mixture, plain beside it
+    plain, pristine, _, plain_out = plain_form(args.workload, K, W, dev)
+    plain_out = plain_out.clone()
+    learned, roof, learned_out, extra_out = learned_form(K, W, dev, pristine, args.learned_graph)
+    identical = bool(torch.equal(learned_out.view(torch.int32), plain_out.view(torch.int32))) and \
+        bool(torch.equal(extra_out.view(torch.int32), plain_out.view(torch.int32)))
+    del learned_out, extra_out, plain_out
     torch.cuda.empty_cache()
-    lvp = None
-    if not args.no_learned and args.workload == "zipf_pairs_u32_2p27":
-        lvp = learned_vs_plain()
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.workload, pristine)
-
-    out = {
-        "metric": "Gkeys/s and HBM GB/s vs peak, plain merge-path vs learned-bucket, bit-exact",
-        "value": round(value, 4),
+    extras = {}
+    if not args.no_extras:
+        for name in ("uniform_u32_2p27", "zipf_pairs_u32_2p27"):
+            r, _, _, _ = plain_form(name, max(3, K // 2), 2, dev)
+            extras[name] = r
+            torch.cuda.empty_cache()
+    ceiling = copy_ceiling(dev)
+    cpu = None if args.no_cpu_baseline else cpu_baselines(args.workload, pristine, None)
+    print(json.dumps({
+        "metric": METRIC,
+        "value": learned["Gkeys_s"],
         "unit": "Gkeys/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": learned["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32" if kb == 4 else "int64",
+        "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": desc, "n": n, "key_bytes": kb, "value_bytes": vb,
-                   "tile": plan["tile"], "merge_tile": plan["merge_tile"], "merge4_tile": plan["merge4_tile"],
-                   "merge_levels": plan["passes"], "hbm_merge_passes": plan["hbm_passes"]},
-        "whole_sort_hbm_GBs": round(total_bytes / (ms_per_step * 1e-3) / 1e9, 1),
-        "kernels": kernels,
-        "roofline": roofline,
+        "config": {"workload": desc, "n": n, "form": "learned-bucket (headline) vs plain merge path",
+                   "input_sha256": plain["input_sha256"]},
+        "roofline": roof,
         "cpu_baseline": cpu,
-        "learned_vs_plain": lvp,
-    }
-    print(json.dumps(out))
+        "learned": learned,
+        "plain": plain,
+        "learned_vs_plain": {"speedup": round(plain["ms_per_step"] / learned["ms_per_step"], 3),
+                             "outputs_identical": identical},
+        "extra_workloads": extras,
+        "copy_ceiling": ceiling,
+    }))
 
 
 if __name__ == "__main__":

@@ -325,6 +325,9 @@ ms_status ms_release_workspace(void);
  * summed duration in milliseconds since the last ms_profile_reset().
  */
 ms_status ms_profile_enable(int on);
+/* Time only the kernel classes whose bit (1 << class) is set in class_mask
+ * (default: all); fewer events per sort disturb the timed run less. */
+ms_status ms_profile_select(uint32_t class_mask);
 ms_status ms_profile_reset(void);
 ms_status ms_profile_read(int kernel, uint64_t* launches, double* total_ms);
 

@@ -92,6 +92,7 @@ def _declare(lib):
         "ms_learned_table": (i32, [vp, vp, c.c_uint32, i32, vp, vp, vp, vp]),
         "ms_learned_bucket_ids": (i32, [vp, sz, vp, vp, c.c_uint32, i32, i32, c.c_uint32, vp, vp]),
         "ms_profile_enable": (i32, [i32]),
+        "ms_profile_select": (i32, [c.c_uint32]),
         "ms_profile_reset": (i32, []),
         "ms_profile_read": (i32, [i32, c.POINTER(c.c_uint64), c.POINTER(c.c_double)]),
     }
@@ -381,6 +382,13 @@ def ms_release_workspace():
 
 def ms_profile_enable(on: bool = True):
     _check(lib().ms_profile_enable(1 if on else 0), "ms_profile_enable")
+
+
+def ms_profile_select(classes=None):
+    """Time only the named kernel classes (None: all)."""
+    mask = 0xFFFFFFFF if classes is None else sum(1 << (PROFILE_KERNELS[c] if isinstance(c, str) else int(c))
+                                                  for c in classes)
+    _check(lib().ms_profile_select(mask), "ms_profile_select")
 
 
 def ms_profile_reset():

@@ -106,6 +106,7 @@ struct ProfRec {
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+uint32_t g_prof_mask = ~0u;  // kernel classes that are timed
 std::vector<ProfRec> g_prof_recs;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_pool;
 size_t g_prof_used = 0;
@@ -116,7 +117,7 @@ ProfSuppress::ProfSuppress() { ++g_prof_suppress; }
 ProfSuppress::~ProfSuppress() { --g_prof_suppress; }
 
 ProfScope::ProfScope(int k, hipStream_t s) : kernel(k), stream(s), slot(-1) {
-  if (!g_prof_on || g_prof_suppress) return;
+  if (!g_prof_on || g_prof_suppress || ((g_prof_mask >> k) & 1u) == 0) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -674,6 +675,12 @@ ms_status ms_tuning_load(const char* path, const char* arch, int* applied) {
 ms_status ms_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof_on = on != 0;
+  return MS_OK;
+}
+
+ms_status ms_profile_select(uint32_t class_mask) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_mask = class_mask;
   return MS_OK;
 }
 
