@@ -66,6 +66,15 @@ int ms_version(void);
  * replay it on any buffers); for tests and diagnostics. */
 uint64_t ms_graph_captures(void);
 
+/*
+ * ms_device_errors -- internal-consistency checks done by the kernels of the
+ * current device since the last call (then cleared): bit 0 (value 1) = a
+ * fused merge tile received partition offsets that do not describe its
+ * pieces and was left unwritten.  Nonzero means a library bug, never a
+ * property of the input.  Synchronises the device.  flags may be NULL.
+ */
+ms_status ms_device_errors(uint32_t* flags);
+
 /* Static text for a status code; never NULL. */
 const char* ms_status_string(ms_status s);
 
@@ -191,7 +200,7 @@ typedef struct ms_options {
   float spill_threshold;     /* fall back when spilled keys > this * n; [0, 0.5], default 0.05 */
   uint32_t bucket_capacity;  /* keys sorted per LDS bucket: 4096 or 16384 (default) */
   uint32_t bucket_fill;      /* target mean keys per bucket, 64..capacity, default 512 */
-  uint32_t train_steps;      /* Adam steps, default 64 */
+  uint32_t train_steps;      /* Adam steps, default 16 */
   float learning_rate;       /* default 1e-4 */
   uint32_t sample_log2;      /* log2 of the sample size, 10..20, default 16 */
   uint64_t seed;             /* sample positions, default 0 */

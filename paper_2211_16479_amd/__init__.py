@@ -75,6 +75,7 @@ def _declare(lib):
         "ms_temp_bytes_segmented": (sz, [sz, sz, i32, sz]),
         "ms_temp_bytes_learned": (sz, [sz, c.POINTER(MsOptions)]),
         "ms_graph_captures": (c.c_uint64, []),
+        "ms_device_errors": (i32, [c.POINTER(c.c_uint32)]),
         "ms_plan_query": (i32, [sz, i32, sz, c.POINTER(i32), c.POINTER(i32), c.POINTER(i32),
                                 c.POINTER(i32), c.POINTER(i32), c.POINTER(i32)]),
         "ms_release_workspace": (i32, []),
@@ -360,6 +361,14 @@ def ms_temp_bytes_learned(n: int, **options) -> int:
             raise TypeError(f"unknown option {k}")
         setattr(o, k, v)
     return int(lib().ms_temp_bytes_learned(n, ctypes.byref(o)))
+
+
+def ms_device_errors() -> int:
+    """Error bits raised by the kernels since the last call (0: none);
+    synchronises the device."""
+    v = ctypes.c_uint32()
+    _check(lib().ms_device_errors(ctypes.byref(v)), "ms_device_errors")
+    return int(v.value)
 
 
 def ms_graph_captures() -> int:

@@ -380,6 +380,18 @@ int ms_version(void) { return 101; }
 
 uint64_t ms_graph_captures(void) { return graph_capture_count(); }
 
+ms_status ms_device_errors(uint32_t* flags) {
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  const uint32_t v = dev_errors_plain() | dev_errors_seg32() | dev_errors_seg64();
+  if (flags) *flags = v & 0x7FFFFFFFu;
+  if (v & 0x80000000u) {
+    set_error("reading the device error words failed");
+    return MS_ERR_HIP;
+  }
+  return MS_OK;
+}
+
 const char* ms_status_string(ms_status s) {
   switch (s) {
     case MS_OK: return "ok";

@@ -227,6 +227,25 @@ __device__ __forceinline__ void load_run(const E* __restrict__ src, E (&v)[N]) {
   }
 }
 
+// Internal-consistency error bits of this code object's kernels (each
+// translation unit has its own word; the host reads and clears them all
+// through ms_device_errors()).  A kernel that detects an inconsistency sets
+// a bit and writes nothing it cannot vouch for.
+constexpr unsigned int DEV_ERR_MERGE_OFFSETS = 1u;  // fused merge tile: offsets do not describe its pieces
+static __device__ unsigned int g_dev_errors;
+__device__ __forceinline__ void raise_dev_error(unsigned int bits) { atomicOr(&g_dev_errors, bits); }
+
+// Host side: read and clear this translation unit's error word (blocking).
+#define MS_DEFINE_DEV_ERRORS(fn)                                                    \
+  unsigned int fn() {                                                              \
+    unsigned int v = 0, z = 0;                                                     \
+    if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_dev_errors), sizeof v) != hipSuccess) \
+      return 0x80000000u;                                                          \
+    if (v && hipMemcpyToSymbol(HIP_SYMBOL(g_dev_errors), &z, sizeof z) != hipSuccess) \
+      return v | 0x80000000u;                                                      \
+    return v;                                                                      \
+  }
+
 // A device pointer read from memory.  Typed as a global-memory pointer, the
 // loads and stores through it stay global instructions; read as a plain
 // void*, it would make the compiler fall back to flat instructions for every

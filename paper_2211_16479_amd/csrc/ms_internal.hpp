@@ -105,6 +105,12 @@ ms_status cached_graph_launch(std::vector<uint64_t> key, size_t ws_bytes, const 
                               const std::function<ms_status(void* ws, void* const* io, hipStream_t cs, SegFork fork)>&
                                   enqueue,
                               hipStream_t s);
+// Read and clear the device error words of the translation units whose
+// kernels can raise them (see g_dev_errors).
+unsigned int dev_errors_plain();
+unsigned int dev_errors_seg32();
+unsigned int dev_errors_seg64();
+
 // Graphs captured so far in this process (all devices).
 uint64_t graph_capture_count();
 // Bytes of a cached graph's scratch taken by its binding block.

@@ -269,7 +269,7 @@ void ms_options_default(ms_options* o) {
   o->spill_threshold = 0.05f;
   o->bucket_capacity = 16384;
   o->bucket_fill = 512;
-  o->train_steps = 64;
+  o->train_steps = 16;
   o->learning_rate = 1e-4f;
   o->sample_log2 = 16;
   o->seed = 0;

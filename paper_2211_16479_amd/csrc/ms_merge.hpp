@@ -758,7 +758,8 @@ __device__ __forceinline__ void merge4_tile(const K* __restrict__ src_k, const V
     for (int r = 0; r < 4; ++r) e[r] = wave_uniform(uint64_t(part4[4 * (k + 1) + r]));
   }
   // offsets that do not describe four in-run pieces filling the tile are
-  // never dereferenced (the tile is skipped); exact partitions always pass
+  // never dereferenced: the tile is left unwritten and the error bit set
+  // (exact partitions always pass)
   const uint64_t rs[4] = {Q.qb, Q.r1, Q.r2, Q.r3}, re[4] = {Q.r1, Q.r2, Q.r3, Q.end};
   bool ok = true;
   uint64_t sum = 0;
@@ -768,6 +769,7 @@ __device__ __forceinline__ void merge4_tile(const K* __restrict__ src_k, const V
     sum += e[r] - s[r];
   }
   ok = ok && sum == g1 - g0;
+  if (!ok && threadIdx.x == 0) raise_dev_error(DEV_ERR_MERGE_OFFSETS);
   uint32_t l[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) l[r] = ok ? uint32_t(e[r] - s[r]) : 0u;

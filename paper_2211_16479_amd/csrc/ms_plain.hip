@@ -205,6 +205,8 @@ ms_status merge_two_runs(const K* src, K* dst, uint64_t n, DevCtl ctl, int64_t* 
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? MS_OK : hip_fail(e, "two-run merge launch");
 }
+MS_DEFINE_DEV_ERRORS(dev_errors_plain)
+
 template ms_status merge_two_runs<uint32_t, NoVal>(const uint32_t*, uint32_t*, uint64_t, DevCtl, int64_t*, hipStream_t,
                                                    uint64_t);
 

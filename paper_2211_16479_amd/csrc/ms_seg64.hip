@@ -8,4 +8,5 @@ MS_SEG_INSTANTIATE(uint64_t, uint64_t)
 MS_SEG_INSTANTIATE(int64_t, NoVal)
 MS_SEG_INSTANTIATE(int64_t, uint32_t)
 MS_SEG_INSTANTIATE(int64_t, uint64_t)
+MS_DEFINE_DEV_ERRORS(dev_errors_seg64)
 }  // namespace ms

@@ -148,17 +148,32 @@ def test_forced_fallback_is_exact(gpu):
 
 
 def test_trained_network_beats_no_network(gpu):
-    """Same keys: the trained MLP spills nothing and stays on the learned
-    path; without the network (bucket = floor(x * B)) the mixture piles into
-    few buckets, spills, and falls back.  Both outputs are exact."""
+    """Four ways to bucket the same mixture keys: the trained network (the
+    default Adam steps), its closed-form quantile start point (no steps),
+    the log feature with no network, and the linear feature with no network
+    (bucket = floor(x * B)).  All four outputs equal the oracle's.  With the
+    network (trained or at its start) nothing spills and the largest bucket
+    is smaller than with either feature alone (the linear one piles the
+    mixture into few buckets, spills and falls back); training lowers the squared
+    rank error of its start point.  (Times of the four at 2^29 are in the
+    design notes; the log feature alone keeps the learned path but runs
+    slower.)"""
     keys = u32_np(workloads.lognormal_mix_u32(1 << 22, seed=11))
     exp = oracle.sort(keys)
-    got_t, st_t = learned_sort(keys, gpu)
-    got_l, st_l = learned_sort(keys, gpu, use_network=0, feature=msort.MS_FEATURE_LINEAR)
-    assert_equal_arrays(got_t, exp, "trained")
-    assert_equal_arrays(got_l, exp, "no network")
-    assert st_t["spilled"] < st_l["spilled"] and st_t["max_bucket"] < st_l["max_bucket"]
-    assert st_t["fallback_taken"] == 0 and st_l["fallback_taken"] == 1
+    rows = {"trained": {}, "start": dict(train_steps=0), "log, no network": dict(use_network=0),
+            "linear, no network": dict(use_network=0, feature=msort.MS_FEATURE_LINEAR)}
+    st = {}
+    for name, opt in rows.items():
+        got, st[name] = learned_sort(keys, gpu, **opt)
+        assert_equal_arrays(got, exp, name)
+        print(name, {k: st[name][k] for k in ("spilled", "max_bucket", "fallback_taken", "loss_initial",
+                                               "loss_final")}, flush=True)
+    for net in ("trained", "start"):
+        assert st[net]["spilled"] == 0 and st[net]["fallback_taken"] == 0
+        assert st[net]["max_bucket"] < st["linear, no network"]["max_bucket"]
+        assert st[net]["max_bucket"] < st["log, no network"]["max_bucket"]
+    assert st["trained"]["loss_final"] < st["trained"]["loss_initial"]
+    assert st["linear, no network"]["spilled"] > 0 and st["linear, no network"]["fallback_taken"] == 1
 
 
 def test_graph_replay_on_new_data(gpu):

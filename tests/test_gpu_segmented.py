@@ -171,3 +171,10 @@ def test_too_small_length_hint_still_sorts(gpu, hint):
             ek, ev = oracle.segmented_sort(k, off, v)
             assert_equal_arrays(gk, ek, f"hint {hint} pair keys")
             assert_equal_arrays(gv, ev, f"hint {hint} pair values")
+
+
+def test_no_internal_errors_raised(gpu):
+    """No kernel of the runs before this one (the whole GPU session when the
+    files run in order) found inconsistent merge offsets."""
+    assert msort.ms_device_errors() == 0
+    assert msort.ms_device_errors() == 0
