@@ -188,7 +188,7 @@ ms_status ms_tuning_load(const char* path, const char* arch, int* applied);
  * (decided on the device).  The output is the same bytes as ms_sort's.
  * ------------------------------------------------------------------------ */
 typedef enum ms_algo {
-  MS_ALGO_AUTO = 0,            /* learned for uint32 and n >= 2^22, else merge path */
+  MS_ALGO_AUTO = 0,            /* learned for uint32 and n >= 2^27, else merge path */
   MS_ALGO_MERGE_PATH = 1,
   MS_ALGO_LEARNED_BUCKET = 2
 } ms_algo;
@@ -208,6 +208,9 @@ typedef struct ms_options {
   int use_network;           /* 1 (default); 0: bucket = floor(x * B) with no network */
   int force_fallback;        /* 1: always take the plain merge sort (testing) */
   int use_graph;             /* 1 (default): replay a cached hipGraph of the pipeline */
+  uint32_t max_workgroups;   /* merge path only, measurement support: at most this many workgroups per
+                                launch, each looping over tiles (the worker count of a scaling study);
+                                0 (default) = one workgroup per tile */
 } ms_options;
 
 /* Written on the device when the sort completes (valid after the stream). */

@@ -41,7 +41,8 @@ class MsOptions(ctypes.Structure):
                 ("bucket_capacity", ctypes.c_uint32), ("bucket_fill", ctypes.c_uint32),
                 ("train_steps", ctypes.c_uint32), ("learning_rate", ctypes.c_float),
                 ("sample_log2", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("feature", ctypes.c_int),
-                ("use_network", ctypes.c_int), ("force_fallback", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("use_network", ctypes.c_int), ("force_fallback", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("max_workgroups", ctypes.c_uint32)]
 
 
 class MsStats(ctypes.Structure):

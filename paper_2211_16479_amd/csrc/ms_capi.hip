@@ -201,6 +201,17 @@ static ms_status sort_impl(void* d_keys, void* d_vals, size_t n, ms_key_type kt,
   });
 }
 
+ms_status plain_sort_capped(void* d_keys, size_t n, ms_key_type kt, uint64_t max_grid, hipStream_t s) {
+  return with_key_type(kt, [&](auto kz) -> ms_status {
+    using K = decltype(kz);
+    void* ws = nullptr;
+    ms_status st = get_workspace(s, plain_temp_bytes<K, NoVal>(n), &ws);
+    if (st != MS_OK) return st;
+    return plain_sort<K, NoVal>(static_cast<K*>(d_keys), nullptr, n, DevCtl{nullptr, nullptr, nullptr}, s, ws,
+                                max_grid);
+  });
+}
+
 template <class F>
 static ms_status with_types(ms_key_type kt, size_t vb, F&& f) {
   return with_key_type(kt, [&](auto kz) -> ms_status {

@@ -63,6 +63,9 @@ template <class K, class V>
 ms_status plain_sort(K* keys, V* vals, uint64_t n, DevCtl ctl, hipStream_t s, void* ws, uint64_t max_grid = 0);
 template <class K, class V>
 size_t plain_temp_bytes(uint64_t n);
+// Keys-only plain sort with every launch's grid capped at max_grid (0: none),
+// scratch from the per-stream workspace.
+ms_status plain_sort_capped(void* d_keys, size_t n, ms_key_type kt, uint64_t max_grid, hipStream_t s);
 template <class K, class V>
 void plain_geometry(int* tile, int* merge_tile, int* merge4_tile, int* fused);
 // One merge of src[0, split) with src[split, n) into dst (split on the device),

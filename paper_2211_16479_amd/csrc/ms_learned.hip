@@ -301,10 +301,11 @@ ms_status ms_sort_ex(void* d_keys, size_t n, ms_key_type kt, const ms_options* o
     set_error("the learned-bucket form needs uint32 keys, n >= 4 * sample size and n < 2^32");
     return MS_ERR_UNSUPPORTED;
   }
-  const bool learned = learned_ok && o.algo != MS_ALGO_MERGE_PATH && (o.algo == MS_ALGO_LEARNED_BUCKET || n >= (1u << 22));
+  const bool learned = learned_ok && o.algo != MS_ALGO_MERGE_PATH && (o.algo == MS_ALGO_LEARNED_BUCKET || n >= (1u << 27));
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (!learned) {
-    ms_status st = ms_sort(d_keys, n, kt, stream);
+    ms_status st = o.max_workgroups ? plain_sort_capped(d_keys, n, kt, o.max_workgroups, s)
+                                    : ms_sort(d_keys, n, kt, stream);
     if (st != MS_OK || !d_stats) return st;
     ls_plain_stats_kernel<<<1, 64, 0, s>>>(d_stats);
     hipError_t e = hipGetLastError();

@@ -246,3 +246,18 @@ def test_fused_pass_run_counts(gpu, kdt, vdt):
                 assert_equal_arrays(gk, ek, f"keys m={m} n={n}")
                 assert_equal_arrays(gv, ev, f"values m={m} n={n}")
 
+
+
+def test_workgroup_cap_same_result(gpu):
+    """The scaling study's worker count: every launch capped at 1, 3, 64
+    workgroups (each looping over tiles) gives the oracle's sort, for u32
+    and int64 keys with a ragged last tile."""
+    rng = np.random.default_rng(51)
+    for dtype in (np.uint32, np.int64):
+        k = keys_fill(300_007, dtype, "uniform", rng)
+        exp = oracle.sort(k)
+        for cap in (1, 3, 64):
+            t = to_dev(k, gpu)
+            msort.ms_sort_ex(t, algo=msort.MS_ALGO_MERGE_PATH, stats=False, max_workgroups=cap)
+            torch.cuda.synchronize()
+            assert_equal_arrays(t.cpu().numpy(), exp, f"{np.dtype(dtype).name} cap {cap}")
