@@ -268,6 +268,7 @@ def ms_sort_ex(keys: torch.Tensor, key_type=None, stats: bool = True, **options)
     fields (algo, spill_threshold, bucket_capacity, ...).  Returns
     (keys, stats dict or None); stats are read after a stream sync."""
     _dev(keys, "keys")
+    _ensure_tuning()  # the learned form sorts its buckets with the per-class shapes
     o = ms_options_default()
     for k, v in options.items():
         if not hasattr(o, k):

@@ -59,8 +59,9 @@ __global__ __launch_bounds__(256) void ls_bucket_ids_kernel(const uint32_t* __re
   __shared__ LsTable tb;
   ls_load_table(md, &tb);
   __syncthreads();
+  const LsUni U = ls_uni(&tb);
   const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = ls_bucket(&tb, keys[i]);
+  if (i < n) out[i] = ls_bucket(&tb, U, keys[i]);
 }
 
 __global__ void ls_plain_stats_kernel(ms_stats* st) {
@@ -93,7 +94,7 @@ struct LsPlan {
   uint64_t chunk_cap;  // bound on level-2 chunks
   // scratch offsets
   size_t md, sample, sample_tmp, partial, loss, bins, coarse, xr, part, seg, bytes;
-  size_t bins_c_off[12], bins_f_off[5];
+  size_t bins_c_off[9], bins_f_off[3];
 };
 
 static LsPlan ls_plan(uint64_t n, const ms_options& o) {
@@ -116,9 +117,9 @@ static LsPlan ls_plan(uint64_t n, const ms_options& o) {
   P.sample_tmp = take(plain_temp_bytes<uint32_t, NoVal>(P.S));
   P.partial = take(sizeof(float) * 2 * LS_TRAIN_G * LS_PS);
   P.loss = take(sizeof(float) * (o.train_steps + 1));
-  for (int i = 0; i < 12; ++i) P.bins_c_off[i] = take(sizeof(uint32_t) * (P.nbc + 1));
-  for (int i = 0; i < 4; ++i) P.bins_f_off[i] = take(sizeof(uint32_t) * P.B);
-  P.bins_f_off[4] = take(sizeof(int64_t) * (P.B + 1));
+  for (int i = 0; i < 9; ++i) P.bins_c_off[i] = take(sizeof(uint32_t) * (P.nbc + 1));
+  for (int i = 0; i < 2; ++i) P.bins_f_off[i] = take(sizeof(uint32_t) * P.B);
+  P.bins_f_off[2] = take(sizeof(int64_t) * (P.B + 1));
   P.coarse = take(std::max<size_t>(sizeof(uint32_t) * n, plain_temp_bytes<uint32_t, NoVal>(n)));
   P.xr = take(sizeof(uint32_t) * n);
   P.part = take(sizeof(int64_t) * (ceil_div(n, PlainCfg<uint32_t, NoVal>::MTILE) + 2));  // merge_two_runs
@@ -129,14 +130,12 @@ static LsPlan ls_plan(uint64_t n, const ms_options& o) {
 
 static LsBins ls_bins(char* w, const LsPlan& P) {
   LsBins b;
-  uint32_t** c[12] = {&b.cnt_c, &b.off_c, &b.cursor_c, &b.chunk_start, &b.kept_tot, &b.spill_tot,
-                      &b.cmin, &b.cmax, &b.cbad, &b.cmaxb, &b.kept_base, &b.spill_base};
-  for (int i = 0; i < 12; ++i) *c[i] = reinterpret_cast<uint32_t*>(w + P.bins_c_off[i]);
+  uint32_t** c[9] = {&b.cnt_c, &b.off_c, &b.cursor_c, &b.chunk_start, &b.kept_tot, &b.spill_tot,
+                     &b.cmaxb, &b.kept_base, &b.spill_base};
+  for (int i = 0; i < 9; ++i) *c[i] = reinterpret_cast<uint32_t*>(w + P.bins_c_off[i]);
   b.cnt_f = reinterpret_cast<uint32_t*>(w + P.bins_f_off[0]);
-  b.fmin = reinterpret_cast<uint32_t*>(w + P.bins_f_off[1]);
-  b.fmax = reinterpret_cast<uint32_t*>(w + P.bins_f_off[2]);
-  b.cursor_f = reinterpret_cast<uint32_t*>(w + P.bins_f_off[3]);
-  b.seg_off = reinterpret_cast<int64_t*>(w + P.bins_f_off[4]);
+  b.cursor_f = reinterpret_cast<uint32_t*>(w + P.bins_f_off[1]);
+  b.seg_off = reinterpret_cast<int64_t*>(w + P.bins_f_off[2]);
   return b;
 }
 
@@ -215,6 +214,7 @@ static ms_status learned_enqueue(uint32_t* keys, uint64_t n, const ms_options& o
                                       reinterpret_cast<void* const*>(&md->r_keys));
   }
   if (st != MS_OK) return st;
+  ls_check_kernel<<<dim3(unsigned(ceil_div(P.B, 256))), 256, 0, s>>>(md, bn, P.B);
   // repair: spill sorted by the plain merge sort, then merged with the kept keys
   // (gated stages run with a bounded grid: when skipped they cost little)
   const uint64_t gated_grid = uint64_t(device_cu_count()) * 4;

@@ -22,15 +22,16 @@
 //   level 2 : fine histogram inside each coarse bucket, then per fine bucket
 //             either "kept" (at most `capacity` keys: placed contiguously
 //             for the LDS bucket sort) or "spilled" (to the spill array);
-//   check   : every kept bucket's minimum must be >= the maximum of all
-//             earlier kept buckets (the judge; it cannot fail for a
-//             non-decreasing bucket function, and forces the plain sort if
-//             it does);
-//   decide  : spilled > tau * n (or a failed check) -> the plain merge sort
-//             runs instead (device flag; every learned kernel then returns);
+//   decide  : spilled > tau * n -> the plain merge sort runs instead
+//             (device flag; every learned kernel then returns);
 //   sort    : kept buckets are sorted in LDS by the segmented small-class
-//             kernels; the spill is sorted by the plain merge sort; one
-//             merge-path pass merges the two (exact repair).
+//             kernels;
+//   check   : the sorted kept buckets must meet in order (the last key of
+//             each <= the first key of the next: the judge; it cannot fail
+//             for a non-decreasing bucket function, and if it does the plain
+//             merge sort sorts the keys, a permutation of the input, again);
+//   repair  : the spill is sorted by the plain merge sort and one
+//             merge-path pass merges it with the kept keys (exact).
 #pragma once
 #include "ms_common.hpp"
 
@@ -331,24 +332,54 @@ __device__ __forceinline__ void ls_load_table(const LsModel* md, LsTable* tb) {
   }
 }
 
-// Bucket id of a key: non-decreasing in the key.
-__device__ __forceinline__ uint32_t ls_bucket(const LsTable* tb, uint32_t key) {
-  const float x = ls_feature(key, tb->log_feature);
+// The table's scalar fields, read once per kernel into scalar registers
+// (every lane holds the same values), so that branches on them are uniform.
+struct LsUni {
+  int n, use_table, log_feature, fine_bits;
+  float t0, tlast, B;
+  uint32_t nb;
+};
+
+__device__ __forceinline__ float uniform_f(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+// After ls_load_table and a barrier.
+__device__ __forceinline__ LsUni ls_uni(const LsTable* tb) {
+  LsUni u;
+  u.n = __builtin_amdgcn_readfirstlane(tb->n);
+  u.use_table = __builtin_amdgcn_readfirstlane(tb->use_table);
+  u.log_feature = __builtin_amdgcn_readfirstlane(tb->log_feature);
+  u.fine_bits = __builtin_amdgcn_readfirstlane(tb->fine_bits);
+  u.t0 = uniform_f(tb->t[0]);
+  u.tlast = uniform_f(tb->t[u.n > 0 ? u.n - 1 : 0]);
+  u.B = uniform_f(tb->B);
+  u.nb = uint32_t(__builtin_amdgcn_readfirstlane(int(tb->nb)));
+  return u;
+}
+
+// Bucket id of a key: non-decreasing in the key.  Branch-free per lane: the
+// table search takes a fixed number of select steps.
+__device__ __forceinline__ uint32_t ls_bucket(const LsTable* tb, const LsUni& U, uint32_t key) {
+  const float x = ls_feature(key, U.log_feature);
   float u;
-  if (tb->use_table) {
-    const float xc = fminf(fmaxf(x, tb->t[0]), tb->t[tb->n - 1]);  // clamp to the table's range
+  if (U.use_table) {
+    // clamp to the table's range (t0 <= tlast; med3 of three ordinary
+    // floats is the middle one)
+    const float xc = __builtin_amdgcn_fmed3f(x, U.t0, U.tlast);
     int j = 0;  // largest j with t[j] <= xc, then at most n-2
 #pragma unroll
-    for (int step = LS_TAB / 2; step >= 1; step >>= 1)
-      if (tb->t[j + step] <= xc) j += step;
-    j = j < tb->n - 2 ? j : tb->n - 2;
-    u = fminf(__fmaf_rn(tb->s[j], __fsub_rn(xc, tb->t[j]), tb->v[j]), tb->v[j + 1]);
+    for (int step = LS_TAB / 2; step >= 1; step >>= 1) j = tb->t[j + step] <= xc ? j + step : j;
+    j = j < U.n - 2 ? j : U.n - 2;
+    // min(value, v[j+1]) then max(., 0): the middle of the three, since the
+    // table values are positive
+    u = __builtin_amdgcn_fmed3f(__fmaf_rn(tb->s[j], __fsub_rn(xc, tb->t[j]), tb->v[j]), 0.f, tb->v[j + 1]);
   } else {
-    u = x;
+    u = fmaxf(x, 0.f);
   }
-  const float f = __fmul_rn(fmaxf(u, 0.f), tb->B);
-  const uint32_t b = f >= tb->B ? tb->nb - 1 : uint32_t(f);
-  return b < tb->nb ? b : tb->nb - 1;
+  const float f = __fmul_rn(u, U.B);
+  const uint32_t b = f >= U.B ? U.nb - 1 : uint32_t(f);
+  return b < U.nb ? b : U.nb - 1;
 }
 
 // ------------------------------------------------------------ scatter
@@ -359,15 +390,10 @@ struct LsBins {
   uint32_t* cursor_c;     // [Bc] coarse scatter cursors
   uint32_t* chunk_start;  // [Bc + 1] first level-2 chunk of each coarse bucket
   uint32_t* cnt_f;        // [B] keys per fine bucket
-  uint32_t* fmin;         // [B] smallest key per fine bucket
-  uint32_t* fmax;         // [B] largest key per fine bucket
   uint32_t* cursor_f;     // [B] fine scatter cursors
   int64_t* seg_off;       // [B + 1] kept-bucket segments for the bucket sort
   uint32_t* kept_tot;     // [Bc] per coarse bucket: kept keys
   uint32_t* spill_tot;    // [Bc] spilled keys
-  uint32_t* cmin;         // [Bc] smallest kept key
-  uint32_t* cmax;         // [Bc] largest kept key
-  uint32_t* cbad;         // [Bc] 1 if kept buckets are out of order inside
   uint32_t* cmaxb;        // [Bc] largest fine bucket
   uint32_t* kept_base;    // [Bc] first kept position of the coarse bucket
   uint32_t* spill_base;   // [Bc] first spill position of the coarse bucket
@@ -413,11 +439,7 @@ __device__ __forceinline__ void ls_block_scan(const uint32_t* cnt, uint32_t* off
 
 __global__ __launch_bounds__(256) void ls_clear_kernel(LsBins bn, uint32_t nb_c, uint32_t nb) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nb) {
-    bn.cnt_f[i] = 0;
-    bn.fmin[i] = 0xFFFFFFFFu;
-    bn.fmax[i] = 0;
-  }
+  if (i < nb) bn.cnt_f[i] = 0;
   if (i < nb_c) bn.cnt_c[i] = 0;
 }
 
@@ -433,20 +455,28 @@ __global__ __launch_bounds__(LS_WG) void ls_hist1_kernel(const uint32_t* __restr
   const uint32_t nbc = md->nbins_c;
   for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) h[i] = 0;
   __syncthreads();
+  const LsUni U = ls_uni(&tb);
   for (int c = 0; c < LS_H1; ++c) {
     const uint64_t base = (uint64_t(blockIdx.x) * LS_H1 + c) * LS_CHK;
     if (base >= n) break;  // workgroup-uniform
-    uint32_t kv[LS_CHK / LS_WG];
+    const uint32_t lim = n - base < uint64_t(LS_CHK) ? uint32_t(n - base) : uint32_t(LS_CHK);
+    const uint32_t* kb = keys + base;
+    // full chunks (all but the last) run without per-element bounds checks
+    auto body = [&](auto fullc) {
+      constexpr bool FULL = decltype(fullc)::value;
+      uint32_t kv[LS_CHK / LS_WG];
 #pragma unroll
-    for (int r = 0; r < LS_CHK / LS_WG; ++r) {
-      const uint64_t e = base + threadIdx.x + uint64_t(r) * LS_WG;
-      kv[r] = e < n ? keys[e] : 0u;
-    }
+      for (int r = 0; r < LS_CHK / LS_WG; ++r) {
+        const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
+        kv[r] = (FULL || i < lim) ? kb[i] : 0u;
+      }
 #pragma unroll
-    for (int r = 0; r < LS_CHK / LS_WG; ++r) {
-      const uint64_t e = base + threadIdx.x + uint64_t(r) * LS_WG;
-      if (e < n) atomicAdd(&h[ls_bucket(&tb, kv[r]) >> tb.fine_bits], 1u);
-    }
+      for (int r = 0; r < LS_CHK / LS_WG; ++r) {
+        const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
+        if (FULL || i < lim) atomicAdd(&h[ls_bucket(&tb, U, kv[r]) >> U.fine_bits], 1u);
+      }
+    };
+    if (lim == uint32_t(LS_CHK)) body(std::true_type{}); else body(std::false_type{});
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG)
@@ -503,39 +533,52 @@ __global__ __launch_bounds__(LS_WG) void ls_scatter1_kernel(const uint32_t* __re
   const uint32_t nbc = md->nbins_c;
   for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) L.cnt[i] = 0;
   __syncthreads();
+  const LsUni U = ls_uni(&tb);
   constexpr int R = LS_CHK / LS_WG;
   const uint64_t base = uint64_t(blockIdx.x) * LS_CHK;
+  const uint32_t lim = n - base < uint64_t(LS_CHK) ? uint32_t(n - base) : uint32_t(LS_CHK);
+  const uint32_t* kb = keys + base;
   uint32_t kv[R], bin[R], rk[R];
+  // full chunks (all but the last) run without per-element bounds checks
+  auto rank = [&](auto fullc) {
+    constexpr bool FULL = decltype(fullc)::value;
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint64_t e = base + threadIdx.x + uint64_t(r) * LS_WG;
-    kv[r] = e < n ? keys[e] : 0u;
-  }
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint64_t e = base + threadIdx.x + uint64_t(r) * LS_WG;
-    if (e < n) {
-      bin[r] = ls_bucket(&tb, kv[r]) >> tb.fine_bits;
-      rk[r] = atomicAdd(&L.cnt[bin[r]], 1u);
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
+      kv[r] = (FULL || i < lim) ? kb[i] : 0u;
     }
-  }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
+      if (FULL || i < lim) {
+        bin[r] = ls_bucket(&tb, U, kv[r]) >> U.fine_bits;
+        rk[r] = atomicAdd(&L.cnt[bin[r]], 1u);
+      }
+    }
+  };
+  auto stage = [&](auto fullc) {
+    constexpr bool FULL = decltype(fullc)::value;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
+      if (FULL || i < lim) {
+        const uint32_t p = L.off[bin[r]] + rk[r];
+        L.stage[p] = kv[r];
+        if constexpr (LS_SBIN) L.sbin[p] = uint16_t(bin[r]);
+      }
+    }
+  };
+  const bool full = lim == uint32_t(LS_CHK);
+  if (full) rank(std::true_type{}); else rank(std::false_type{});
   __syncthreads();
   ls_block_scan(L.cnt, L.off, nbc, L.tmp, &L.total);
   for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG)
     if (L.cnt[i]) L.gb[i] = atomicAdd(&bn.cursor_c[i], L.cnt[i]);
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint64_t e = base + threadIdx.x + uint64_t(r) * LS_WG;
-    if (e < n) {
-      const uint32_t p = L.off[bin[r]] + rk[r];
-      L.stage[p] = kv[r];
-      if constexpr (LS_SBIN) L.sbin[p] = uint16_t(bin[r]);
-    }
-  }
+  if (full) stage(std::true_type{}); else stage(std::false_type{});
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < L.total; i += LS_WG) {
     const uint32_t x = L.stage[i];
-    const uint32_t b = LS_SBIN ? uint32_t(L.sbin[i]) : ls_bucket(&tb, x) >> tb.fine_bits;
+    const uint32_t b = LS_SBIN ? uint32_t(L.sbin[i]) : ls_bucket(&tb, U, x) >> U.fine_bits;
     out[L.gb[b] + (i - L.off[b])] = x;
   }
 }
@@ -557,114 +600,66 @@ __device__ __forceinline__ bool ls_chunk(const LsModel* md, const LsBins& bn, ui
   return true;
 }
 
-// Level 2 histogram with per-fine-bucket min / max (for the order check).
+// Level 2 histogram: fine-bucket counts of one chunk of a coarse bucket.
 __global__ __launch_bounds__(LS_WG) void ls_hist2_kernel(const uint32_t* __restrict__ keys, const LsModel* md,
                                                          LsBins bn) {
   __shared__ LsTable tb;
-  __shared__ uint32_t h[LS_MAX_BINS], mn[LS_MAX_BINS], mx[LS_MAX_BINS];
+  __shared__ uint32_t h[LS_MAX_BINS];
   uint32_t c, lo, hi;
   if (!ls_chunk(md, bn, blockIdx.x, &c, &lo, &hi)) return;
   ls_load_table(md, &tb);
   const uint32_t nbf = md->nbins_f;
-  for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG) {
-    h[i] = 0;
-    mn[i] = 0xFFFFFFFFu;
-    mx[i] = 0;
-  }
+  for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG) h[i] = 0;
   __syncthreads();
+  const LsUni U = ls_uni(&tb);
   constexpr int R = LS_CHK / LS_WG;
-  uint32_t kv[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t e = lo + threadIdx.x + uint32_t(r) * LS_WG;
-    kv[r] = e < hi ? keys[e] : 0u;
-  }
+  const uint32_t lim = hi - lo;
+  const uint32_t* kb = keys + lo;
   const uint32_t fmask = nbf - 1;
+  // full chunks run without per-element bounds checks
+  auto body = [&](auto fullc) {
+    constexpr bool FULL = decltype(fullc)::value;
+    uint32_t kv[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t e = lo + threadIdx.x + uint32_t(r) * LS_WG;
-    if (e < hi) {
-      const uint32_t f = ls_bucket(&tb, kv[r]) & fmask;
-      atomicAdd(&h[f], 1u);
-      atomicMin(&mn[f], kv[r]);
-      atomicMax(&mx[f], kv[r]);
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
+      kv[r] = (FULL || i < lim) ? kb[i] : 0u;
     }
-  }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
+      if (FULL || i < lim) atomicAdd(&h[ls_bucket(&tb, U, kv[r]) & fmask], 1u);
+    }
+  };
+  if (lim == uint32_t(LS_CHK)) body(std::true_type{}); else body(std::false_type{});
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG)
-    if (h[i]) {
-      const uint32_t b = (c << tb.fine_bits) | i;
-      atomicAdd(&bn.cnt_f[b], h[i]);
-      atomicMin(&bn.fmin[b], mn[i]);
-      atomicMax(&bn.fmax[b], mx[i]);
-    }
+    if (h[i]) atomicAdd(&bn.cnt_f[(c << U.fine_bits) | i], h[i]);
 }
 
-// Inclusive prefix maximum of x[0, nb) in place (nb <= 2 * LS_WG), whole
-// workgroup, Hillis-Steele over LDS; ends with a barrier.
-__device__ __forceinline__ void ls_block_prefix_max(uint32_t* x, uint32_t nb) {
-  for (uint32_t d = 1; d < nb; d <<= 1) {
-    uint32_t v[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const uint32_t i = threadIdx.x + uint32_t(h) * LS_WG;
-      v[h] = (i < nb && i >= d) ? x[i - d] : 0u;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const uint32_t i = threadIdx.x + uint32_t(h) * LS_WG;
-      if (i < nb && i >= d) x[i] = x[i] > v[h] ? x[i] : v[h];
-    }
-    __syncthreads();
-  }
-}
-
-// Per coarse bucket (one workgroup each): kept / spilled totals, largest
-// bucket, and the order of its kept buckets: every kept bucket's minimum
-// must not be below the maximum of the kept buckets before it.
+// Per coarse bucket (one workgroup each): kept / spilled totals and the
+// largest bucket.
 __global__ __launch_bounds__(LS_WG) void ls_totals_kernel(const LsModel* md, LsBins bn, uint32_t capacity) {
-  __shared__ uint32_t cnt[LS_MAX_BINS], mn[LS_MAX_BINS], mx[LS_MAX_BINS];
-  __shared__ uint32_t kept, spill, maxb, bad, kmin, kmax;
+  __shared__ uint32_t kept, spill, maxb;
   const uint32_t c = blockIdx.x;
   const uint32_t nbf = md->nbins_f;
   const uint32_t b0 = c << md->fine_bits;
-  if (threadIdx.x == 0) {
-    kept = spill = maxb = bad = kmax = 0;
-    kmin = 0xFFFFFFFFu;
-  }
+  if (threadIdx.x == 0) kept = spill = maxb = 0;
+  __syncthreads();
+  uint32_t k_acc = 0, s_acc = 0, m_acc = 0;
   for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG) {
     const uint32_t k = bn.cnt_f[b0 + i];
-    const bool kp = k != 0 && k <= capacity;
-    cnt[i] = k;
-    mn[i] = kp ? bn.fmin[b0 + i] : 0xFFFFFFFFu;
-    mx[i] = kp ? bn.fmax[b0 + i] : 0u;  // 0 is neutral for the running maximum
+    if (k > capacity) s_acc += k; else k_acc += k;
+    m_acc = k > m_acc ? k : m_acc;
   }
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG) {
-    const uint32_t k = cnt[i];
-    if (k > capacity) atomicAdd(&spill, k);
-    else if (k) {
-      atomicAdd(&kept, k);
-      atomicMin(&kmin, mn[i]);
-      atomicMax(&kmax, mx[i]);
-    }
-    atomicMax(&maxb, k);
-  }
-  ls_block_prefix_max(mx, nbf);
-  for (uint32_t i = threadIdx.x + 1; i < nbf; i += LS_WG)
-    if (mn[i] != 0xFFFFFFFFu && mn[i] < mx[i - 1]) bad = 1;
-  // kept buckets with every key equal to 0xFFFFFFFF carry that as their
-  // minimum too; they can only follow buckets whose maximum is <= it
+  if (k_acc) atomicAdd(&kept, k_acc);
+  if (s_acc) atomicAdd(&spill, s_acc);
+  if (m_acc) atomicMax(&maxb, m_acc);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const bool any = kept != 0;
     bn.kept_tot[c] = kept;
     bn.spill_tot[c] = spill;
     bn.cmaxb[c] = maxb;
-    bn.cbad[c] = bad;
-    bn.cmin[c] = any ? kmin : 0xFFFFFFFFu;
-    bn.cmax[c] = any ? kmax : 0u;
   }
 }
 
@@ -688,29 +683,15 @@ __global__ __launch_bounds__(LS_WG) void ls_plan2_kernel(LsModel* md, LsBins bn,
     bn.kept_base[i] = kb[i];
     bn.spill_base[i] = sb[i];
   }
-  // the walk below reads LDS copies (loaded in parallel), not global memory
-  __shared__ uint32_t cb[LS_MAX_BINS], cm[LS_MAX_BINS], cn[LS_MAX_BINS], cx[LS_MAX_BINS];
-  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) {
-    cb[i] = bn.cbad[i];
-    cm[i] = bn.cmaxb[i];
-    cn[i] = bn.cmin[i];
-    cx[i] = bn.cmax[i];
-  }
+  __shared__ uint32_t cm[LS_MAX_BINS];
+  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) cm[i] = bn.cmaxb[i];
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t bad = 0, run = 0, maxb = 0;
-    bool any = false;
-    for (uint32_t c = 0; c < nbc; ++c) {
-      bad |= cb[c];
-      maxb = cm[c] > maxb ? cm[c] : maxb;
-      if (k[c] == 0) continue;
-      if (any && cn[c] < run) bad = 1;
-      run = any ? (cx[c] > run ? cx[c] : run) : cx[c];
-      any = true;
-    }
+    uint32_t maxb = 0;
+    for (uint32_t c = 0; c < nbc; ++c) maxb = cm[c] > maxb ? cm[c] : maxb;
     const uint64_t s = stot;
-    const int fb = (force_fallback || bad || s > spill_limit || uint64_t(ktot) + s != n) ? 1 : 0;
-    md->misordered = bad ? 1 : 0;
+    const int fb = (force_fallback || s > spill_limit || uint64_t(ktot) + s != n) ? 1 : 0;
+    md->misordered = 0;
     md->fallback = fb;
     md->do_learned = fb ? 0 : 1;
     md->do_repair = (!fb && s > 0) ? 1 : 0;
@@ -765,22 +746,43 @@ __global__ __launch_bounds__(LS_WG) void ls_scatter2_kernel(const uint32_t* __re
   const uint32_t b0 = c << md->fine_bits;
   for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG) L.cnt[i] = 0;
   __syncthreads();
+  const LsUni U = ls_uni(&tb);
   constexpr int R = LS_CHK / LS_WG;
   const uint32_t fmask = nbf - 1;
+  const uint32_t lim = hi - lo;
+  const uint32_t* kb = keys + lo;
   uint32_t kv[R], bin[R], rk[R];
+  // full chunks run without per-element bounds checks
+  auto rank = [&](auto fullc) {
+    constexpr bool FULL = decltype(fullc)::value;
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t e = lo + threadIdx.x + uint32_t(r) * LS_WG;
-    kv[r] = e < hi ? keys[e] : 0u;
-  }
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t e = lo + threadIdx.x + uint32_t(r) * LS_WG;
-    if (e < hi) {
-      bin[r] = ls_bucket(&tb, kv[r]) & fmask;
-      rk[r] = atomicAdd(&L.cnt[bin[r]], 1u);
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
+      kv[r] = (FULL || i < lim) ? kb[i] : 0u;
     }
-  }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
+      if (FULL || i < lim) {
+        bin[r] = ls_bucket(&tb, U, kv[r]) & fmask;
+        rk[r] = atomicAdd(&L.cnt[bin[r]], 1u);
+      }
+    }
+  };
+  auto stage = [&](auto fullc) {
+    constexpr bool FULL = decltype(fullc)::value;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
+      if (FULL || i < lim) {
+        const uint32_t p = L.off[bin[r]] + rk[r];
+        L.stage[p] = kv[r];
+        if constexpr (LS_SBIN) L.sbin[p] = uint16_t(bin[r]);
+      }
+    }
+  };
+  const bool full = lim == uint32_t(LS_CHK);
+  if (full) rank(std::true_type{}); else rank(std::false_type{});
   __syncthreads();
   ls_block_scan(L.cnt, L.off, nbf, L.tmp, &L.total);
   for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG)
@@ -788,22 +790,32 @@ __global__ __launch_bounds__(LS_WG) void ls_scatter2_kernel(const uint32_t* __re
       L.gb[i] = atomicAdd(&bn.cursor_f[b0 + i], L.cnt[i]);
       kept[i] = bn.cnt_f[b0 + i] <= capacity ? 1 : 0;
     }
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t e = lo + threadIdx.x + uint32_t(r) * LS_WG;
-    if (e < hi) {
-      const uint32_t p = L.off[bin[r]] + rk[r];
-      L.stage[p] = kv[r];
-      if constexpr (LS_SBIN) L.sbin[p] = uint16_t(bin[r]);
-    }
-  }
+  if (full) stage(std::true_type{}); else stage(std::false_type{});
   __syncthreads();
   uint32_t* rk_arr = global_ptr<uint32_t>(&md->r_keys);
   for (uint32_t i = threadIdx.x; i < L.total; i += LS_WG) {
     const uint32_t x = L.stage[i];
-    const uint32_t b = LS_SBIN ? uint32_t(L.sbin[i]) : (ls_bucket(&tb, x) & fmask);
+    const uint32_t b = LS_SBIN ? uint32_t(L.sbin[i]) : (ls_bucket(&tb, U, x) & fmask);
     uint32_t* dst = kept[b] ? rk_arr : xr;
     dst[L.gb[b] + (i - L.off[b])] = x;
+  }
+}
+
+// The judge: after the bucket sort, the kept buckets (each sorted, laid out
+// in bucket order from r_base) must meet in order.  One thread per bucket
+// compares the key before the bucket's first position with its first key;
+// a failure sends the keys (a permutation of the input) to the plain merge
+// sort.
+__global__ __launch_bounds__(256) void ls_check_kernel(LsModel* md, LsBins bn, uint64_t nb) {
+  if (md->do_learned == 0) return;
+  const uint64_t b = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const int64_t lo = bn.seg_off[b], hi = bn.seg_off[b + 1];
+  if (hi <= lo || uint64_t(lo) <= md->r_base) return;
+  const uint32_t* rk = global_ptr<const uint32_t>(&md->r_keys);
+  if (rk[lo] < rk[lo - 1]) {
+    md->misordered = 1;
+    md->fallback = 1;
   }
 }
 

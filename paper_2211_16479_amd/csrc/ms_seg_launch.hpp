@@ -44,24 +44,28 @@ template <class K, class V>
 struct SegCands {
   static constexpr bool FULL = sizeof(K) == 4 && (!HasVal<V>::value || sizeof(typename std::conditional<
                                                                            HasVal<V>::value, V, int>::type) == 4);
-  static int count(uint32_t bound) {
-    if (!FULL) return 1;
+  static constexpr int MAXC = 3;
+  // {wg, ipt} per class bound, default first
+  static int table(uint32_t bound, int (*t)[2]) {
     switch (bound) {
-      case 256: return 2;
-      case 1024: return 3;
-      case 2048: return 2;
-      case 4096: return 3;
-      case 16384: return 2;
+      case 256: t[0][0] = 64; t[0][1] = 4; t[1][0] = 128; t[1][1] = 2; return 2;
+      case 512: t[0][0] = 64; t[0][1] = 8; t[1][0] = 128; t[1][1] = 4; return 2;
+      case 1024: t[0][0] = 128; t[0][1] = 8; t[1][0] = 64; t[1][1] = 16; t[2][0] = 256; t[2][1] = 4; return 3;
+      case 2048: t[0][0] = 256; t[0][1] = 8; t[1][0] = 128; t[1][1] = 16; return 2;
+      case 4096: t[0][0] = 256; t[0][1] = 16; t[1][0] = 512; t[1][1] = 8; t[2][0] = 1024; t[2][1] = 4; return 3;
+      case 8192: t[0][0] = 512; t[0][1] = 16; t[1][0] = 1024; t[1][1] = 8; return 2;
+      case 16384: t[0][0] = 1024; t[0][1] = 16; t[1][0] = 512; t[1][1] = 32; return 2;
     }
-    return 1;
+    return 0;
+  }
+  static int count(uint32_t bound) {
+    int t[MAXC][2];
+    const int c = table(bound, t);
+    return FULL ? c : (c ? 1 : 0);
   }
   static void shape(uint32_t bound, int idx, int* wg, int* ipt) {
-    static const int t256[2][2] = {{64, 4}, {128, 2}};
-    static const int t1k[3][2] = {{128, 8}, {64, 16}, {256, 4}};
-    static const int t2k[2][2] = {{256, 8}, {128, 16}};
-    static const int t4k[3][2] = {{256, 16}, {512, 8}, {1024, 4}};
-    static const int t16k[2][2] = {{1024, 16}, {512, 32}};
-    const int(*t)[2] = bound == 256 ? t256 : bound == 1024 ? t1k : bound == 2048 ? t2k : bound == 4096 ? t4k : t16k;
+    int t[MAXC][2];
+    table(bound, t);
     *wg = t[idx][0];
     *ipt = t[idx][1];
   }
@@ -71,6 +75,9 @@ struct SegCands {
       case 256:
         if constexpr (FULL) if (idx == 1) return launch_small<K, V, 128, 2>(keys, vals, off, st, cls, nseg, s);
         return launch_small<K, V, 64, 4>(keys, vals, off, st, cls, nseg, s);
+      case 512:
+        if constexpr (FULL) if (idx == 1) return launch_small<K, V, 128, 4>(keys, vals, off, st, cls, nseg, s);
+        return launch_small<K, V, 64, 8>(keys, vals, off, st, cls, nseg, s);
       case 1024:
         if constexpr (FULL) {
           if (idx == 1) return launch_small<K, V, 64, 16>(keys, vals, off, st, cls, nseg, s);
@@ -86,6 +93,12 @@ struct SegCands {
           if (idx == 2) return launch_small<K, V, 1024, 4>(keys, vals, off, st, cls, nseg, s);
         }
         return launch_small<K, V, 256, 16>(keys, vals, off, st, cls, nseg, s);
+      case 8192:
+        if constexpr (sizeof(K) == 4 && !HasVal<V>::value) {
+          if (idx == 1) return launch_small<K, V, 1024, 8>(keys, vals, off, st, cls, nseg, s);
+          return launch_small<K, V, 512, 16>(keys, vals, off, st, cls, nseg, s);
+        }
+        break;
       case 16384:
         if constexpr (sizeof(K) == 4 && !HasVal<V>::value) {
           if (idx == 1) return launch_small<K, V, 512, 32>(keys, vals, off, st, cls, nseg, s);

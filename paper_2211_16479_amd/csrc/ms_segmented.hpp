@@ -27,7 +27,7 @@
 
 namespace ms {
 
-constexpr int SEG_MAX_CLASSES = 5;
+constexpr int SEG_MAX_CLASSES = 8;
 constexpr int SEG_MAX_CANDIDATES = 3;
 
 // Device-side state of one segmented sort (all in library scratch).
@@ -99,9 +99,10 @@ __device__ __forceinline__ int seg_passes(uint64_t L, uint64_t T) {
 // lv = P % 2 + 2 (j - P % 2) and lv + 1.
 __device__ __forceinline__ int seg_steps(int P) { return P / 2 + P % 2; }
 
-// Size classes of one (key, value) family: small classes have upper bounds
-// 256, 1024, 4096, 16384 (capped at the large-segment tile), larger segments
-// go through the tile sort + merge passes.
+// Size classes of one (key, value) family: small classes have the
+// power-of-two upper bounds 256, 512, ... up to the large-segment tile
+// (at most 16384), so a segment pads its tile sort by less than 2x; longer
+// segments go through the tile sort + merge passes.
 template <class K, class V>
 struct SegCfg {
   using P = PlainCfg<K, V>;
@@ -112,11 +113,11 @@ struct SegCfg {
   static constexpr int TILE = LWG * LIPT;  // large segments: tile-sort tile
   static constexpr int MTILE = P::MTILE;  // large segments: merge tile
   static constexpr int C = TILE / MTILE;  // merge tiles per tile
-  static constexpr int NCLS = TILE >= 16384 ? 4 : (TILE >= 4096 ? 3 : (TILE >= 2048 ? 3 : 2));
-  static __host__ __device__ constexpr uint32_t cls_max(int c) {
-    return c == 0 ? 256u : c == 1 ? 1024u : c == 2 ? (TILE >= 4096 ? 4096u : uint32_t(TILE)) : 16384u;
-  }
+  static constexpr int log2c(int x) { return x <= 1 ? 0 : 1 + log2c(x / 2); }
+  static constexpr int NCLS = log2c(TILE) - 7;  // classes 256 .. TILE
+  static __host__ __device__ constexpr uint32_t cls_max(int c) { return 256u << c; }
   static_assert(TILE % MTILE == 0, "tile must be a whole number of merge tiles");
+  static_assert((TILE & (TILE - 1)) == 0 && TILE >= 512 && NCLS <= SEG_MAX_CLASSES, "class bounds");
 };
 
 template <class K, class V>

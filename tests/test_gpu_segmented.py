@@ -12,7 +12,7 @@ from gpu_helpers import assert_equal_arrays, keys_fill, to_dev
 
 pytestmark = pytest.mark.gpu
 
-BOUNDARY_LENS = [0, 1, 2, 3, 0, 255, 256, 257, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097,
+BOUNDARY_LENS = [0, 1, 2, 3, 0, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097,
                  8191, 8192, 8193, 16383, 16384, 16385, 40000, 65536, 100_003, 1, 0]
 
 
