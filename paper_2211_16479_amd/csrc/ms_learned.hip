@@ -139,6 +139,14 @@ static LsBins ls_bins(char* w, const LsPlan& P) {
   return b;
 }
 
+// Tile-sort shape (candidate index) per size class of the bucket sort.  The
+// learned buckets (lengths spread around the fill, 512) favour other
+// shapes than the batched form's autotuned table, whose segment lengths are
+// log-uniform inside each class; measured on the 2^29 mixture, one class
+// changed at a time: 256: 64x4, 512: 128x4, 1024: 128x8, 2048: 256x8,
+// 4096: 1024x4, 8192: 512x16, 16384: 1024x16.
+static const int kLearnedBucketShapes[8] = {0, 1, 0, 0, 2, 0, 0, 0};  // at least the class count
+
 // Model training on an already sorted sample: start point, then T Adam steps.
 static ms_status ls_train_enqueue(const uint32_t* sample, uint32_t S, LsModel* md, float* partial, int T, float lr,
                                   float* loss_hist, bool init, hipStream_t s) {
@@ -210,7 +218,7 @@ static ms_status learned_enqueue(uint32_t* keys, uint64_t n, const ms_options& o
   {
     ProfScope ps(PK_LEARN_BUCKET, s);
     st = seg_enqueue<uint32_t, NoVal>(keys, nullptr, bn.seg_off, P.B, o.bucket_capacity, o.bucket_capacity, w + P.seg,
-                                      s, seg_tuning_row(MS_KEY_U32, 0), SegFork{nullptr, nullptr, nullptr},
+                                      s, kLearnedBucketShapes, SegFork{nullptr, nullptr, nullptr},
                                       reinterpret_cast<void* const*>(&md->r_keys));
   }
   if (st != MS_OK) return st;
@@ -327,7 +335,7 @@ ms_status ms_sort_ex(void* d_keys, size_t n, ms_key_type kt, const ms_options* o
     // on every launch
     std::vector<uint64_t> key = {2, n, d_stats ? 1u : 0u, th_bits, o.bucket_capacity, o.bucket_fill, o.train_steps,
                                  lr_bits, o.sample_log2, o.seed, uint64_t(o.feature), uint64_t(o.use_network),
-                                 uint64_t(o.force_fallback), seg_tuning_generation()};
+                                 uint64_t(o.force_fallback)};
     return cached_graph_launch(
         key, P.bytes, {d_keys, d_stats},
         [&](void* ws, void* const* io, hipStream_t cs, SegFork) {
