@@ -168,43 +168,57 @@ ms_status ms_tuning_get(ms_key_type kt, size_t val_bytes, int cls, int* wg, int*
 ms_status ms_tuning_load(const char* path, const char* arch, int* applied);
 
 /* ------------------------------------------------------------------------
- * Learned-bucket form (uint32 keys).  A small two-layer ReLU MLP
+ * Learned-bucket form (all four key types).  A small two-layer ReLU MLP
  *   F(x) = b2 + sum_h w2_h * relu(w1_h * x + b1_h),   H = 16 hidden units,
- * of a feature x of the key (MS_FEATURE_LOG: a monotone piecewise-linear
- * log2(1 + key) / 32 computed from the float bits; MS_FEATURE_LINEAR:
- * key * 2^-32) is trained on the GPU to map keys to normalised ranks, on a
+ * of a feature x of the key is trained on the GPU to map keys to normalised
+ * ranks.  Features: uint32 keys u, MS_FEATURE_LOG a monotone
+ * piecewise-linear log2(1 + u) / 32 computed from the float bits and
+ * MS_FEATURE_LINEAR u * 2^-32; the other types, with u the key's
+ * order-preserving unsigned image (the sign bit flipped for signed types),
+ * the same two forms of the offset d = u - u0 (0 below u0), where u0 lies
+ * 1/64 of the sample's range below the sample's smallest u (or is 0):
+ * (float bits of 1 + d minus those of 1.0) * 2^-29, and d * 2^-e with e the
+ * bit length of (the sample's largest u) - u0.  Training runs on a
  * sample of 2^sample_log2 keys that the plain merge sort ranks: closed-form
  * start at the piecewise-linear interpolant through 16 sample quantiles,
  * then full-batch Adam on the mean squared rank error.  The trained network
  * is evaluated as the piecewise-linear function it is, on the sample's
- * feature range with the ends pinned to the sample's extreme mid-ranks, and
- * through a running-max envelope, so bucket ids floor(F(x) * B) are
+ * feature range with the ends pinned to the sample's extreme mid-ranks,
+ * through a running-max envelope, and beyond that range along its first and
+ * last segments (clipped to [0, 1]), so bucket ids floor(F(x) * B) are
  * non-decreasing in the key.
  * Keys are scattered (two levels) into B ~ n / bucket_fill buckets; buckets
- * of at most bucket_capacity keys are sorted in LDS; larger ones spill.  The
+ * of at most bucket_capacity keys (64-bit keys: at most 4096, the largest
+ * bucket one workgroup sorts in LDS) are sorted in LDS; larger ones spill.  The
  * spill is sorted by the plain merge sort and merged back with one exact
  * merge-path pass.  If more than spill_threshold * n keys spill, or the order
  * check of the buckets fails, the plain merge sort sorts the input instead
  * (decided on the device).  The output is the same bytes as ms_sort's.
  * ------------------------------------------------------------------------ */
 typedef enum ms_algo {
-  MS_ALGO_AUTO = 0,            /* learned for uint32 and n >= 2^27, else merge path */
+  MS_ALGO_AUTO = 0,            /* learned for uint32 keys and n >= 2^27, else merge path */
   MS_ALGO_MERGE_PATH = 1,
   MS_ALGO_LEARNED_BUCKET = 2
 } ms_algo;
 
-typedef enum ms_feature { MS_FEATURE_LOG = 0, MS_FEATURE_LINEAR = 1 } ms_feature;
+/* MS_FEATURE_AUTO: log for uint32 keys, linear for the other types (a log
+ * of the offset from the sample's smallest key crowds the lower tail of a
+ * symmetric distribution into a few buckets). */
+typedef enum ms_feature { MS_FEATURE_LOG = 0, MS_FEATURE_LINEAR = 1, MS_FEATURE_AUTO = 2 } ms_feature;
 
 typedef struct ms_options {
   int algo;                  /* ms_algo */
   float spill_threshold;     /* fall back when spilled keys > this * n; [0, 0.5], default 0.05 */
   uint32_t bucket_capacity;  /* keys sorted per LDS bucket: 4096 or 16384 (default) */
-  uint32_t bucket_fill;      /* target mean keys per bucket, 64..capacity, default 512 */
+  uint32_t bucket_fill;      /* target mean keys per bucket, 64..capacity; 0 (default): 512 for
+                                32-bit keys, 256 for 64-bit keys */
   uint32_t train_steps;      /* Adam steps, default 16 */
   float learning_rate;       /* default 1e-4 */
-  uint32_t sample_log2;      /* log2 of the sample size, 10..20, default 16 */
+  uint32_t sample_log2;      /* log2 of the sample size, 10..20; 0 (default): 16 for 32-bit keys,
+                                18 for 64-bit keys (about n / 2^sample_log2 keys fall beyond each
+                                of the sample's extremes and share one end bucket) */
   uint64_t seed;             /* sample positions, default 0 */
-  int feature;               /* ms_feature, default MS_FEATURE_LOG */
+  int feature;               /* ms_feature, default MS_FEATURE_AUTO */
   int use_network;           /* 1 (default); 0: bucket = floor(x * B) with no network */
   int force_fallback;        /* 1: always take the plain merge sort (testing) */
   int use_graph;             /* 1 (default): replay a cached hipGraph of the pipeline */
@@ -232,19 +246,20 @@ void ms_options_default(ms_options* opt);
 /*
  * ms_sort_ex -- ms_sort with a choice of algorithm.  opt may be NULL
  * (defaults); d_stats may be NULL, otherwise a device pointer to one
- * ms_stats.  MS_ALGO_LEARNED_BUCKET requires MS_KEY_U32,
- * n >= 4 * 2^sample_log2 and n < 2^32 (else MS_ERR_UNSUPPORTED); invalid
- * options give MS_ERR_INVALID_ARG.  The learned pipeline is replayed from a
- * cached hipGraph (use_graph = 1) keyed by n, whether d_stats is NULL and the
- * options (not by the buffers, which are bound per launch); the graph owns
- * ms_temp_bytes_learned(n, opt) bytes of scratch.
+ * ms_stats.  MS_ALGO_LEARNED_BUCKET requires n >= 4 * 2^sample_log2 (the
+ * resolved value: 2^20 keys for 64-bit keys by default) and
+ * n < 2^32 (else MS_ERR_UNSUPPORTED); invalid options give
+ * MS_ERR_INVALID_ARG.  The learned pipeline is replayed from a cached
+ * hipGraph (use_graph = 1) keyed by the key type, n, whether d_stats is NULL
+ * and the options (not by the buffers, which are bound per launch); the
+ * graph owns ms_temp_bytes_learned(n, kt, opt) bytes of scratch.
  */
 ms_status ms_sort_ex(void* d_keys, size_t n, ms_key_type kt, const ms_options* opt, ms_stats* d_stats,
                      void* stream);
-size_t ms_temp_bytes_learned(size_t n, const ms_options* opt);
+size_t ms_temp_bytes_learned(size_t n, ms_key_type kt, const ms_options* opt);
 
 /*
- * Steps of the learned form, for tests and inspection (all device pointers;
+ * Steps of the learned form on uint32 keys, for tests and inspection (all device pointers;
  * parameters theta are 49 floats laid out [w1 x16, b1 x16, w2 x16, b2]):
  *   ms_learned_grad   : at theta, over the sorted sample (S keys, target of
  *                       position i = (i + 0.5) / S), write the gradient of the
@@ -280,8 +295,8 @@ ms_status ms_learned_bucket_ids(const uint32_t* d_keys, size_t n, const float* d
  * num_segments segments and n_total keys owns (0 for an unsupported type).
  *
  * ms_temp_bytes_learned -- scratch that one ms_sort_ex learned-bucket graph
- * of n uint32 keys owns under options opt (NULL = defaults); 0 if the
- * options are invalid.  Host arithmetic only.
+ * of n keys of type kt owns under options opt (NULL = defaults); 0 if the
+ * options or the key type are invalid.  Host arithmetic only.
  */
 size_t ms_temp_bytes(size_t n, ms_key_type kt, size_t val_bytes);
 size_t ms_temp_bytes_segmented(size_t num_segments, size_t n_total, ms_key_type kt, size_t val_bytes);

@@ -30,13 +30,20 @@ feature range [x_min, x_max]: points x_min, the breakpoints strictly inside,
 x_max; values the running maximum of F at those points (the smallest
 non-decreasing function >= F there), clamped into [0.5/S, 1 - 0.5/S], with
 the two ends pinned to 0.5/S and 1 - 0.5/S -- the mid-ranks of the sample's
-own extremes.  `pl_eval` clamps x into the range and interpolates linearly,
-capped at the next point's value.  Inside the range, wherever F is
-non-decreasing and within the clamp, the table reproduces F; everywhere it
-is non-decreasing, so bucket ids derived from it are ordered like the keys.
-(Pinning the ends keeps the thin tails of a distribution from collapsing
-into the first and last bucket when the trained F over- or undershoots
-there.)
+own extremes; then every interior point whose value (as a float32, the
+precision the table is stored in) is not above the previous kept point's, or
+reaches the upper clamp, is dropped, so no segment is flat (a flat segment
+would send all its keys to one bucket).  `pl_eval` finds x's segment (the first one for x below the
+range, the last one above it) and interpolates linearly, capped at the next
+point's value inside the range; beyond the ends the first and last segments
+continue with their slopes, clipped to [0, 1].  Inside the range, wherever F
+is non-decreasing and within the clamp, the table reproduces F; everywhere
+it is non-decreasing, so bucket ids derived from it are ordered like the
+keys.  (Pinning the ends keeps the thin tails of a distribution from
+collapsing into the first and last bucket when the trained F over- or
+undershoots there; continuing the end segments spreads the keys beyond the
+sample's extremes -- about n / S of them at each end -- over the buckets of
+the remaining rank 0.5 / S, where a clamp would put them all into one.)
 
 Input features are computed from the integer key in float32, exactly as the
 GPU computes them (IEEE round-to-nearest-even), so both sides see
@@ -154,18 +161,26 @@ def pl_table(theta: np.ndarray, H: int, x_min: float, x_max: float, S: int):
     lo, hi = 0.5 / S, 1.0 - 0.5 / S
     V = np.clip(np.maximum.accumulate(forward(theta, t, H)), lo, hi)
     V[0], V[-1] = lo, hi
-    return t, V
+    keep = [0]   # compared as the float32 values the table stores
+    f = V.astype(np.float32)
+    for i in range(1, t.size - 1):
+        if f[keep[-1]] < f[i] < np.float32(hi):
+            keep.append(i)
+    keep.append(t.size - 1)
+    return t[keep], V[keep]
 
 
 def pl_eval(table, x: np.ndarray) -> np.ndarray:
-    """Monotone evaluation of a table: clamp x to [t_0, t_last], find the
-    segment, interpolate, cap at the segment's right value."""
+    """Monotone evaluation of a table: find x's segment (the first below
+    t_0, the last above t_last), interpolate, cap at the segment's right
+    value (1 for the last segment), floor at 0."""
     t, V = table
-    x = np.clip(np.asarray(x, np.float64), t[0], t[-1])
+    x = np.asarray(x, np.float64)
     j = np.clip(np.searchsorted(t, x, side="right") - 1, 0, t.size - 2)
     dt = t[j + 1] - t[j]
     slope = np.where(dt > 0, (V[j + 1] - V[j]) / np.where(dt > 0, dt, 1.0), 0.0)
-    return np.minimum(V[j] + slope * (x - t[j]), V[j + 1])
+    cap = np.where(j == t.size - 2, 1.0, V[j + 1])
+    return np.clip(V[j] + slope * (x - t[j]), 0.0, cap)
 
 
 def feature_linear(keys: np.ndarray) -> np.ndarray:

@@ -30,7 +30,7 @@ PROFILE_KERNELS = {"tile_sort": 0, "partition": 1, "merge": 2, "seg_classify": 3
                    "partition_samples": 15}
 
 MS_ALGO_AUTO, MS_ALGO_MERGE_PATH, MS_ALGO_LEARNED_BUCKET = 0, 1, 2
-MS_FEATURE_LOG, MS_FEATURE_LINEAR = 0, 1
+MS_FEATURE_LOG, MS_FEATURE_LINEAR, MS_FEATURE_AUTO = 0, 1, 2
 MLP_HIDDEN = 16
 MLP_PARAMS = 3 * MLP_HIDDEN + 1
 
@@ -74,7 +74,7 @@ def _declare(lib):
         "ms_sort_noalloc": (i32, [vp, sz, i32, vp]),
         "ms_temp_bytes": (sz, [sz, i32, sz]),
         "ms_temp_bytes_segmented": (sz, [sz, sz, i32, sz]),
-        "ms_temp_bytes_learned": (sz, [sz, c.POINTER(MsOptions)]),
+        "ms_temp_bytes_learned": (sz, [sz, c.c_int, c.POINTER(MsOptions)]),
         "ms_graph_captures": (c.c_uint64, []),
         "ms_device_errors": (i32, [c.POINTER(c.c_uint32)]),
         "ms_plan_query": (i32, [sz, i32, sz, c.POINTER(i32), c.POINTER(i32), c.POINTER(i32),
@@ -356,13 +356,13 @@ def ms_temp_bytes_segmented(num_segments: int, n_total: int, key_type: int, val_
     return int(lib().ms_temp_bytes_segmented(num_segments, n_total, key_type, val_bytes))
 
 
-def ms_temp_bytes_learned(n: int, **options) -> int:
+def ms_temp_bytes_learned(n: int, key_type: int = MS_KEY_U32, **options) -> int:
     o = ms_options_default()
     for k, v in options.items():
         if not hasattr(o, k):
             raise TypeError(f"unknown option {k}")
         setattr(o, k, v)
-    return int(lib().ms_temp_bytes_learned(n, ctypes.byref(o)))
+    return int(lib().ms_temp_bytes_learned(n, key_type, ctypes.byref(o)))
 
 
 def ms_device_errors() -> int:

@@ -29,6 +29,8 @@ __global__ void ls_setup_kernel(LsModel* md, int log_feature, int use_table, int
   md->max_bucket = 0;
   md->loss0 = 0.f;
   md->loss_last = 0.f;
+  md->off64 = 0;
+  md->scale64 = 1.f;
 }
 
 __global__ void ls_set_theta_kernel(LsModel* md, const float* theta) {
@@ -84,12 +86,24 @@ __global__ void ls_stats_kernel(const LsModel* md, ms_stats* st, uint64_t bucket
   st->loss_final = md->loss_last;
 }
 
+// 1 for the log feature, 0 for the linear one.  MS_FEATURE_AUTO: log for
+// uint32 keys (the key itself, suited to skewed positive workloads), linear
+// for the other types (their feature works on offsets from the sample's
+// smallest key, where a log would crowd the lower tail of a symmetric
+// distribution into a few buckets).
+static int log_feature(int feature, bool uint32_keys) {
+  if (feature == MS_FEATURE_AUTO) return uint32_keys ? 1 : 0;
+  return feature == MS_FEATURE_LOG ? 1 : 0;
+}
+
 // Sizes of one learned sort.
 struct LsPlan {
   uint32_t S;          // sample size
   int cb, fb;          // coarse / fine bits
   uint32_t nbc, nbf;   // coarse / fine bins
   uint64_t B;          // buckets
+  uint32_t capacity;   // largest bucket sorted in place (the option, at most
+                       // the bucket sort's largest small class for the key type)
   uint64_t spill_cap;  // spill that still takes the learned path
   uint64_t chunk_cap;  // bound on level-2 chunks
   // scratch offsets
@@ -97,9 +111,19 @@ struct LsPlan {
   size_t bins_c_off[9], bins_f_off[3];
 };
 
+template <class K>
+static uint32_t ls_capacity(const ms_options& o) {
+  uint32_t bound = 0;
+  int ncand = 0;
+  seg_class_info<K, NoVal>(seg_num_classes<K, NoVal>() - 1, &bound, &ncand);
+  return std::min<uint32_t>(o.bucket_capacity, bound);
+}
+
+template <class K>
 static LsPlan ls_plan(uint64_t n, const ms_options& o) {
   LsPlan P{};
   P.S = 1u << o.sample_log2;
+  P.capacity = ls_capacity<K>(o);
   const uint64_t want = std::max<uint64_t>(1, (n + o.bucket_fill - 1) / o.bucket_fill);
   int tb = 0;
   while ((uint64_t(1) << tb) < want && tb < 20) ++tb;
@@ -109,21 +133,21 @@ static LsPlan ls_plan(uint64_t n, const ms_options& o) {
   P.nbf = 1u << P.fb;
   P.B = uint64_t(1) << tb;
   P.spill_cap = std::min<uint64_t>(n, uint64_t(std::ceil(double(o.spill_threshold) * double(n))));
-  P.chunk_cap = ceil_div(n, LS_CHK) + P.nbc;
+  P.chunk_cap = ceil_div(n, ls_chk<K>()) + P.nbc;
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t at = off; off = align_up(off + bytes, 256); return at; };
   P.md = take(sizeof(LsModel));
-  P.sample = take(sizeof(uint32_t) * P.S);
-  P.sample_tmp = take(plain_temp_bytes<uint32_t, NoVal>(P.S));
+  P.sample = take(sizeof(K) * P.S);
+  P.sample_tmp = take(plain_temp_bytes<K, NoVal>(P.S));
   P.partial = take(sizeof(float) * 2 * LS_TRAIN_G * LS_PS);
   P.loss = take(sizeof(float) * (o.train_steps + 1));
   for (int i = 0; i < 9; ++i) P.bins_c_off[i] = take(sizeof(uint32_t) * (P.nbc + 1));
   for (int i = 0; i < 2; ++i) P.bins_f_off[i] = take(sizeof(uint32_t) * P.B);
   P.bins_f_off[2] = take(sizeof(int64_t) * (P.B + 1));
-  P.coarse = take(std::max<size_t>(sizeof(uint32_t) * n, plain_temp_bytes<uint32_t, NoVal>(n)));
-  P.xr = take(sizeof(uint32_t) * n);
-  P.part = take(sizeof(int64_t) * (ceil_div(n, PlainCfg<uint32_t, NoVal>::MTILE) + 2));  // merge_two_runs
-  P.seg = take(seg_temp_bytes<uint32_t, NoVal>(P.B, o.bucket_capacity));
+  P.coarse = take(std::max<size_t>(sizeof(K) * n, plain_temp_bytes<K, NoVal>(n)));
+  P.xr = take(sizeof(K) * n);
+  P.part = take(sizeof(int64_t) * (ceil_div(n, PlainCfg<K, NoVal>::MTILE) + 2));  // merge_two_runs
+  P.seg = take(seg_temp_bytes<K, NoVal>(P.B, P.capacity));
   P.bytes = off;
   return P;
 }
@@ -148,7 +172,8 @@ static LsBins ls_bins(char* w, const LsPlan& P) {
 static const int kLearnedBucketShapes[8] = {0, 1, 0, 0, 2, 0, 0, 0};  // at least the class count
 
 // Model training on an already sorted sample: start point, then T Adam steps.
-static ms_status ls_train_enqueue(const uint32_t* sample, uint32_t S, LsModel* md, float* partial, int T, float lr,
+template <class K>
+static ms_status ls_train_enqueue(const K* sample, uint32_t S, LsModel* md, float* partial, int T, float lr,
                                   float* loss_hist, bool init, hipStream_t s) {
   if (init) ls_init_kernel<<<1, 64, 0, s>>>(sample, S, md);
   for (int t = 0; t <= T; ++t) {
@@ -161,27 +186,29 @@ static ms_status ls_train_enqueue(const uint32_t* sample, uint32_t S, LsModel* m
 
 // io: if non-null, the caller's buffers of this launch are read from io[0]
 // (keys) and io[1] (stats) at run time (graph replays on new buffers).
-static ms_status learned_enqueue(uint32_t* keys, uint64_t n, const ms_options& o, ms_stats* d_stats, void* ws,
+template <class K>
+static ms_status learned_enqueue(K* keys, uint64_t n, const ms_options& o, ms_stats* d_stats, void* ws,
                                  void* const* io, hipStream_t s) {
-  const LsPlan P = ls_plan(n, o);
+  const LsPlan P = ls_plan<K>(n, o);
   char* w = static_cast<char*>(ws);
   LsModel* md = reinterpret_cast<LsModel*>(w + P.md);
-  uint32_t* sample = reinterpret_cast<uint32_t*>(w + P.sample);
+  K* sample = reinterpret_cast<K*>(w + P.sample);
   float* partial = reinterpret_cast<float*>(w + P.partial);
   float* loss = reinterpret_cast<float*>(w + P.loss);
-  uint32_t* coarse = reinterpret_cast<uint32_t*>(w + P.coarse);
-  uint32_t* xr = reinterpret_cast<uint32_t*>(w + P.xr);
+  K* coarse = reinterpret_cast<K*>(w + P.coarse);
+  K* xr = reinterpret_cast<K*>(w + P.xr);
   int64_t* part = reinterpret_cast<int64_t*>(w + P.part);
   const LsBins bn = ls_bins(w, P);
   const DevCtl none{nullptr, nullptr, nullptr};
   const Rebind rk{keys, io ? &io[0] : nullptr};
   const Rebind rs{d_stats, io ? &io[1] : nullptr};
 
-  ls_setup_kernel<<<1, 64, 0, s>>>(md, o.feature == MS_FEATURE_LOG ? 1 : 0, o.use_network ? 1 : 0, P.cb, P.fb);
+  ls_setup_kernel<<<1, 64, 0, s>>>(md, log_feature(o.feature, std::is_same<K, uint32_t>::value), o.use_network ? 1 : 0, P.cb, P.fb);
   // sample, ranked by the plain merge sort
   ls_sample_kernel<<<dim3(unsigned(ceil_div(P.S, 256))), 256, 0, s>>>(keys, n, P.S, o.seed, sample, rk);
-  ms_status st = plain_sort<uint32_t, NoVal>(sample, nullptr, P.S, none, s, w + P.sample_tmp);
+  ms_status st = plain_sort<K, NoVal>(sample, nullptr, P.S, none, s, w + P.sample_tmp);
   if (st != MS_OK) return st;
+  ls_feature_range_kernel<K><<<1, 64, 0, s>>>(md, sample, P.S);
   // train and compile the network
   st = ls_train_enqueue(sample, P.S, md, partial, int(o.train_steps), o.learning_rate, loss, true, s);
   if (st != MS_OK) return st;
@@ -189,27 +216,28 @@ static ms_status learned_enqueue(uint32_t* keys, uint64_t n, const ms_options& o
   // level 1
   ls_clear_kernel<<<dim3(unsigned(ceil_div(std::max<uint64_t>(P.B, P.nbc), 256))), 256, 0, s>>>(bn, P.nbc,
                                                                                                  uint32_t(P.B));
-  const unsigned chunks1 = unsigned(ceil_div(n, LS_CHK));
+  const unsigned chunks1 = unsigned(ceil_div(n, ls_chk<K>()));
+  const uint32_t last_len = uint32_t(n - uint64_t(chunks1 - 1) * ls_chk<K>());
   {
     ProfScope ps(PK_LEARN_HIST, s);
-    ls_hist1_kernel<<<unsigned(ceil_div(chunks1, LS_H1)), LS_WG, 0, s>>>(keys, n, md, bn, rk);
+    ls_hist1_kernel<<<unsigned(ceil_div(chunks1, LS_H1)), LS_WG, 0, s>>>(keys, chunks1, last_len, md, bn, rk);
   }
-  ls_plan1_kernel<<<1, LS_WG, 0, s>>>(md, bn);
+  ls_plan1_kernel<<<1, LS_WG, 0, s>>>(md, bn, uint32_t(ls_chk<K>()));
   {
     ProfScope ps(PK_LEARN_SCATTER, s);
-    ls_scatter1_kernel<<<chunks1, LS_WG, 0, s>>>(keys, n, md, bn, coarse, rk);
+    ls_scatter1_kernel<<<chunks1, LS_WG, 0, s>>>(keys, chunks1, last_len, md, bn, coarse, rk);
   }
   // level 2
   {
     ProfScope ps(PK_LEARN_HIST2, s);
     ls_hist2_kernel<<<unsigned(P.chunk_cap), LS_WG, 0, s>>>(coarse, md, bn);
   }
-  ls_totals_kernel<<<P.nbc, LS_WG, 0, s>>>(md, bn, o.bucket_capacity);
+  ls_totals_kernel<<<P.nbc, LS_WG, 0, s>>>(md, bn, P.capacity);
   ls_plan2_kernel<<<1, LS_WG, 0, s>>>(md, bn, n, P.spill_cap, o.force_fallback, keys, xr, rk);
-  ls_offsets_kernel<<<P.nbc, LS_WG, 0, s>>>(md, bn, o.bucket_capacity);
+  ls_offsets_kernel<<<P.nbc, LS_WG, 0, s>>>(md, bn, P.capacity);
   {
     ProfScope ps(PK_LEARN_SCATTER2, s);
-    ls_scatter2_kernel<<<unsigned(P.chunk_cap), LS_WG, 0, s>>>(coarse, md, bn, o.bucket_capacity, xr);
+    ls_scatter2_kernel<<<unsigned(P.chunk_cap), LS_WG, 0, s>>>(coarse, md, bn, P.capacity, xr);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "learned bucketing launch");
@@ -217,27 +245,25 @@ static ms_status learned_enqueue(uint32_t* keys, uint64_t n, const ms_options& o
   // array chosen on the device (*md->r_keys)
   {
     ProfScope ps(PK_LEARN_BUCKET, s);
-    st = seg_enqueue<uint32_t, NoVal>(keys, nullptr, bn.seg_off, P.B, o.bucket_capacity, o.bucket_capacity, w + P.seg,
-                                      s, kLearnedBucketShapes, SegFork{nullptr, nullptr, nullptr},
-                                      reinterpret_cast<void* const*>(&md->r_keys));
+    st = seg_enqueue<K, NoVal>(keys, nullptr, bn.seg_off, P.B, P.capacity, P.capacity, w + P.seg, s,
+                               kLearnedBucketShapes, SegFork{nullptr, nullptr, nullptr},
+                               reinterpret_cast<void* const*>(&md->r_keys));
   }
   if (st != MS_OK) return st;
-  ls_check_kernel<<<dim3(unsigned(ceil_div(P.B, 256))), 256, 0, s>>>(md, bn, P.B);
+  ls_check_kernel<K><<<dim3(unsigned(ceil_div(P.B, 256))), 256, 0, s>>>(md, bn, P.B);
   // repair: spill sorted by the plain merge sort, then merged with the kept keys
   // (gated stages run with a bounded grid: when skipped they cost little)
   const uint64_t gated_grid = uint64_t(device_cu_count()) * 4;
   const uint64_t* spilled = reinterpret_cast<const uint64_t*>(&md->spilled);
   if (P.spill_cap > 0) {
-    st = plain_sort<uint32_t, NoVal>(xr, nullptr, P.spill_cap, DevCtl{spilled, &md->do_repair, nullptr}, s, coarse,
-                                     gated_grid);
+    st = plain_sort<K, NoVal>(xr, nullptr, P.spill_cap, DevCtl{spilled, &md->do_repair, nullptr}, s, coarse,
+                              gated_grid);
     if (st != MS_OK) return st;
-    st = merge_two_runs<uint32_t, NoVal>(xr, keys, n, DevCtl{nullptr, &md->do_repair, spilled, rk}, part, s,
-                                         gated_grid);
+    st = merge_two_runs<K, NoVal>(xr, keys, n, DevCtl{nullptr, &md->do_repair, spilled, rk}, part, s, gated_grid);
     if (st != MS_OK) return st;
   }
   // fallback: the plain merge sort of the untouched input
-  st = plain_sort<uint32_t, NoVal>(keys, nullptr, n, DevCtl{nullptr, &md->fallback, nullptr, rk}, s, coarse,
-                                   gated_grid);
+  st = plain_sort<K, NoVal>(keys, nullptr, n, DevCtl{nullptr, &md->fallback, nullptr, rk}, s, coarse, gated_grid);
   if (st != MS_OK) return st;
   if (d_stats) ls_stats_kernel<<<1, 64, 0, s>>>(md, d_stats, P.B, rs);
   e = hipGetLastError();
@@ -248,12 +274,56 @@ static ms_status check_options(const ms_options& o) {
   if (o.algo < MS_ALGO_AUTO || o.algo > MS_ALGO_LEARNED_BUCKET) return MS_ERR_INVALID_ARG;
   if (!(o.spill_threshold >= 0.f && o.spill_threshold <= 0.5f)) return MS_ERR_INVALID_ARG;
   if (o.bucket_capacity != 4096 && o.bucket_capacity != 16384) return MS_ERR_INVALID_ARG;
-  if (o.bucket_fill < 64 || o.bucket_fill > o.bucket_capacity) return MS_ERR_INVALID_ARG;
+  if (o.bucket_fill != 0 && (o.bucket_fill < 64 || o.bucket_fill > o.bucket_capacity)) return MS_ERR_INVALID_ARG;
   if (o.train_steps > 100000) return MS_ERR_INVALID_ARG;
   if (!(o.learning_rate >= 0.f && o.learning_rate < 1.f)) return MS_ERR_INVALID_ARG;
-  if (o.sample_log2 < 10 || o.sample_log2 > 20) return MS_ERR_INVALID_ARG;
-  if (o.feature != MS_FEATURE_LOG && o.feature != MS_FEATURE_LINEAR) return MS_ERR_INVALID_ARG;
+  if (o.sample_log2 != 0 && (o.sample_log2 < 10 || o.sample_log2 > 20)) return MS_ERR_INVALID_ARG;
+  if (o.feature != MS_FEATURE_LOG && o.feature != MS_FEATURE_LINEAR && o.feature != MS_FEATURE_AUTO)
+    return MS_ERR_INVALID_ARG;
   return MS_OK;
+}
+
+// The learned sort of one key type: direct enqueue, or the cached graph.
+template <class K>
+static ms_status learned_sort(K* keys, ms_key_type kt, uint64_t n, const ms_options& o, ms_stats* d_stats,
+                              hipStream_t s) {
+  const LsPlan P = ls_plan<K>(n, o);
+  if (!o.use_graph) {
+    void* ws = nullptr;
+    ms_status st = get_workspace(s, P.bytes, &ws);
+    if (st != MS_OK) return st;
+    return learned_enqueue(keys, n, o, d_stats, ws, nullptr, s);
+  }
+  uint32_t lr_bits, th_bits;
+  std::memcpy(&lr_bits, &o.learning_rate, 4);
+  std::memcpy(&th_bits, &o.spill_threshold, 4);
+  // the graph does not depend on the buffers: keys and stats are rebound on
+  // every launch
+  std::vector<uint64_t> key = {2, uint64_t(kt), n, d_stats ? 1u : 0u, th_bits, o.bucket_capacity, o.bucket_fill,
+                               o.train_steps, lr_bits, o.sample_log2, o.seed, uint64_t(o.feature),
+                               uint64_t(o.use_network), uint64_t(o.force_fallback)};
+  return cached_graph_launch(
+      key, P.bytes, {static_cast<void*>(keys), d_stats},
+      [&](void* ws, void* const* io, hipStream_t cs, SegFork) {
+        return learned_enqueue(keys, n, o, d_stats, ws, io, cs);
+      },
+      s);
+}
+
+// Automatic choice of the learned form (MS_ALGO_AUTO).
+static bool learned_auto(ms_key_type kt, uint64_t n) {
+  return kt == MS_KEY_U32 && n >= (uint64_t(1) << 27);
+}
+
+// Options left at 0 take the key type's defaults.  64-bit keys: a 2^18-key
+// sample and 256 keys per bucket, since about n / S keys fall beyond each of
+// the sample's extremes and share one bucket there, and a workgroup sorts
+// at most 4096 such keys in LDS; 32-bit keys: 2^16 and 512 (capacity 16384).
+static ms_options resolve_options(ms_options o, ms_key_type kt) {
+  const bool wide = kt == MS_KEY_U64 || kt == MS_KEY_I64;
+  if (o.sample_log2 == 0) o.sample_log2 = wide ? 18 : 16;
+  if (o.bucket_fill == 0) o.bucket_fill = wide ? 256 : 512;
+  return o;
 }
 
 // A scratch LsModel for the step-level entry points (per device, stream).
@@ -276,12 +346,12 @@ void ms_options_default(ms_options* o) {
   o->algo = MS_ALGO_AUTO;
   o->spill_threshold = 0.05f;
   o->bucket_capacity = 16384;
-  o->bucket_fill = 512;
+  o->bucket_fill = 0;
   o->train_steps = 16;
   o->learning_rate = 1e-4f;
-  o->sample_log2 = 16;
+  o->sample_log2 = 0;
   o->seed = 0;
-  o->feature = MS_FEATURE_LOG;
+  o->feature = MS_FEATURE_AUTO;
   o->use_network = 1;
   o->force_fallback = 0;
   o->use_graph = 1;
@@ -304,12 +374,16 @@ ms_status ms_sort_ex(void* d_keys, size_t n, ms_key_type kt, const ms_options* o
     return MS_ERR_UNSUPPORTED;
   }
   if (n == 0) return MS_OK;
-  const bool learned_ok = kt == MS_KEY_U32 && n >= (uint64_t(4) << o.sample_log2) && n < (uint64_t(1) << 32);
+  o = resolve_options(o, kt);
+  const bool learned_ok = n >= (uint64_t(4) << o.sample_log2) && n < (uint64_t(1) << 32);
   if (o.algo == MS_ALGO_LEARNED_BUCKET && !learned_ok) {
-    set_error("the learned-bucket form needs uint32 keys, n >= 4 * sample size and n < 2^32");
+    set_error("the learned-bucket form needs n >= 4 * sample size and n < 2^32");
     return MS_ERR_UNSUPPORTED;
   }
-  const bool learned = learned_ok && o.algo != MS_ALGO_MERGE_PATH && (o.algo == MS_ALGO_LEARNED_BUCKET || n >= (1u << 27));
+  // automatic choice: where the learned form was measured faster than the
+  // plain sort (see learned_auto)
+  const bool learned = learned_ok && o.algo != MS_ALGO_MERGE_PATH &&
+                       (o.algo == MS_ALGO_LEARNED_BUCKET || learned_auto(kt, n));
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (!learned) {
     ms_status st = o.max_workgroups ? plain_sort_capped(d_keys, n, kt, o.max_workgroups, s)
@@ -320,41 +394,33 @@ ms_status ms_sort_ex(void* d_keys, size_t n, ms_key_type kt, const ms_options* o
     return e == hipSuccess ? MS_OK : hip_fail(e, "stats launch");
   }
   try {
-    const LsPlan P = ls_plan(n, o);
-    uint32_t* keys = static_cast<uint32_t*>(d_keys);
-    if (!o.use_graph) {
-      void* ws = nullptr;
-      ms_status st = get_workspace(s, P.bytes, &ws);
-      if (st != MS_OK) return st;
-      return learned_enqueue(keys, n, o, d_stats, ws, nullptr, s);
+    switch (kt) {
+      case MS_KEY_U32: return learned_sort(static_cast<uint32_t*>(d_keys), kt, n, o, d_stats, s);
+      case MS_KEY_I32: return learned_sort(static_cast<int32_t*>(d_keys), kt, n, o, d_stats, s);
+      case MS_KEY_U64: return learned_sort(static_cast<uint64_t*>(d_keys), kt, n, o, d_stats, s);
+      case MS_KEY_I64: return learned_sort(static_cast<int64_t*>(d_keys), kt, n, o, d_stats, s);
     }
-    uint32_t lr_bits, th_bits;
-    std::memcpy(&lr_bits, &o.learning_rate, 4);
-    std::memcpy(&th_bits, &o.spill_threshold, 4);
-    // the graph does not depend on the buffers: keys and stats are rebound
-    // on every launch
-    std::vector<uint64_t> key = {2, n, d_stats ? 1u : 0u, th_bits, o.bucket_capacity, o.bucket_fill, o.train_steps,
-                                 lr_bits, o.sample_log2, o.seed, uint64_t(o.feature), uint64_t(o.use_network),
-                                 uint64_t(o.force_fallback)};
-    return cached_graph_launch(
-        key, P.bytes, {d_keys, d_stats},
-        [&](void* ws, void* const* io, hipStream_t cs, SegFork) {
-          return learned_enqueue(keys, n, o, d_stats, ws, io, cs);
-        },
-        s);
+    return MS_ERR_UNSUPPORTED;
   } catch (...) {
     set_error("unexpected exception");
     return MS_ERR_INTERNAL;
   }
 }
 
-size_t ms_temp_bytes_learned(size_t n, const ms_options* opt) {
+size_t ms_temp_bytes_learned(size_t n, ms_key_type kt, const ms_options* opt) {
   ms_options o;
   ms_options_default(&o);
   if (opt) o = *opt;
   if (check_options(o) != MS_OK || n == 0) return 0;
+  o = resolve_options(o, kt);
   try {
-    return graph_bind_bytes() + ls_plan(n, o).bytes;
+    switch (kt) {
+      case MS_KEY_U32: return graph_bind_bytes() + ls_plan<uint32_t>(n, o).bytes;
+      case MS_KEY_I32: return graph_bind_bytes() + ls_plan<int32_t>(n, o).bytes;
+      case MS_KEY_U64: return graph_bind_bytes() + ls_plan<uint64_t>(n, o).bytes;
+      case MS_KEY_I64: return graph_bind_bytes() + ls_plan<int64_t>(n, o).bytes;
+    }
+    return 0;
   } catch (...) {
     return 0;
   }
@@ -372,7 +438,7 @@ ms_status ms_learned_grad(const uint32_t* d_sample, uint32_t S, int feature, con
   if (st != MS_OK) return st;
   LsModel* md = reinterpret_cast<LsModel*>(w);
   float* partial = reinterpret_cast<float*>(w + align_up(sizeof(LsModel), 256));
-  ls_setup_kernel<<<1, 64, 0, s>>>(md, feature == MS_FEATURE_LOG ? 1 : 0, 1, 0, 0);
+  ls_setup_kernel<<<1, 64, 0, s>>>(md, log_feature(feature, true), 1, 0, 0);
   ls_set_theta_kernel<<<1, 64, 0, s>>>(md, d_theta);
   ls_train_kernel<<<LS_TRAIN_G, LS_TRAIN_WG, 0, s>>>(d_sample, S, md, partial, 0, 1, 0.f, nullptr, nullptr, nullptr);
   ls_train_kernel<<<LS_TRAIN_G, LS_TRAIN_WG, 0, s>>>(d_sample, S, md, partial, 1, 1, 0.f, nullptr, d_out, nullptr);
@@ -392,7 +458,7 @@ ms_status ms_learned_train(const uint32_t* d_sample, uint32_t S, int feature, ui
   if (st != MS_OK) return st;
   LsModel* md = reinterpret_cast<LsModel*>(w);
   float* partial = reinterpret_cast<float*>(w + align_up(sizeof(LsModel), 256));
-  ls_setup_kernel<<<1, 64, 0, s>>>(md, feature == MS_FEATURE_LOG ? 1 : 0, 1, 0, 0);
+  ls_setup_kernel<<<1, 64, 0, s>>>(md, log_feature(feature, true), 1, 0, 0);
   if (d_theta0) ls_set_theta_kernel<<<1, 64, 0, s>>>(md, d_theta0);
   st = ls_train_enqueue(d_sample, S, md, partial, int(steps), learning_rate, d_loss_hist, d_theta0 == nullptr, s);
   if (st != MS_OK) return st;
@@ -412,7 +478,7 @@ ms_status ms_learned_table(const float* d_theta, const uint32_t* d_sample, uint3
   ms_status st = step_scratch(s, 0, &w);
   if (st != MS_OK) return st;
   LsModel* md = reinterpret_cast<LsModel*>(w);
-  ls_setup_kernel<<<1, 64, 0, s>>>(md, feature == MS_FEATURE_LOG ? 1 : 0, 1, 0, 0);
+  ls_setup_kernel<<<1, 64, 0, s>>>(md, log_feature(feature, true), 1, 0, 0);
   ls_set_theta_kernel<<<1, 64, 0, s>>>(md, d_theta);
   ls_compile_kernel<<<1, 64, 0, s>>>(md, 0, d_sample, S, nullptr);
   ls_get_table_kernel<<<1, 64, 0, s>>>(md, d_t, d_v, d_count);
@@ -434,7 +500,7 @@ ms_status ms_learned_bucket_ids(const uint32_t* d_keys, size_t n, const float* d
   if (st != MS_OK) return st;
   LsModel* md = reinterpret_cast<LsModel*>(w);
   const int cb = int(std::min<uint32_t>(log2_buckets, 10)), fb = int(log2_buckets) - cb;
-  ls_setup_kernel<<<1, 64, 0, s>>>(md, feature == MS_FEATURE_LOG ? 1 : 0, use_network ? 1 : 0, cb, fb);
+  ls_setup_kernel<<<1, 64, 0, s>>>(md, log_feature(feature, true), use_network ? 1 : 0, cb, fb);
   ls_set_theta_kernel<<<1, 64, 0, s>>>(md, d_theta);
   ls_compile_kernel<<<1, 64, 0, s>>>(md, 0, d_sample, S, nullptr);
   ls_bucket_ids_kernel<<<dim3(unsigned(ceil_div(n, 256))), 256, 0, s>>>(d_keys, n, md, d_out);

@@ -1,4 +1,4 @@
-// Learned-bucket sort of uint32 keys: device kernels.
+// Learned-bucket sort (32- and 64-bit keys): device kernels.
 //
 // The network is this library's small CDF model (the paper has none): a
 // two-layer ReLU MLP F(x) = b2 + sum_h w2_h relu(w1_h x + b1_h) of one input
@@ -44,7 +44,10 @@ constexpr int LS_TAB = 32;           // table capacity (>= LS_H + 2)
 constexpr int LS_TRAIN_G = 64;       // training workgroups
 constexpr int LS_TRAIN_WG = 256;     // training workgroup size
 constexpr int LS_WG = 512;           // histogram / scatter workgroup size
-constexpr int LS_CHK = 8192;         // keys per histogram / scatter chunk
+constexpr int LS_CHK = 8192;         // 32-bit keys per histogram / scatter chunk
+// keys per chunk for a key type: the LDS staging of a chunk stays 32 KB
+template <class K>
+__host__ __device__ constexpr int ls_chk() { return LS_CHK * 4 / int(sizeof(K)); }
 constexpr int LS_MAX_BINS = 1024;    // max coarse or fine bins per level
 #ifndef MS_LS_H1
 #define MS_LS_H1 4
@@ -60,6 +63,40 @@ __device__ __forceinline__ float ls_feature(uint32_t k, int log_feature) {
     return __int2float_rn(bits) * 0x1p-28f;
   }
   return __uint2float_rn(k) * 0x1p-32f;
+}
+
+// Order-preserving unsigned image of a key (signed types: sign bit flipped).
+template <class K>
+__device__ __forceinline__ auto ls_unsigned(K k) {
+  if constexpr (sizeof(K) == 4) {
+    return std::is_signed<K>::value ? uint32_t(k) ^ 0x80000000u : uint32_t(k);
+  } else {
+    return std::is_signed<K>::value ? uint64_t(k) ^ 0x8000000000000000ull : uint64_t(k);
+  }
+}
+
+// Feature of a key of any type.  uint32 keys: ls_feature of the key itself
+// (bit-identical to the CPU oracle's float32 computation).  Other types: the
+// same two forms applied to the offset d of the key's unsigned image from
+// off64 (a point just below the sample's smallest image; d = 0 below it):
+// linear fl32(d) * scale, log (bits(fl32(fl32(d) + 1)) - bits(1.0)) * 2^-29.  (The
+// raw image would not do for signed keys: small keys of either sign sit next
+// to 2^31 or 2^63, where a float32 has no resolution left.)  Both forms are
+// non-decreasing in the key.
+template <class K>
+__device__ __forceinline__ float ls_key_feature(K k, int log_feature, uint64_t off64, float scale64) {
+  if constexpr (std::is_same<K, uint32_t>::value) {
+    return ls_feature(k, log_feature);
+  } else {
+    const uint64_t u = ls_unsigned(k);
+    const uint64_t d = u > off64 ? u - off64 : 0ull;
+    const float fd = __ull2float_rn(d);
+    if (log_feature) {
+      const int bits = __float_as_int(__fadd_rn(fd, 1.0f)) - 0x3F800000;
+      return __int2float_rn(bits) * 0x1p-29f;
+    }
+    return __fmul_rn(fd, scale64);
+  }
 }
 
 // Model / table / decision record in device memory.
@@ -82,11 +119,37 @@ struct LsModel {
   uint64_t r_base;       // first kept position in r_keys
   uint32_t total_chunks; // level-2 chunks
   float loss0, loss_last;
+  uint64_t off64;        // keys other than uint32: feature offset (the sample's smallest unsigned image)
+  float scale64;         // keys other than uint32: linear feature scale
 };
 
+// Keys other than uint32: the feature's offset and scale from the sorted
+// sample (one thread).  The offset sits 1/64 of the sample's range below its
+// smallest key (or at 0), so that keys below the sample still get distinct
+// features; the scale is the power of two that maps offset .. the sample's
+// largest key into [0, 1].
+template <class K>
+__global__ void ls_feature_range_kernel(LsModel* md, const K* __restrict__ sample, uint32_t S) {
+  if (threadIdx.x != 0) return;
+  if constexpr (std::is_same<K, uint32_t>::value) {
+    md->off64 = 0;
+    md->scale64 = 1.f;
+  } else {
+    const uint64_t lo = ls_unsigned(sample[0]), hi = ls_unsigned(sample[S - 1]);
+    const uint64_t margin = (hi - lo) >> 6;
+    const uint64_t off = lo > margin ? lo - margin : 0ull;
+    const uint64_t r = hi - off;
+    int e = 0;
+    while (e < 64 && (r >> e) != 0) ++e;  // bit length of the range
+    md->off64 = off;
+    md->scale64 = __int_as_float((127 - e) << 23);  // 2^-e
+  }
+}
+
 // ------------------------------------------------------------ sampling
-__global__ __launch_bounds__(256) void ls_sample_kernel(const uint32_t* __restrict__ keys, uint64_t n, uint32_t S,
-                                                        uint64_t seed, uint32_t* __restrict__ out, Rebind rk) {
+template <class K>
+__global__ __launch_bounds__(256) void ls_sample_kernel(const K* __restrict__ keys, uint64_t n, uint32_t S,
+                                                        uint64_t seed, K* __restrict__ out, Rebind rk) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S) return;
   keys = rebind(keys, rk);
@@ -102,13 +165,14 @@ __global__ __launch_bounds__(256) void ls_sample_kernel(const uint32_t* __restri
 // One thread: knots at sample positions q_i = floor(i (S-1) / H), i = 0..H,
 // values (q_i + 0.5) / S; of a run of equal knots only the last is kept;
 // unit h is relu(x - k_h) with output weight = slope change at k_h.
-__global__ void ls_init_kernel(const uint32_t* __restrict__ sample, uint32_t S, LsModel* md) {
+template <class K>
+__global__ void ls_init_kernel(const K* __restrict__ sample, uint32_t S, LsModel* md) {
   if (threadIdx.x != 0) return;
   double k[LS_H + 1], y[LS_H + 1];
   int m = 0;
   for (int i = 0; i <= LS_H; ++i) {
     const uint32_t q = uint32_t((uint64_t(i) * (S - 1)) / LS_H);
-    const double kk = double(ls_feature(sample[q], md->log_feature));
+    const double kk = double(ls_key_feature(sample[q], md->log_feature, md->off64, md->scale64));
     const double yy = (double(q) + 0.5) / double(S);
     if (m > 0 && k[m - 1] == kk) {
       y[m - 1] = yy;  // keep the last of a run of equal knots
@@ -145,7 +209,8 @@ __global__ void ls_init_kernel(const uint32_t* __restrict__ sample, uint32_t S, 
 // (and squared-error sum) at theta_t to partial[t&1][blockIdx.x].
 // grad_out / loss_out (optional): the summed gradient + squared-error sum of
 // the previous launch.
-__global__ __launch_bounds__(LS_TRAIN_WG) void ls_train_kernel(const uint32_t* __restrict__ sample, uint32_t S,
+template <class K>
+__global__ __launch_bounds__(LS_TRAIN_WG) void ls_train_kernel(const K* __restrict__ sample, uint32_t S,
                                                                 LsModel* md, float* __restrict__ partial, int t,
                                                                 int T, float lr, float* __restrict__ loss_hist,
                                                                 float* __restrict__ grad_out, const int* gate) {
@@ -202,7 +267,7 @@ __global__ __launch_bounds__(LS_TRAIN_WG) void ls_train_kernel(const uint32_t* _
   for (int p = 0; p < LS_PS; ++p) acc[p] = 0.f;
   const float inv2 = 2.f / float(S);
   for (uint32_t i = blockIdx.x * LS_TRAIN_WG + tid; i < S; i += G * LS_TRAIN_WG) {
-    const float x = ls_feature(sample[i], md->log_feature);
+    const float x = ls_key_feature(sample[i], md->log_feature, md->off64, md->scale64);
     const float y = (float(i) + 0.5f) / float(S);
     float z[LS_H];
     float F = th[3 * LS_H];
@@ -247,14 +312,18 @@ __global__ __launch_bounds__(LS_TRAIN_WG) void ls_train_kernel(const uint32_t* _
 // One thread: the trained network restricted to the sample's feature range
 // [x_min, x_max]: x_min, the breakpoints strictly inside (sorted), x_max;
 // F there in double; running maximum clamped into [0.5/S, 1 - 0.5/S], ends
-// pinned to those values; FP32 table with segment slopes.
-__global__ void ls_compile_kernel(LsModel* md, int final_parity, const uint32_t* __restrict__ sample, uint32_t S,
+// pinned to those values; interior points that would leave a flat segment
+// (FP32 value not above the previous kept point's, or at the upper clamp)
+// are dropped, since a flat segment sends all its keys to one bucket; FP32
+// table with segment slopes.
+template <class K>
+__global__ void ls_compile_kernel(LsModel* md, int final_parity, const K* __restrict__ sample, uint32_t S,
                                   const int* gate) {
   if (gate && *gate == 0) return;
   if (threadIdx.x != 0) return;
   const float* th = md->theta[final_parity];
-  const double xmin = ls_feature(sample[0], md->log_feature);
-  const double xmax = ls_feature(sample[S - 1], md->log_feature);
+  const double xmin = ls_key_feature(sample[0], md->log_feature, md->off64, md->scale64);
+  const double xmax = ls_key_feature(sample[S - 1], md->log_feature, md->off64, md->scale64);
   double t[LS_H + 2];
   int nt = 0;
   for (int h = 0; h < LS_H; ++h) {
@@ -291,6 +360,16 @@ __global__ void ls_compile_kernel(LsModel* md, int final_parity, const uint32_t*
   }
   V[0] = lo;
   V[np - 1] = hi;
+  int m = 1;
+  for (int i = 1; i < np - 1; ++i)
+    if (float(V[i]) > float(V[m - 1]) && float(V[i]) < float(hi)) {
+      pts[m] = pts[i];
+      V[m] = V[i];
+      ++m;
+    }
+  pts[m] = pts[np - 1];
+  V[m] = V[np - 1];
+  np = m + 1;
   for (int i = 0; i < LS_TAB; ++i) {
     if (i < np) {
       md->tab_t[i] = float(pts[i]);
@@ -307,12 +386,15 @@ __global__ void ls_compile_kernel(LsModel* md, int final_parity, const uint32_t*
   md->tab_n = np;
 }
 
-// Table in LDS for the per-key bucket function.
+// Table in LDS for the per-key bucket function: points t, values v, slopes
+// s and caps c (c[j] = v[j + 1], and 1 for the last segment).
 struct LsTable {
-  float t[LS_TAB], v[LS_TAB], s[LS_TAB];
+  float t[LS_TAB], v[LS_TAB], s[LS_TAB], c[LS_TAB];
   int n, use_table, log_feature, fine_bits;
   float B;
   uint32_t nb;  // total buckets
+  uint64_t off64;
+  float scale64;
 };
 
 __device__ __forceinline__ void ls_load_table(const LsModel* md, LsTable* tb) {
@@ -321,6 +403,7 @@ __device__ __forceinline__ void ls_load_table(const LsModel* md, LsTable* tb) {
     tb->t[tid] = md->tab_t[tid];
     tb->v[tid] = md->tab_v[tid];
     tb->s[tid] = md->tab_s[tid];
+    tb->c[tid] = tid + 2 < md->tab_n ? md->tab_v[tid + 1] : 1.0f;
   }
   if (tid == 0) {
     tb->n = md->tab_n;
@@ -329,6 +412,8 @@ __device__ __forceinline__ void ls_load_table(const LsModel* md, LsTable* tb) {
     tb->fine_bits = md->fine_bits;
     tb->nb = md->nbins_c << md->fine_bits;
     tb->B = float(tb->nb);
+    tb->off64 = md->off64;
+    tb->scale64 = md->scale64;
   }
 }
 
@@ -336,8 +421,10 @@ __device__ __forceinline__ void ls_load_table(const LsModel* md, LsTable* tb) {
 // (every lane holds the same values), so that branches on them are uniform.
 struct LsUni {
   int n, use_table, log_feature, fine_bits;
-  float t0, tlast, B;
+  float B;
   uint32_t nb;
+  uint64_t off64;
+  float scale64;
 };
 
 __device__ __forceinline__ float uniform_f(float x) {
@@ -351,29 +438,29 @@ __device__ __forceinline__ LsUni ls_uni(const LsTable* tb) {
   u.use_table = __builtin_amdgcn_readfirstlane(tb->use_table);
   u.log_feature = __builtin_amdgcn_readfirstlane(tb->log_feature);
   u.fine_bits = __builtin_amdgcn_readfirstlane(tb->fine_bits);
-  u.t0 = uniform_f(tb->t[0]);
-  u.tlast = uniform_f(tb->t[u.n > 0 ? u.n - 1 : 0]);
   u.B = uniform_f(tb->B);
   u.nb = uint32_t(__builtin_amdgcn_readfirstlane(int(tb->nb)));
+  u.off64 = wave_uniform(tb->off64);
+  u.scale64 = uniform_f(tb->scale64);
   return u;
 }
 
 // Bucket id of a key: non-decreasing in the key.  Branch-free per lane: the
-// table search takes a fixed number of select steps.
-__device__ __forceinline__ uint32_t ls_bucket(const LsTable* tb, const LsUni& U, uint32_t key) {
-  const float x = ls_feature(key, U.log_feature);
+// table search takes a fixed number of select steps.  Keys beyond the
+// table's range continue its first or last segment (clipped to [0, 1]), so
+// the keys past the sample's extremes spread over the end buckets.
+template <class K>
+__device__ __forceinline__ uint32_t ls_bucket(const LsTable* tb, const LsUni& U, K key) {
+  const float x = ls_key_feature(key, U.log_feature, U.off64, U.scale64);
   float u;
   if (U.use_table) {
-    // clamp to the table's range (t0 <= tlast; med3 of three ordinary
-    // floats is the middle one)
-    const float xc = __builtin_amdgcn_fmed3f(x, U.t0, U.tlast);
-    int j = 0;  // largest j with t[j] <= xc, then at most n-2
+    int j = 0;  // largest j with t[j] <= x (0 below the range), at most n-2
 #pragma unroll
-    for (int step = LS_TAB / 2; step >= 1; step >>= 1) j = tb->t[j + step] <= xc ? j + step : j;
+    for (int step = LS_TAB / 2; step >= 1; step >>= 1) j = tb->t[j + step] <= x ? j + step : j;
     j = j < U.n - 2 ? j : U.n - 2;
-    // min(value, v[j+1]) then max(., 0): the middle of the three, since the
-    // table values are positive
-    u = __builtin_amdgcn_fmed3f(__fmaf_rn(tb->s[j], __fsub_rn(xc, tb->t[j]), tb->v[j]), 0.f, tb->v[j + 1]);
+    // min(value, cap) then max(., 0): the middle of the three, since the
+    // caps are positive
+    u = __builtin_amdgcn_fmed3f(__fmaf_rn(tb->s[j], __fsub_rn(x, tb->t[j]), tb->v[j]), 0.f, tb->c[j]);
   } else {
     u = fmaxf(x, 0.f);
   }
@@ -446,8 +533,14 @@ __global__ __launch_bounds__(256) void ls_clear_kernel(LsBins bn, uint32_t nb_c,
 // Level 1: coarse histogram of LS_H1 consecutive chunks per workgroup (one
 // flush of LDS counts into the global counters per LS_H1 chunks, which
 // keeps the 1024 global counters from serialising the whole launch).
-__global__ __launch_bounds__(LS_WG) void ls_hist1_kernel(const uint32_t* __restrict__ keys, uint64_t n,
-                                                         const LsModel* md, LsBins bn, Rebind rk) {
+// The input is nch chunks, all full but the last, of last_len keys; chunk
+// lengths come from these 32-bit counts rather than from a 64-bit
+// min(n - base, chunk), which this compiler has been seen to lower into a
+// select on a stale scalar condition code (every chunk then counted full).
+template <class K>
+__global__ __launch_bounds__(LS_WG) void ls_hist1_kernel(const K* __restrict__ keys, uint32_t nch,
+                                                         uint32_t last_len, const LsModel* md, LsBins bn,
+                                                         Rebind rk) {
   __shared__ LsTable tb;
   __shared__ uint32_t h[LS_MAX_BINS];
   keys = rebind(keys, rk);
@@ -456,41 +549,43 @@ __global__ __launch_bounds__(LS_WG) void ls_hist1_kernel(const uint32_t* __restr
   for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) h[i] = 0;
   __syncthreads();
   const LsUni U = ls_uni(&tb);
+  constexpr int CHK = ls_chk<K>();
   for (int c = 0; c < LS_H1; ++c) {
-    const uint64_t base = (uint64_t(blockIdx.x) * LS_H1 + c) * LS_CHK;
-    if (base >= n) break;  // workgroup-uniform
-    const uint32_t lim = n - base < uint64_t(LS_CHK) ? uint32_t(n - base) : uint32_t(LS_CHK);
-    const uint32_t* kb = keys + base;
+    const uint32_t ci = blockIdx.x * LS_H1 + c;  // chunk index
+    if (ci >= nch) break;  // workgroup-uniform
+    const uint32_t lim = ci + 1 < nch ? uint32_t(CHK) : last_len;
+    const K* kb = keys + uint64_t(ci) * CHK;
     // full chunks (all but the last) run without per-element bounds checks
     auto body = [&](auto fullc) {
       constexpr bool FULL = decltype(fullc)::value;
-      uint32_t kv[LS_CHK / LS_WG];
+      K kv[CHK / LS_WG];
 #pragma unroll
-      for (int r = 0; r < LS_CHK / LS_WG; ++r) {
+      for (int r = 0; r < CHK / LS_WG; ++r) {
         const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
-        kv[r] = (FULL || i < lim) ? kb[i] : 0u;
+        kv[r] = (FULL || i < lim) ? kb[i] : K(0);
       }
 #pragma unroll
-      for (int r = 0; r < LS_CHK / LS_WG; ++r) {
+      for (int r = 0; r < CHK / LS_WG; ++r) {
         const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
         if (FULL || i < lim) atomicAdd(&h[ls_bucket(&tb, U, kv[r]) >> U.fine_bits], 1u);
       }
     };
-    if (lim == uint32_t(LS_CHK)) body(std::true_type{}); else body(std::false_type{});
+    if (lim == uint32_t(CHK)) body(std::true_type{}); else body(std::false_type{});
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG)
     if (h[i]) atomicAdd(&bn.cnt_c[i], h[i]);
 }
 
-// Level 1 plan (one workgroup): coarse offsets, cursors, level-2 chunk map.
-__global__ __launch_bounds__(LS_WG) void ls_plan1_kernel(LsModel* md, LsBins bn) {
+// Level 1 plan (one workgroup): coarse offsets, cursors, level-2 chunk map
+// (chunks of `chk` keys).
+__global__ __launch_bounds__(LS_WG) void ls_plan1_kernel(LsModel* md, LsBins bn, uint32_t chk) {
   __shared__ uint32_t cnt[LS_MAX_BINS], off[LS_MAX_BINS], ch[LS_MAX_BINS], choff[LS_MAX_BINS], tmp[LS_WG];
   __shared__ uint32_t total, tch;
   const uint32_t nbc = md->nbins_c;
   for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) {
     cnt[i] = bn.cnt_c[i];
-    ch[i] = (cnt[i] + LS_CHK - 1) / LS_CHK;
+    ch[i] = (cnt[i] + chk - 1) / chk;
   }
   __syncthreads();
   ls_block_scan(cnt, off, nbc, tmp, &total);
@@ -515,37 +610,41 @@ __global__ __launch_bounds__(LS_WG) void ls_plan1_kernel(LsModel* md, LsBins bn)
 #define MS_LS_SBIN 1
 #endif
 constexpr int LS_SBIN = MS_LS_SBIN;
+template <class K>
 struct LsScatterLds {
   uint32_t cnt[LS_MAX_BINS], off[LS_MAX_BINS], gb[LS_MAX_BINS], tmp[LS_WG];
-  uint32_t stage[LS_CHK];
-  uint16_t sbin[LS_SBIN ? LS_CHK : 1];
+  K stage[ls_chk<K>()];
+  uint16_t sbin[LS_SBIN ? ls_chk<K>() : 1];
   uint32_t total;
 };
 
 // Level 1 scatter: chunk blockIdx.x of the input into coarse buckets.
-__global__ __launch_bounds__(LS_WG) void ls_scatter1_kernel(const uint32_t* __restrict__ keys, uint64_t n,
-                                                            const LsModel* md, LsBins bn, uint32_t* __restrict__ out,
-                                                            Rebind rkeys) {
+// (chunks as in ls_hist1_kernel)
+template <class K>
+__global__ __launch_bounds__(LS_WG) void ls_scatter1_kernel(const K* __restrict__ keys, uint32_t nch,
+                                                            uint32_t last_len, const LsModel* md, LsBins bn,
+                                                            K* __restrict__ out, Rebind rkeys) {
   __shared__ LsTable tb;
-  __shared__ LsScatterLds L;
+  __shared__ LsScatterLds<K> L;
   keys = rebind(keys, rkeys);
   ls_load_table(md, &tb);
   const uint32_t nbc = md->nbins_c;
   for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) L.cnt[i] = 0;
   __syncthreads();
   const LsUni U = ls_uni(&tb);
-  constexpr int R = LS_CHK / LS_WG;
-  const uint64_t base = uint64_t(blockIdx.x) * LS_CHK;
-  const uint32_t lim = n - base < uint64_t(LS_CHK) ? uint32_t(n - base) : uint32_t(LS_CHK);
-  const uint32_t* kb = keys + base;
-  uint32_t kv[R], bin[R], rk[R];
+  constexpr int CHK = ls_chk<K>();
+  constexpr int R = CHK / LS_WG;
+  const uint32_t lim = blockIdx.x + 1 < nch ? uint32_t(CHK) : last_len;
+  const K* kb = keys + uint64_t(blockIdx.x) * CHK;
+  K kv[R];
+  uint32_t bin[R], rk[R];
   // full chunks (all but the last) run without per-element bounds checks
   auto rank = [&](auto fullc) {
     constexpr bool FULL = decltype(fullc)::value;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
-      kv[r] = (FULL || i < lim) ? kb[i] : 0u;
+      kv[r] = (FULL || i < lim) ? kb[i] : K(0);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -568,7 +667,7 @@ __global__ __launch_bounds__(LS_WG) void ls_scatter1_kernel(const uint32_t* __re
       }
     }
   };
-  const bool full = lim == uint32_t(LS_CHK);
+  const bool full = lim == uint32_t(CHK);
   if (full) rank(std::true_type{}); else rank(std::false_type{});
   __syncthreads();
   ls_block_scan(L.cnt, L.off, nbc, L.tmp, &L.total);
@@ -577,15 +676,15 @@ __global__ __launch_bounds__(LS_WG) void ls_scatter1_kernel(const uint32_t* __re
   if (full) stage(std::true_type{}); else stage(std::false_type{});
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < L.total; i += LS_WG) {
-    const uint32_t x = L.stage[i];
+    const K x = L.stage[i];
     const uint32_t b = LS_SBIN ? uint32_t(L.sbin[i]) : ls_bucket(&tb, U, x) >> U.fine_bits;
     out[L.gb[b] + (i - L.off[b])] = x;
   }
 }
 
 // Level-2 chunk w -> coarse bucket c and key range [lo, hi).
-__device__ __forceinline__ bool ls_chunk(const LsModel* md, const LsBins& bn, uint32_t w, uint32_t* c,
-                                         uint32_t* lo, uint32_t* hi) {
+__device__ __forceinline__ bool ls_chunk(const LsModel* md, const LsBins& bn, uint32_t w, uint32_t chk,
+                                         uint32_t* c, uint32_t* lo, uint32_t* hi) {
   if (w >= md->total_chunks) return false;
   uint32_t a = 0, b = md->nbins_c;  // largest c with chunk_start[c] <= w
   while (b - a > 1) {
@@ -594,36 +693,38 @@ __device__ __forceinline__ bool ls_chunk(const LsModel* md, const LsBins& bn, ui
   }
   *c = a;
   const uint32_t j = w - bn.chunk_start[a];
-  const uint32_t s = bn.off_c[a] + j * LS_CHK, e = bn.off_c[a + 1];
+  const uint32_t s = bn.off_c[a] + j * chk, e = bn.off_c[a + 1];
   *lo = s;
-  *hi = s + LS_CHK < e ? s + LS_CHK : e;
+  *hi = s + chk < e ? s + chk : e;
   return true;
 }
 
 // Level 2 histogram: fine-bucket counts of one chunk of a coarse bucket.
-__global__ __launch_bounds__(LS_WG) void ls_hist2_kernel(const uint32_t* __restrict__ keys, const LsModel* md,
+template <class K>
+__global__ __launch_bounds__(LS_WG) void ls_hist2_kernel(const K* __restrict__ keys, const LsModel* md,
                                                          LsBins bn) {
   __shared__ LsTable tb;
   __shared__ uint32_t h[LS_MAX_BINS];
+  constexpr int CHK = ls_chk<K>();
   uint32_t c, lo, hi;
-  if (!ls_chunk(md, bn, blockIdx.x, &c, &lo, &hi)) return;
+  if (!ls_chunk(md, bn, blockIdx.x, CHK, &c, &lo, &hi)) return;
   ls_load_table(md, &tb);
   const uint32_t nbf = md->nbins_f;
   for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG) h[i] = 0;
   __syncthreads();
   const LsUni U = ls_uni(&tb);
-  constexpr int R = LS_CHK / LS_WG;
+  constexpr int R = CHK / LS_WG;
   const uint32_t lim = hi - lo;
-  const uint32_t* kb = keys + lo;
+  const K* kb = keys + lo;
   const uint32_t fmask = nbf - 1;
   // full chunks run without per-element bounds checks
   auto body = [&](auto fullc) {
     constexpr bool FULL = decltype(fullc)::value;
-    uint32_t kv[R];
+    K kv[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
-      kv[r] = (FULL || i < lim) ? kb[i] : 0u;
+      kv[r] = (FULL || i < lim) ? kb[i] : K(0);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -631,7 +732,7 @@ __global__ __launch_bounds__(LS_WG) void ls_hist2_kernel(const uint32_t* __restr
       if (FULL || i < lim) atomicAdd(&h[ls_bucket(&tb, U, kv[r]) & fmask], 1u);
     }
   };
-  if (lim == uint32_t(LS_CHK)) body(std::true_type{}); else body(std::false_type{});
+  if (lim == uint32_t(CHK)) body(std::true_type{}); else body(std::false_type{});
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG)
     if (h[i]) atomicAdd(&bn.cnt_f[(c << U.fine_bits) | i], h[i]);
@@ -665,9 +766,9 @@ __global__ __launch_bounds__(LS_WG) void ls_totals_kernel(const LsModel* md, LsB
 
 // Decision (one workgroup): kept / spill bases, the order check across coarse
 // buckets, fallback and repair flags, where the kept buckets live.
+template <class K>
 __global__ __launch_bounds__(LS_WG) void ls_plan2_kernel(LsModel* md, LsBins bn, uint64_t n, uint64_t spill_limit,
-                                                         int force_fallback, uint32_t* d_keys, uint32_t* xr,
-                                                         Rebind rk) {
+                                                         int force_fallback, K* d_keys, K* xr, Rebind rk) {
   __shared__ uint32_t k[LS_MAX_BINS], sp[LS_MAX_BINS], kb[LS_MAX_BINS], sb[LS_MAX_BINS], tmp[LS_WG];
   __shared__ uint32_t ktot, stot;
   d_keys = rebind(d_keys, rk);
@@ -733,32 +834,35 @@ __global__ __launch_bounds__(LS_WG) void ls_offsets_kernel(const LsModel* md, Ls
 
 // Level 2 scatter: keys of a coarse chunk into their fine buckets, kept
 // buckets into the kept array, spilled ones into the spill area.
-__global__ __launch_bounds__(LS_WG) void ls_scatter2_kernel(const uint32_t* __restrict__ keys, const LsModel* md,
-                                                            LsBins bn, uint32_t capacity, uint32_t* xr) {
+template <class K>
+__global__ __launch_bounds__(LS_WG) void ls_scatter2_kernel(const K* __restrict__ keys, const LsModel* md,
+                                                            LsBins bn, uint32_t capacity, K* xr) {
   __shared__ LsTable tb;
-  __shared__ LsScatterLds L;
+  __shared__ LsScatterLds<K> L;
   __shared__ uint8_t kept[LS_MAX_BINS];
   if (md->do_learned == 0) return;
+  constexpr int CHK = ls_chk<K>();
   uint32_t c, lo, hi;
-  if (!ls_chunk(md, bn, blockIdx.x, &c, &lo, &hi)) return;
+  if (!ls_chunk(md, bn, blockIdx.x, CHK, &c, &lo, &hi)) return;
   ls_load_table(md, &tb);
   const uint32_t nbf = md->nbins_f;
   const uint32_t b0 = c << md->fine_bits;
   for (uint32_t i = threadIdx.x; i < nbf; i += LS_WG) L.cnt[i] = 0;
   __syncthreads();
   const LsUni U = ls_uni(&tb);
-  constexpr int R = LS_CHK / LS_WG;
+  constexpr int R = CHK / LS_WG;
   const uint32_t fmask = nbf - 1;
   const uint32_t lim = hi - lo;
-  const uint32_t* kb = keys + lo;
-  uint32_t kv[R], bin[R], rk[R];
+  const K* kb = keys + lo;
+  K kv[R];
+  uint32_t bin[R], rk[R];
   // full chunks run without per-element bounds checks
   auto rank = [&](auto fullc) {
     constexpr bool FULL = decltype(fullc)::value;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
-      kv[r] = (FULL || i < lim) ? kb[i] : 0u;
+      kv[r] = (FULL || i < lim) ? kb[i] : K(0);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -781,7 +885,7 @@ __global__ __launch_bounds__(LS_WG) void ls_scatter2_kernel(const uint32_t* __re
       }
     }
   };
-  const bool full = lim == uint32_t(LS_CHK);
+  const bool full = lim == uint32_t(CHK);
   if (full) rank(std::true_type{}); else rank(std::false_type{});
   __syncthreads();
   ls_block_scan(L.cnt, L.off, nbf, L.tmp, &L.total);
@@ -792,11 +896,11 @@ __global__ __launch_bounds__(LS_WG) void ls_scatter2_kernel(const uint32_t* __re
     }
   if (full) stage(std::true_type{}); else stage(std::false_type{});
   __syncthreads();
-  uint32_t* rk_arr = global_ptr<uint32_t>(&md->r_keys);
+  K* rk_arr = global_ptr<K>(&md->r_keys);
   for (uint32_t i = threadIdx.x; i < L.total; i += LS_WG) {
-    const uint32_t x = L.stage[i];
+    const K x = L.stage[i];
     const uint32_t b = LS_SBIN ? uint32_t(L.sbin[i]) : (ls_bucket(&tb, U, x) & fmask);
-    uint32_t* dst = kept[b] ? rk_arr : xr;
+    K* dst = kept[b] ? rk_arr : xr;
     dst[L.gb[b] + (i - L.off[b])] = x;
   }
 }
@@ -806,13 +910,14 @@ __global__ __launch_bounds__(LS_WG) void ls_scatter2_kernel(const uint32_t* __re
 // compares the key before the bucket's first position with its first key;
 // a failure sends the keys (a permutation of the input) to the plain merge
 // sort.
+template <class K>
 __global__ __launch_bounds__(256) void ls_check_kernel(LsModel* md, LsBins bn, uint64_t nb) {
   if (md->do_learned == 0) return;
   const uint64_t b = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (b >= nb) return;
   const int64_t lo = bn.seg_off[b], hi = bn.seg_off[b + 1];
   if (hi <= lo || uint64_t(lo) <= md->r_base) return;
-  const uint32_t* rk = global_ptr<const uint32_t>(&md->r_keys);
+  const K* rk = global_ptr<const K>(&md->r_keys);
   if (rk[lo] < rk[lo - 1]) {
     md->misordered = 1;
     md->fallback = 1;

@@ -207,8 +207,12 @@ ms_status merge_two_runs(const K* src, K* dst, uint64_t n, DevCtl ctl, int64_t* 
 }
 MS_DEFINE_DEV_ERRORS(dev_errors_plain)
 
-template ms_status merge_two_runs<uint32_t, NoVal>(const uint32_t*, uint32_t*, uint64_t, DevCtl, int64_t*, hipStream_t,
-                                                   uint64_t);
+#define MS_MERGE2_INSTANTIATE(K) \
+  template ms_status merge_two_runs<K, NoVal>(const K*, K*, uint64_t, DevCtl, int64_t*, hipStream_t, uint64_t);
+MS_MERGE2_INSTANTIATE(uint32_t)
+MS_MERGE2_INSTANTIATE(int32_t)
+MS_MERGE2_INSTANTIATE(uint64_t)
+MS_MERGE2_INSTANTIATE(int64_t)
 
 #define MS_INSTANTIATE(K, V)                                                                  \
   template ms_status plain_sort<K, V>(K*, V*, uint64_t, DevCtl, hipStream_t, void*, uint64_t); \

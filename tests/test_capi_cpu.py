@@ -146,3 +146,8 @@ def test_temp_bytes_of_every_form():
     # the learned scratch holds two n-key arrays (bucketed copy and spill) at least
     assert lrn[2] >= 8 * (1 << 29)
     assert msort.ms_temp_bytes_learned(1 << 20, bucket_capacity=1000) == 0
+    # 64-bit keys: twice the key bytes; an unknown key type gets 0
+    b64 = msort.ms_temp_bytes_learned(1 << 24, msort.MS_KEY_I64)
+    assert b64 > msort.ms_temp_bytes_learned(1 << 24, msort.MS_KEY_U32) > 0
+    assert b64 >= 16 * (1 << 24)
+    assert msort.ms_temp_bytes_learned(1 << 24, 7) == 0

@@ -106,11 +106,15 @@ def test_pl_table_exact_for_monotone_networks_and_monotone_always():
                                    F[inner][(xs[inner] > tab[0][1]) & (xs[inner] < tab[0][-2])],
                                    rtol=1e-12, atol=1e-12)
         assert tab[1][0] == lo and tab[1][-1] == hi
-        # arbitrary network: non-decreasing, inside [lo, hi], running max at interior points
+        # arbitrary network: non-decreasing, inside [lo, hi] on the range and
+        # inside [0, 1] beyond it, running max at interior points
         th2 = rng.normal(scale=2.0, size=3 * H + 1)
         t, V = mlp.pl_table(th2, H, x_min, x_max, S)
-        ev = mlp.pl_eval((t, V), np.linspace(-0.5, 1.5, 40001))
-        assert (np.diff(ev) >= 0).all() and ev.min() >= lo and ev.max() <= hi
+        wide = np.linspace(-0.5, 1.5, 40001)
+        ev = mlp.pl_eval((t, V), wide)
+        assert (np.diff(ev) >= 0).all() and ev.min() >= 0 and ev.max() <= 1
+        inside = (wide >= x_min) & (wide <= x_max)
+        assert ev[inside].min() >= lo and ev[inside].max() <= hi
         dense = np.linspace(x_min, x_max, 200001)
         runmax = np.clip(np.maximum.accumulate(mlp.forward(th2, dense, H)), lo, hi)
         np.testing.assert_allclose(V[1:-1], np.interp(t[1:-1], dense, runmax), atol=1e-3 * (1 + np.abs(V).max()))
@@ -125,6 +129,48 @@ def test_pl_table_ends_spread_the_tails():
     xs = np.linspace(0.5, 1.0, 1001)                     # F >= 1 on all of these
     b = mlp.bucket_ids(mlp.pl_table(th, H, x_min, x_max, S), xs, 1024)
     assert np.unique(b).size > 500
+
+
+def test_pl_table_has_no_flat_segment():
+    """A network that reaches the upper clamp at an interior breakpoint, or
+    is flat between two, would leave a flat segment holding every key of its
+    x range in one bucket; those points are dropped and every segment of the
+    table rises."""
+    H = 3
+    # F(x) = 4 relu(x - 0.1) - 4 relu(x - 0.3) + 2 relu(x - 0.6): rises on
+    # [0.1, 0.3], flat on [0.3, 0.6], rises past 1 by x = 0.9
+    th = np.array([1.0, 1.0, 1.0, -0.1, -0.3, -0.6, 4.0, -4.0, 2.0, 0.0])
+    S = 1 << 10
+    t, V = mlp.pl_table(th, H, 0.0, 1.0, S)
+    assert t[0] == 0.0 and t[-1] == 1.0
+    assert (np.diff(V) > 0).all(), (t, V)
+    assert 0.6 not in t.tolist()     # flat after 0.3: dropped
+    # keys spread over [0.3, 1.0] instead of piling up at one value
+    xs = np.linspace(0.31, 0.99, 1000)
+    assert np.unique(mlp.bucket_ids((t, V), xs, 1 << 12)).size > 500
+
+
+def test_pl_eval_continues_the_end_segments():
+    """Beyond the sample's extremes the first and last segments continue
+    with their slopes, clipped to [0, 1]: for uniform keys (F(x) = x on
+    [0.25, 0.75]) a key above the range lands where the line puts it, and
+    the keys beyond the ends spread over as many buckets as keys inside
+    would, instead of piling into the end buckets."""
+    S = 1000
+    t = np.array([0.25, 0.5, 0.75])
+    V = np.array([0.5 / S, 0.5, 1 - 0.5 / S])
+    s_hi = (V[2] - V[1]) / 0.25
+    s_lo = (V[1] - V[0]) / 0.25
+    xs = np.array([0.0, 0.2499, 0.7501, 0.76, 2.0])
+    got = mlp.pl_eval((t, V), xs)
+    want = [max(0.0, V[0] - s_lo * 0.25), V[0] - s_lo * 0.0001, V[2] + s_hi * 0.0001,
+            min(1.0, V[2] + s_hi * 0.01), 1.0]
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-15)
+    # 64 keys evenly past the top end, 0.5 / S of rank: with B = 64 S buckets
+    # they fill B / (2 S) = 32 buckets, not one
+    B = 64 * S
+    top = 0.75 + (np.arange(64) + 0.5) / 64 * (0.5 / S) / s_hi
+    assert np.unique(mlp.bucket_ids((t, V), top, B)).size == 32
 
 
 def test_feature_values_and_monotonicity():
