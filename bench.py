@@ -234,46 +234,50 @@ def plain_form(name, K, W, dev, events=True):
 
 
 LEARNED_STAGES = {
-    # profiler class: (kernels, algorithmic bytes per key processed)
-    "learned_hist": ("ls_hist1_kernel", 4),       # read every key
-    "learned_scatter": ("ls_scatter1_kernel", 8),  # read and write every key
-    "learned_hist2": ("ls_hist2_kernel", 4),
-    "learned_scatter2": ("ls_scatter2_kernel", 8),
-    "bucket_sort": ("seg_init/classify/owner + seg_small_kernel per class", 8),  # kept keys, read + write
+    # profiler class: (kernels, algorithmic key transfers per key processed)
+    "learned_hist": ("ls_hist1_kernel", 1),       # read every key
+    "learned_scatter": ("ls_scatter1_kernel", 2),  # read and write every key
+    "learned_hist2": ("ls_hist2_kernel", 1),
+    "learned_scatter2": ("ls_scatter2_kernel", 2),
+    "bucket_sort": ("seg_init/classify/owner + seg_small_kernel per class", 2),  # kept keys, read + write
 }
 
 
-def learned_form(K, W, dev, pristine, use_graph):
-    """K timed learned-bucket sorts of fresh copies of the lognormal mixture."""
+def learned_form(K, W, dev, pristine, use_graph, workload="lognormal_u32_2p29"):
+    """K timed learned-bucket sorts of fresh copies of `pristine` (the
+    workload's keys; any of the four key types)."""
     import torch
     import paper_2211_16479_amd as msort
     n = pristine.numel()
+    kb = pristine.element_size()
+    kt = WORKLOADS[workload][4]
     bufs = [pristine.clone() for _ in range(K + W)]
     torch.cuda.synchronize()
 
     def step(i):
-        msort.ms_sort_ex(bufs[i], algo=msort.MS_ALGO_LEARNED_BUCKET, stats=False, use_graph=1 if use_graph else 0)
+        msort.ms_sort_ex(bufs[i], key_type=kt, algo=msort.MS_ALGO_LEARNED_BUCKET, stats=False,
+                         use_graph=1 if use_graph else 0)
 
     # only the stages priced below are bracketed by events (the training
     # steps and the small kernels would add an event pair per launch)
     ms, kernels = timed_steps(step, K, W, events=not use_graph, classes=list(LEARNED_STAGES))
     # device-side statistics of one more sort of the same input (untimed)
     extra = pristine.clone()
-    _, st = msort.ms_sort_ex(extra, algo=msort.MS_ALGO_LEARNED_BUCKET, use_graph=1 if use_graph else 0)
+    _, st = msort.ms_sort_ex(extra, key_type=kt, algo=msort.MS_ALGO_LEARNED_BUCKET, use_graph=1 if use_graph else 0)
     torch.cuda.synchronize()
     kept = n - int(st["spilled"]) if not st["fallback_taken"] else 0
     stages = {}
-    for cls, (kname, bpk) in LEARNED_STAGES.items():
+    for cls, (kname, transfers) in LEARNED_STAGES.items():
         if cls in kernels:
             keys = kept if cls == "bucket_sort" else n
-            stages[cls] = hbm_entry(kname, bpk * keys, kernels[cls]["avg_us"])
+            stages[cls] = hbm_entry(kname, transfers * kb * keys, kernels[cls]["avg_us"])
             stages[cls]["ms_per_step"] = kernels[cls]["ms_per_step"]
     dom = max(stages, key=lambda c: stages[c]["ms_per_step"], default=None)
     roof = None
     if dom:
         roof = dict(stages[dom])
         roof.pop("ms_per_step")
-        roof["traffic"] = profiled_traffic("lognormal_u32_2p29", roof["kernel"].split(" ")[0])
+        roof["traffic"] = profiled_traffic(workload, roof["kernel"].split(" ")[0])
     out = {"ms_per_step": round(ms, 4), "Gkeys_s": round(n / (ms * 1e-3) / 1e9, 3), "graph_replay": bool(use_graph),
            "learned_stats": {k: (round(v, 8) if isinstance(v, float) else v) for k, v in st.items()},
            "kernels": kernels, "stages": stages, "dominant": dom}
@@ -404,8 +408,18 @@ def main():
         return bench_segmented(args, dev)
 
     if args.workload != "lognormal_u32_2p29":
-        # a plain workload on its own
-        res, pk, pv, _ = plain_form(args.workload, K, W, dev)
+        # a plain workload on its own (the normal int64 keys also by the
+        # learned-bucket form beside it, with a byte comparison)
+        res, pk, pv, plain_out = plain_form(args.workload, K, W, dev)
+        lrn = None
+        if args.workload == "normal_i64_2p28":
+            plain_out = plain_out.clone()
+            lres, _, lout, lextra = learned_form(K, W, dev, pk, args.learned_graph, args.workload)
+            lrn = dict(lres, speedup_vs_plain=round(res["ms_per_step"] / lres["ms_per_step"], 3),
+                       outputs_identical=bool(torch.equal(lout, plain_out) and torch.equal(lextra, plain_out)))
+            del lout, lextra
+        del plain_out
+        torch.cuda.empty_cache()
         cpu = None if args.no_cpu_baseline else cpu_baselines(args.workload, pk, pv)
         print(json.dumps({
             "metric": METRIC, "value": res["Gkeys_s"], "unit": "Gkeys/s", "n_gpus": 1, "steps": K, "warmup": W,
@@ -414,13 +428,13 @@ def main():
             "config": {"workload": desc, "n": n, "key_bytes": kb, "value_bytes": vb,
                        "input_sha256": res["input_sha256"], "plan": res["plan"]},
             "roofline": res["roofline"], "cpu_baseline": cpu, "fused_pass": res["fused_pass"],
-            "kernels": res["kernels"], "whole_sort_hbm_GBs": res["whole_sort_hbm_GBs"]}))
+            "kernels": res["kernels"], "whole_sort_hbm_GBs": res["whole_sort_hbm_GBs"], "learned": lrn}))
         return
 
     # headline: the learned-bucket form on the lognormal mixture, plain beside it
     plain, pristine, _, plain_out = plain_form(args.workload, K, W, dev)
     plain_out = plain_out.clone()
-    learned, roof, learned_out, extra_out = learned_form(K, W, dev, pristine, args.learned_graph)
+    learned, roof, learned_out, extra_out = learned_form(K, W, dev, pristine, args.learned_graph, args.workload)
     identical = bool(torch.equal(learned_out.view(torch.int32), plain_out.view(torch.int32))) and \
         bool(torch.equal(extra_out.view(torch.int32), plain_out.view(torch.int32)))
     del learned_out, extra_out, plain_out
