@@ -259,6 +259,28 @@ ms_status ms_sort_ex(void* d_keys, size_t n, ms_key_type kt, const ms_options* o
 size_t ms_temp_bytes_learned(size_t n, ms_key_type kt, const ms_options* opt);
 
 /*
+ * ms_sort_pairs_ex -- ms_sort_pairs with a choice of algorithm (stable, as
+ * ms_sort_pairs).  MS_ALGO_LEARNED_BUCKET (32-bit keys, values of 4 or 8
+ * bytes, n >= 4 * 2^sample_log2 with the 64-bit keys' default 2^18 when 0,
+ * n < 2^32; else MS_ERR_UNSUPPORTED): each key and its input position are
+ * packed into one 64-bit key (the key's order-preserving unsigned image
+ * above, the position below), the packed keys are sorted by the learned
+ * form for 64-bit keys (options as for ms_sort_ex, their 64-bit defaults;
+ * MS_FEATURE_AUTO: log for uint32 keys, linear for int32),
+ * then the keys are unpacked and the values gathered by position.  Packed
+ * keys are distinct, so equal keys keep their input order.  Heavy ties
+ * (one key over a bucket's capacity) spill or fall back to the plain sort,
+ * exact either way.  MS_ALGO_AUTO and MS_ALGO_MERGE_PATH run ms_sort_pairs.
+ * d_stats as for ms_sort_ex.  The cached graph (use_graph = 1) is keyed by
+ * key type, value width, n, whether d_stats is NULL and the options, and
+ * owns ms_temp_bytes_learned_pairs(n, kt, val_bytes, opt) bytes of scratch
+ * (0 for unsupported arguments).
+ */
+ms_status ms_sort_pairs_ex(void* d_keys, void* d_vals, size_t n, ms_key_type kt, size_t val_bytes,
+                           const ms_options* opt, ms_stats* d_stats, void* stream);
+size_t ms_temp_bytes_learned_pairs(size_t n, ms_key_type kt, size_t val_bytes, const ms_options* opt);
+
+/*
  * Steps of the learned form on uint32 keys, for tests and inspection (all device pointers;
  * parameters theta are 49 floats laid out [w1 x16, b1 x16, w2 x16, b2]):
  *   ms_learned_grad   : at theta, over the sorted sample (S keys, target of

@@ -75,6 +75,8 @@ def _declare(lib):
         "ms_temp_bytes": (sz, [sz, i32, sz]),
         "ms_temp_bytes_segmented": (sz, [sz, sz, i32, sz]),
         "ms_temp_bytes_learned": (sz, [sz, c.c_int, c.POINTER(MsOptions)]),
+        "ms_sort_pairs_ex": (c.c_int, [vp, vp, sz, c.c_int, sz, c.POINTER(MsOptions), vp, vp]),
+        "ms_temp_bytes_learned_pairs": (sz, [sz, c.c_int, sz, c.POINTER(MsOptions)]),
         "ms_graph_captures": (c.c_uint64, []),
         "ms_device_errors": (i32, [c.POINTER(c.c_uint32)]),
         "ms_plan_query": (i32, [sz, i32, sz, c.POINTER(i32), c.POINTER(i32), c.POINTER(i32),
@@ -283,6 +285,40 @@ def ms_sort_ex(keys: torch.Tensor, key_type=None, stats: bool = True, **options)
     torch.cuda.current_stream(keys.device).synchronize()
     raw = MsStats.from_buffer_copy(bytes(st.cpu().numpy()))
     return keys, {f: getattr(raw, f) for f, _ in MsStats._fields_}
+
+
+def ms_sort_pairs_ex(keys: torch.Tensor, vals: torch.Tensor, key_type=None, stats: bool = True, **options):
+    """ms_sort_pairs with an algorithm choice (stable); keyword arguments set
+    ms_options fields.  Returns (keys, vals, stats dict or None)."""
+    _dev(keys, "keys")
+    _dev(vals, "vals")
+    if vals.numel() != keys.numel():
+        raise ValueError("keys and vals differ in length")
+    _ensure_tuning()
+    o = ms_options_default()
+    for k, v in options.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    st = torch.zeros(ctypes.sizeof(MsStats), dtype=torch.uint8, device=keys.device) if stats else None
+    _check(lib().ms_sort_pairs_ex(ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()),
+                                  keys.numel(), _key_type(keys, key_type), vals.element_size(), ctypes.byref(o),
+                                  None if st is None else ctypes.c_void_p(st.data_ptr()), _stream(keys)),
+           "ms_sort_pairs_ex")
+    if st is None:
+        return keys, vals, None
+    torch.cuda.current_stream(keys.device).synchronize()
+    raw = MsStats.from_buffer_copy(bytes(st.cpu().numpy()))
+    return keys, vals, {f: getattr(raw, f) for f, _ in MsStats._fields_}
+
+
+def ms_temp_bytes_learned_pairs(n: int, key_type: int = MS_KEY_U32, val_bytes: int = 4, **options) -> int:
+    o = ms_options_default()
+    for k, v in options.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return int(lib().ms_temp_bytes_learned_pairs(n, key_type, val_bytes, ctypes.byref(o)))
 
 
 def _f32(t: torch.Tensor, n: int, name: str):

@@ -184,11 +184,12 @@ static ms_status ls_train_enqueue(const K* sample, uint32_t S, LsModel* md, floa
   return e == hipSuccess ? MS_OK : hip_fail(e, "training launch");
 }
 
-// io: if non-null, the caller's buffers of this launch are read from io[0]
-// (keys) and io[1] (stats) at run time (graph replays on new buffers).
+// io_keys / io_stats: if non-null, the caller's key and stats buffers of
+// this launch are read from *io_keys and *io_stats at run time (graph
+// replays on new buffers).
 template <class K>
 static ms_status learned_enqueue(K* keys, uint64_t n, const ms_options& o, ms_stats* d_stats, void* ws,
-                                 void* const* io, hipStream_t s) {
+                                 void* const* io_keys, void* const* io_stats, hipStream_t s) {
   const LsPlan P = ls_plan<K>(n, o);
   char* w = static_cast<char*>(ws);
   LsModel* md = reinterpret_cast<LsModel*>(w + P.md);
@@ -200,8 +201,8 @@ static ms_status learned_enqueue(K* keys, uint64_t n, const ms_options& o, ms_st
   int64_t* part = reinterpret_cast<int64_t*>(w + P.part);
   const LsBins bn = ls_bins(w, P);
   const DevCtl none{nullptr, nullptr, nullptr};
-  const Rebind rk{keys, io ? &io[0] : nullptr};
-  const Rebind rs{d_stats, io ? &io[1] : nullptr};
+  const Rebind rk{keys, io_keys};
+  const Rebind rs{d_stats, io_stats};
 
   ls_setup_kernel<<<1, 64, 0, s>>>(md, log_feature(o.feature, std::is_same<K, uint32_t>::value), o.use_network ? 1 : 0, P.cb, P.fb);
   // sample, ranked by the plain merge sort
@@ -292,7 +293,7 @@ static ms_status learned_sort(K* keys, ms_key_type kt, uint64_t n, const ms_opti
     void* ws = nullptr;
     ms_status st = get_workspace(s, P.bytes, &ws);
     if (st != MS_OK) return st;
-    return learned_enqueue(keys, n, o, d_stats, ws, nullptr, s);
+    return learned_enqueue(keys, n, o, d_stats, ws, nullptr, nullptr, s);
   }
   uint32_t lr_bits, th_bits;
   std::memcpy(&lr_bits, &o.learning_rate, 4);
@@ -305,7 +306,106 @@ static ms_status learned_sort(K* keys, ms_key_type kt, uint64_t n, const ms_opti
   return cached_graph_launch(
       key, P.bytes, {static_cast<void*>(keys), d_stats},
       [&](void* ws, void* const* io, hipStream_t cs, SegFork) {
-        return learned_enqueue(keys, n, o, d_stats, ws, io, cs);
+        return learned_enqueue(keys, n, o, d_stats, ws, &io[0], &io[1], cs);
+      },
+      s);
+}
+
+// ------------------------------------------------------------ pairs
+// Learned pairs: each 32-bit key and its input position are packed into one
+// 64-bit key (the key's unsigned image above, the position below), so every
+// packed key is distinct and equal keys order by position: the learned sort
+// of the packed keys is the stable order.  Then the keys are unpacked and
+// the values gathered by position from a copy.
+template <class K32>
+__global__ __launch_bounds__(256) void lp_pack_kernel(const K32* __restrict__ keys, uint64_t n,
+                                                      uint64_t* __restrict__ kp, Rebind rk) {
+  keys = rebind(keys, rk);
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    kp[i] = (uint64_t(ls_unsigned(keys[i])) << 32) | i;
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void lp_copy_kernel(const V* __restrict__ vals, uint64_t n, V* __restrict__ out,
+                                                      Rebind rv) {
+  vals = rebind(vals, rv);
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = vals[i];
+}
+
+template <class K32, class V>
+__global__ __launch_bounds__(256) void lp_unpack_kernel(const uint64_t* __restrict__ kp, const V* __restrict__ vcopy,
+                                                        uint64_t n, K32* __restrict__ keys, V* __restrict__ vals,
+                                                        Rebind rk, Rebind rv) {
+  keys = rebind(keys, rk);
+  vals = rebind(vals, rv);
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint64_t p = kp[i];
+    const uint32_t u = uint32_t(p >> 32);
+    keys[i] = K32(std::is_signed<K32>::value ? u ^ 0x80000000u : u);
+    vals[i] = vcopy[uint32_t(p)];
+  }
+}
+
+// Scratch of one learned pairs sort: packed keys, value copy, then the
+// 64-bit learned sort's own scratch.
+struct LpPlan {
+  size_t kp, vcopy, core, bytes;
+};
+
+static LpPlan lp_plan(uint64_t n, size_t vb, const ms_options& o) {
+  LpPlan L{};
+  L.kp = 0;
+  L.vcopy = align_up(sizeof(uint64_t) * n, 256);
+  L.core = align_up(L.vcopy + vb * n, 256);
+  L.bytes = L.core + ls_plan<uint64_t>(n, o).bytes;
+  return L;
+}
+
+// io_keys / io_vals / io_stats as for learned_enqueue.
+template <class K32, class V>
+static ms_status learned_pairs_enqueue(K32* keys, V* vals, uint64_t n, const ms_options& o, ms_stats* d_stats,
+                                       void* ws, void* const* io_keys, void* const* io_vals,
+                                       void* const* io_stats, hipStream_t s) {
+  const LpPlan L = lp_plan(n, sizeof(V), o);
+  char* w = static_cast<char*>(ws);
+  uint64_t* kp = reinterpret_cast<uint64_t*>(w + L.kp);
+  V* vcopy = reinterpret_cast<V*>(w + L.vcopy);
+  const unsigned grid = unsigned(std::min<uint64_t>(ceil_div(n, 256), uint64_t(device_cu_count()) * 16));
+  lp_pack_kernel<K32><<<grid, 256, 0, s>>>(keys, n, kp, Rebind{keys, io_keys});
+  lp_copy_kernel<V><<<grid, 256, 0, s>>>(vals, n, vcopy, Rebind{vals, io_vals});
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "pairs pack launch");
+  ms_status st = learned_enqueue<uint64_t>(kp, n, o, d_stats, w + L.core, nullptr, io_stats, s);
+  if (st != MS_OK) return st;
+  lp_unpack_kernel<K32, V><<<grid, 256, 0, s>>>(kp, vcopy, n, keys, vals, Rebind{keys, io_keys},
+                                                Rebind{vals, io_vals});
+  e = hipGetLastError();
+  return e == hipSuccess ? MS_OK : hip_fail(e, "pairs unpack launch");
+}
+
+template <class K32, class V>
+static ms_status learned_pairs(K32* keys, V* vals, ms_key_type kt, uint64_t n, const ms_options& o,
+                               ms_stats* d_stats, hipStream_t s) {
+  const LpPlan L = lp_plan(n, sizeof(V), o);
+  if (!o.use_graph) {
+    void* ws = nullptr;
+    ms_status st = get_workspace(s, L.bytes, &ws);
+    if (st != MS_OK) return st;
+    return learned_pairs_enqueue(keys, vals, n, o, d_stats, ws, nullptr, nullptr, nullptr, s);
+  }
+  uint32_t lr_bits, th_bits;
+  std::memcpy(&lr_bits, &o.learning_rate, 4);
+  std::memcpy(&th_bits, &o.spill_threshold, 4);
+  std::vector<uint64_t> key = {3, uint64_t(kt), sizeof(V), n, d_stats ? 1u : 0u, th_bits, o.bucket_capacity,
+                               o.bucket_fill, o.train_steps, lr_bits, o.sample_log2, o.seed, uint64_t(o.feature),
+                               uint64_t(o.use_network), uint64_t(o.force_fallback)};
+  return cached_graph_launch(
+      key, L.bytes, {static_cast<void*>(keys), static_cast<void*>(vals), d_stats},
+      [&](void* ws, void* const* io, hipStream_t cs, SegFork) {
+        return learned_pairs_enqueue(keys, vals, n, o, d_stats, ws, &io[0], &io[1], &io[2], cs);
       },
       s);
 }
@@ -404,6 +504,81 @@ ms_status ms_sort_ex(void* d_keys, size_t n, ms_key_type kt, const ms_options* o
   } catch (...) {
     set_error("unexpected exception");
     return MS_ERR_INTERNAL;
+  }
+}
+
+ms_status ms_sort_pairs_ex(void* d_keys, void* d_vals, size_t n, ms_key_type kt, size_t val_bytes,
+                           const ms_options* opt, ms_stats* d_stats, void* stream) {
+  ms_options o;
+  ms_options_default(&o);
+  if (opt) o = *opt;
+  if (check_options(o) != MS_OK) {
+    set_error("invalid ms_options");
+    return MS_ERR_INVALID_ARG;
+  }
+  if (kt < MS_KEY_U32 || kt > MS_KEY_I64) {
+    set_error("unknown key type");
+    return MS_ERR_UNSUPPORTED;
+  }
+  if (val_bytes != 4 && val_bytes != 8) {
+    set_error("value width must be 4 or 8 bytes");
+    return MS_ERR_UNSUPPORTED;
+  }
+  if (n > 0 && (d_keys == nullptr || d_vals == nullptr)) {
+    set_error("d_keys or d_vals is NULL with n > 0");
+    return MS_ERR_INVALID_ARG;
+  }
+  if (n > 0 && d_keys == d_vals) {
+    set_error("key and value buffers overlap");
+    return MS_ERR_INVALID_ARG;
+  }
+  if (n == 0) return MS_OK;
+  const bool narrow = kt == MS_KEY_U32 || kt == MS_KEY_I32;
+  // the packed sort runs on 64-bit keys: their defaults apply, except the
+  // feature: the packed key's offset is the key's own offset times 2^32, so
+  // uint32 keys keep the log feature they take alone
+  o = resolve_options(o, MS_KEY_U64);
+  if (o.feature == MS_FEATURE_AUTO) o.feature = kt == MS_KEY_U32 ? MS_FEATURE_LOG : MS_FEATURE_LINEAR;
+  const bool learned_ok = narrow && n >= (uint64_t(4) << o.sample_log2) && n < (uint64_t(1) << 32);
+  if (o.algo == MS_ALGO_LEARNED_BUCKET && !learned_ok) {
+    set_error("learned pairs need 32-bit keys, n >= 4 * sample size and n < 2^32");
+    return MS_ERR_UNSUPPORTED;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (o.algo != MS_ALGO_LEARNED_BUCKET) {
+    ms_status st = ms_sort_pairs(d_keys, d_vals, n, kt, val_bytes, stream);
+    if (st != MS_OK || !d_stats) return st;
+    ls_plain_stats_kernel<<<1, 64, 0, s>>>(d_stats);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MS_OK : hip_fail(e, "stats launch");
+  }
+  try {
+    if (kt == MS_KEY_U32) {
+      if (val_bytes == 4)
+        return learned_pairs(static_cast<uint32_t*>(d_keys), static_cast<uint32_t*>(d_vals), kt, n, o, d_stats, s);
+      return learned_pairs(static_cast<uint32_t*>(d_keys), static_cast<uint64_t*>(d_vals), kt, n, o, d_stats, s);
+    }
+    if (val_bytes == 4)
+      return learned_pairs(static_cast<int32_t*>(d_keys), static_cast<uint32_t*>(d_vals), kt, n, o, d_stats, s);
+    return learned_pairs(static_cast<int32_t*>(d_keys), static_cast<uint64_t*>(d_vals), kt, n, o, d_stats, s);
+  } catch (...) {
+    set_error("unexpected exception");
+    return MS_ERR_INTERNAL;
+  }
+}
+
+size_t ms_temp_bytes_learned_pairs(size_t n, ms_key_type kt, size_t val_bytes, const ms_options* opt) {
+  ms_options o;
+  ms_options_default(&o);
+  if (opt) o = *opt;
+  if (check_options(o) != MS_OK || n == 0 || (kt != MS_KEY_U32 && kt != MS_KEY_I32) ||
+      (val_bytes != 4 && val_bytes != 8))
+    return 0;
+  o = resolve_options(o, MS_KEY_U64);
+  try {
+    return graph_bind_bytes() + lp_plan(n, val_bytes, o).bytes;
+  } catch (...) {
+    return 0;
   }
 }
 
