@@ -66,9 +66,11 @@ def kernel_source_hash() -> str:
 
 
 def profiled_traffic(workload: str, kernel: str):
-    """Calibrated HBM bytes per launch of `kernel` from the committed counter
-    summary, or None when there is none or the kernel sources changed since."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
+    """Calibrated HBM bytes (FETCH_SIZE + WRITE_SIZE) per launch of `kernel`
+    (or per sort, for a stage of several kernels) from the committed counter
+    summary profiles/traffic_<workload>.md, or None when there is none or the
+    kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -79,7 +81,7 @@ def profiled_traffic(workload: str, kernel: str):
     if fields.get("source_sha256") != kernel_source_hash():
         return None
     try:
-        return int(fields["traffic_bytes_per_launch"])
+        return int(fields[f"traffic.{kernel}"])
     except (KeyError, ValueError):
         return None
 
@@ -190,12 +192,18 @@ def plain_roofline(name, n, kb, vb, kernels):
         return None, None
     kname = "merge4_kernel" if dom == "merge4" else "merge_kernel"
     roof = hbm_entry(kname, per, kernels[dom]["avg_us"], name, kname)
+    if roof["achieved"] > HBM_PEAK_GBS:
+        # run detection skipped the passes (their kernels returned at once):
+        # the bytes never moved, so there is no roofline to report
+        return {"kernel": kname, "avg_us": roof["avg_us"], "skipped": True,
+                "note": "merge passes skipped by run detection; no roofline"}, None
     fused = None
     if "merge4" in kernels and "partition4" in kernels and "partition_samples" in kernels:
         m4 = kernels["merge4"]
         if kernels["partition4"]["launches"] == m4["launches"] == kernels["partition_samples"]["launches"]:
             us = sum(kernels[k]["avg_us"] for k in ("partition_samples", "partition4", "merge4"))
-            fused = hbm_entry("partition_kernel (samples) + partition4_kernel + merge4_kernel", per, us)
+            fused = hbm_entry("partition_kernel (samples) + partition4_kernel + merge4_kernel", per, us, name,
+                              "fused_pass")
             fused["share_of_pass"] = {k: round(kernels[k]["avg_us"] / us, 3)
                                       for k in ("partition_samples", "partition4", "merge4")}
     return roof, fused
@@ -234,12 +242,13 @@ def plain_form(name, K, W, dev, events=True):
 
 
 LEARNED_STAGES = {
-    # profiler class: (kernels, algorithmic key transfers per key processed)
-    "learned_hist": ("ls_hist1_kernel", 1),       # read every key
-    "learned_scatter": ("ls_scatter1_kernel", 2),  # read and write every key
-    "learned_hist2": ("ls_hist2_kernel", 1),
-    "learned_scatter2": ("ls_scatter2_kernel", 2),
-    "bucket_sort": ("seg_init/classify/owner + seg_small_kernel per class", 2),  # kept keys, read + write
+    # profiler class: (kernels, trace name, algorithmic key transfers per key processed)
+    "learned_hist": ("ls_hist1_kernel", "ls_hist1_kernel", 1),       # read every key
+    "learned_scatter": ("ls_scatter1_kernel", "ls_scatter1_kernel", 2),  # read and write every key
+    "learned_hist2": ("ls_hist2_kernel", "ls_hist2_kernel", 1),
+    "learned_scatter2": ("ls_scatter2_kernel", "ls_scatter2_kernel", 2),
+    # kept keys, read + write
+    "bucket_sort": ("seg_init/classify/owner + seg_small_kernel per class", "bucket_sort", 2),
 }
 
 
@@ -267,17 +276,16 @@ def learned_form(K, W, dev, pristine, use_graph, workload="lognormal_u32_2p29"):
     torch.cuda.synchronize()
     kept = n - int(st["spilled"]) if not st["fallback_taken"] else 0
     stages = {}
-    for cls, (kname, transfers) in LEARNED_STAGES.items():
+    for cls, (kname, tname, transfers) in LEARNED_STAGES.items():
         if cls in kernels:
             keys = kept if cls == "bucket_sort" else n
-            stages[cls] = hbm_entry(kname, transfers * kb * keys, kernels[cls]["avg_us"])
+            stages[cls] = hbm_entry(kname, transfers * kb * keys, kernels[cls]["avg_us"], workload, tname)
             stages[cls]["ms_per_step"] = kernels[cls]["ms_per_step"]
     dom = max(stages, key=lambda c: stages[c]["ms_per_step"], default=None)
     roof = None
     if dom:
         roof = dict(stages[dom])
         roof.pop("ms_per_step")
-        roof["traffic"] = profiled_traffic(workload, roof["kernel"].split(" ")[0])
     out = {"ms_per_step": round(ms, 4), "Gkeys_s": round(n / (ms * 1e-3) / 1e9, 3), "graph_replay": bool(use_graph),
            "learned_stats": {k: (round(v, 8) if isinstance(v, float) else v) for k, v in st.items()},
            "kernels": kernels, "stages": stages, "dominant": dom}
