@@ -90,6 +90,10 @@ const char* ms_last_error(void);
  * the result is the unique sorted sequence.
  * Method: tile sort (one workgroup per tile), then ceil(log2(n / tile))
  * merge-path passes; each pass is a partition kernel and a merge kernel.
+ * Keys-only sorts of at most 2^22 keys replay a cached hipGraph from the
+ * second call with the same key type and n on a stream (the buffer is
+ * bound per launch; the graph owns ms_temp_bytes(n, kt, 0) bytes of
+ * scratch); other sizes, and first calls, enqueue the kernels directly.
  */
 ms_status ms_sort(void* d_keys, size_t n, ms_key_type kt, void* stream);
 

@@ -261,3 +261,20 @@ def test_workgroup_cap_same_result(gpu):
             msort.ms_sort_ex(t, algo=msort.MS_ALGO_MERGE_PATH, stats=False, max_workgroups=cap)
             torch.cuda.synchronize()
             assert_equal_arrays(t.cpu().numpy(), exp, f"{np.dtype(dtype).name} cap {cap}")
+
+
+def test_small_repeated_sorts_replay_a_graph(gpu):
+    """Keys-only sorts of at most 2^22 keys replay a cached graph from the
+    second call with the same size on a stream (the caller's buffer bound
+    per launch): fresh buffers every call, one capture per size, every
+    output equal to the oracle's."""
+    import workloads
+    for n in (1 << 20, (1 << 20) + 777):
+        before = msort.ms_graph_captures()
+        for rep in range(4):
+            k = workloads.uniform_u32(n, seed=300 + rep, device=gpu)
+            exp = oracle.sort(k.cpu().view(torch.int32).numpy().view(np.uint32))
+            msort.ms_sort(k)
+            torch.cuda.synchronize()
+            assert_equal_arrays(k.cpu().view(torch.int32).numpy().view(np.uint32), exp, f"n={n} call {rep}")
+        assert msort.ms_graph_captures() - before == 1, n
