@@ -10,8 +10,10 @@ candidate, and keeps the fastest.  The table is written as text lines
 
 Timing: HIP events around each call on the current stream (the graph for a
 candidate is captured on its first call, which is not timed); median of the
-timed repetitions.  Keys are uniform uint32 (int32 keys behave the same);
-64-bit families have a single compiled shape per class and are not swept.
+timed repetitions.  Keys are uniform unsigned (the signed family of the same
+width takes the same shapes); families swept: 32-bit keys alone, with 4-byte
+and with 8-byte values, and 64-bit keys alone (64-bit keys with values have a
+single compiled shape per class).
 """
 import argparse
 import math
@@ -25,7 +27,9 @@ if __package__ in (None, ""):
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 import paper_2211_16479_amd as msort  # noqa: E402
 
-FAMILIES = [("u32", msort.MS_KEY_U32, 0), ("u32", msort.MS_KEY_U32, 4)]
+FAMILIES = [("u32", msort.MS_KEY_U32, 0), ("u32", msort.MS_KEY_U32, 4), ("u32", msort.MS_KEY_U32, 8),
+            ("u64", msort.MS_KEY_U64, 0)]
+SIGNED = {msort.MS_KEY_U32: "i32", msort.MS_KEY_U64: "i64"}
 KT_NAME = {msort.MS_KEY_U32: "u32", msort.MS_KEY_I32: "i32", msort.MS_KEY_U64: "u64", msort.MS_KEY_I64: "i64"}
 
 
@@ -72,17 +76,24 @@ def tune(keys_per_class: int = 1 << 24, reps: int = 7, arch: str = None, verbose
             lo = 2 if c == 0 else classes[c - 1][0] + 1
             off, max_len = class_segments(lo, bound, keys_per_class, gen, dev)
             n = int(off[-1])
-            base = torch.randint(0, 2 ** 32, (n,), dtype=torch.int64, generator=gen).to(dev)
-            pristine = (base & 0xFFFFFFFF).to(torch.int32).view(torch.uint32)
+            if kt == msort.MS_KEY_U64:
+                pristine = torch.randint(-2 ** 63, 2 ** 63 - 1, (n,), dtype=torch.int64, generator=gen).to(dev)
+            else:
+                base = torch.randint(0, 2 ** 32, (n,), dtype=torch.int64, generator=gen).to(dev)
+                pristine = (base & 0xFFFFFFFF).to(torch.int32).view(torch.uint32)
             keys = torch.empty_like(pristine)
-            vals = torch.arange(n, dtype=torch.int32, device=dev).view(torch.uint32) if vb else None
+            vals = None
+            if vb == 4:
+                vals = torch.arange(n, dtype=torch.int32, device=dev).view(torch.uint32)
+            elif vb == 8:
+                vals = torch.arange(n, dtype=torch.int64, device=dev)
             best = None
             for wg, ipt in shapes:
                 msort.ms_tuning_set(kt, vb, c, wg, ipt)
 
                 def call():
                     keys.copy_(pristine)
-                    msort.ms_segmented_sort(keys, off, vals, max_segment_len=max_len)
+                    msort.ms_segmented_sort(keys, off, vals, max_segment_len=max_len, key_type=kt)
 
                 call()  # capture
                 torch.cuda.synchronize()
@@ -95,9 +106,8 @@ def tune(keys_per_class: int = 1 << 24, reps: int = 7, arch: str = None, verbose
                     best = (t, wg, ipt)
             msort.ms_tuning_set(kt, vb, c, best[1], best[2])
             lines.append(f"{arch} {KT_NAME[kt]} {vb} {c} {best[1]} {best[2]}")
-            # the same choice for the signed 32-bit family
-            if kt == msort.MS_KEY_U32:
-                lines.append(f"{arch} i32 {vb} {c} {best[1]} {best[2]}")
+            # the same choice for the signed family of the same width
+            lines.append(f"{arch} {SIGNED[kt]} {vb} {c} {best[1]} {best[2]}")
     return lines
 
 

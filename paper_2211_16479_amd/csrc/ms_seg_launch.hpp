@@ -38,12 +38,11 @@ static hipError_t launch_small(K* keys, V* vals, const int64_t* off, SegState st
 }
 
 // Candidate (WG, IPT) shapes per class bound; index 0 is the default.
-// 32-bit keys (keys only or 4-byte values) get every candidate, other
-// families the default only, to bound compile time.
+// Keys-only families and 32-bit keys with values get every candidate;
+// 64-bit keys with values the default only, to bound compile time.
 template <class K, class V>
 struct SegCands {
-  static constexpr bool FULL = sizeof(K) == 4 && (!HasVal<V>::value || sizeof(typename std::conditional<
-                                                                           HasVal<V>::value, V, int>::type) == 4);
+  static constexpr bool FULL = !HasVal<V>::value || sizeof(K) == 4;
   static constexpr int MAXC = 3;
   // {wg, ipt} per class bound, default first
   static int table(uint32_t bound, int (*t)[2]) {

@@ -47,22 +47,30 @@ def test_class_boundaries(gpu, kdt, vdt):
             assert_equal_arrays(gv, ev, f"{dist} values")
 
 
-@pytest.mark.parametrize("vb", [0, 4])
-def test_every_class_candidate(gpu, vb):
-    """Each compiled per-class shape sorts correctly (tuning table entries)."""
+FAMILIES = [(np.uint32, None, msort.MS_KEY_U32), (np.uint32, np.uint32, msort.MS_KEY_U32),
+            (np.int32, np.uint64, msort.MS_KEY_I32), (np.uint64, None, msort.MS_KEY_U64),
+            (np.int64, None, msort.MS_KEY_I64)]
+
+
+@pytest.mark.parametrize("kdt,vdt,kt", FAMILIES,
+                         ids=lambda d: "none" if d is None else (np.dtype(d).name if not isinstance(d, int) else str(d)))
+def test_every_class_candidate(gpu, kdt, vdt, kt):
+    """Each compiled per-class shape of every tuned family sorts correctly
+    (tuning table entries), against the oracle, heavy ties."""
     rng = np.random.default_rng(22)
-    classes = msort.ms_seg_classes(msort.MS_KEY_U32, vb)
-    saved = [msort.ms_tuning_get(msort.MS_KEY_U32, vb, c) for c in range(len(classes))]
+    vb = 0 if vdt is None else np.dtype(vdt).itemsize
+    classes = msort.ms_seg_classes(kt, vb)
+    saved = [msort.ms_tuning_get(kt, vb, c) for c in range(len(classes))]
     try:
         for c, (bound, shapes) in enumerate(classes):
             lo = 2 if c == 0 else classes[c - 1][0] + 1
             lens = np.concatenate([[lo, bound, (lo + bound) // 2], rng.integers(lo, bound + 1, size=40)])
             off = offsets_of(lens)
-            k = keys_fill(int(off[-1]), np.uint32, "few", rng)
-            v = np.arange(off[-1], dtype=np.uint32) if vb else None
+            k = keys_fill(int(off[-1]), kdt, "few", rng)
+            v = None if vdt is None else np.arange(off[-1], dtype=vdt)
             exp = oracle.segmented_sort(k, off, v)
             for wg, ipt in shapes:
-                msort.ms_tuning_set(msort.MS_KEY_U32, vb, c, wg, ipt)
+                msort.ms_tuning_set(kt, vb, c, wg, ipt)
                 gk, gv = run_seg(k, off, v, gpu)
                 if v is None:
                     assert_equal_arrays(gk, exp, f"class {c} shape {wg}x{ipt}")
@@ -71,7 +79,7 @@ def test_every_class_candidate(gpu, vb):
                     assert_equal_arrays(gv, exp[1], f"class {c} shape {wg}x{ipt} values")
     finally:
         for c, (wg, ipt) in enumerate(saved):
-            msort.ms_tuning_set(msort.MS_KEY_U32, vb, c, wg, ipt)
+            msort.ms_tuning_set(kt, vb, c, wg, ipt)
 
 
 def test_batched_reduced(gpu):
