@@ -393,7 +393,7 @@ def main():
                          "(reference dispatches for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the sharded design is described, not built)", file=sys.stderr)
         sys.exit(2)
 

@@ -27,7 +27,7 @@
 //   sort    : kept buckets are sorted in LDS by the segmented small-class
 //             kernels;
 //   check   : the sorted kept buckets must meet in order (the last key of
-//             each <= the first key of the next: the judge; it cannot fail
+//             each <= the first key of the next; it cannot fail
 //             for a non-decreasing bucket function, and if it does the plain
 //             merge sort sorts the keys, a permutation of the input, again);
 //   repair  : the spill is sorted by the plain merge sort and one
@@ -905,7 +905,7 @@ __global__ __launch_bounds__(LS_WG) void ls_scatter2_kernel(const K* __restrict_
   }
 }
 
-// The judge: after the bucket sort, the kept buckets (each sorted, laid out
+// The order check: after the bucket sort, the kept buckets (each sorted, laid out
 // in bucket order from r_base) must meet in order.  One thread per bucket
 // compares the key before the bucket's first position with its first key;
 // a failure sends the keys (a permutation of the input) to the plain merge
