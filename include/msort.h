@@ -200,7 +200,8 @@ ms_status ms_tuning_load(const char* path, const char* arch, int* applied);
  * (decided on the device).  The output is the same bytes as ms_sort's.
  * ------------------------------------------------------------------------ */
 typedef enum ms_algo {
-  MS_ALGO_AUTO = 0,            /* learned for uint32 keys and n >= 2^27, else merge path */
+  MS_ALGO_AUTO = 0,            /* learned for 32-bit keys from n = 2^27 and 64-bit keys from 2^26
+                                  (where it measured faster), else merge path */
   MS_ALGO_MERGE_PATH = 1,
   MS_ALGO_LEARNED_BUCKET = 2
 } ms_algo;
