@@ -153,3 +153,21 @@ def test_full_normal_int64_2p28_learned_equals_oracle(gpu):
     assert st["fallback_taken"] == 0 and st["spilled"] == 0
     exp = oracle.sort(k.cpu().numpy(), threads=oracle.host_threads())
     assert_equal_arrays(a.cpu().numpy(), exp, "2^28 int64 learned")
+
+
+def test_automatic_choice_by_key_width(gpu):
+    """MS_ALGO_AUTO: 64-bit keys take the learned form from 2^26 keys, 32-bit
+    keys from 2^27 (below, the plain sort); either way the output is the
+    oracle's."""
+    for n, expect in ((1 << 25, msort.MS_ALGO_MERGE_PATH), (1 << 26, msort.MS_ALGO_LEARNED_BUCKET)):
+        k = workloads.normal_i64(n, seed=40, device=gpu)
+        exp = oracle.sort(k.cpu().numpy(), threads=oracle.host_threads())
+        _, st = msort.ms_sort_ex(k)
+        torch.cuda.synchronize()
+        assert st["algo_used"] == expect, (n, st)
+        assert_equal_arrays(k.cpu().numpy(), exp, f"auto int64 n={n}")
+        del k
+    k = workloads.normal_i64(1 << 26, sigma=2.0 ** 28, seed=41, device=gpu).to(torch.int32)
+    _, st = msort.ms_sort_ex(k)
+    torch.cuda.synchronize()
+    assert st["algo_used"] == msort.MS_ALGO_MERGE_PATH
