@@ -253,6 +253,9 @@ def plain_form(name, K, W, dev, events=True):
 
 LEARNED_STAGES = {
     # profiler class: (kernels, trace name, algorithmic key transfers per key processed)
+    # level 1: size estimate from a random sample (from 2^23 keys), else the
+    # exact histogram
+    "learned_estimate": ("ls_est1_kernel", "ls_est1_kernel", 1),      # read every sampled key
     "learned_hist": ("ls_hist1_kernel", "ls_hist1_kernel", 1),       # read every key
     "learned_scatter": ("ls_scatter1_kernel", "ls_scatter1_kernel", 2),  # read and write every key
     "learned_hist2": ("ls_hist2_kernel", "ls_hist2_kernel", 1),
@@ -260,6 +263,15 @@ LEARNED_STAGES = {
     # kept keys, read + write
     "bucket_sort": ("seg_init/classify/owner + seg_small_kernel per class", "bucket_sort", 2),
 }
+
+
+def est_sample_size(n):
+    """Keys the learned form's level-1 size estimate reads: min(2^20, n / 128)
+    as a power of two, at least 2^16."""
+    s = 1 << 16
+    while s < (1 << 20) and 2 * s * 128 <= n:
+        s *= 2
+    return s
 
 
 def learned_form(K, W, dev, pristine, use_graph, workload="lognormal_u32_2p29"):
@@ -288,7 +300,7 @@ def learned_form(K, W, dev, pristine, use_graph, workload="lognormal_u32_2p29"):
     stages = {}
     for cls, (kname, tname, transfers) in LEARNED_STAGES.items():
         if cls in kernels:
-            keys = kept if cls == "bucket_sort" else n
+            keys = kept if cls == "bucket_sort" else est_sample_size(n) if cls == "learned_estimate" else n
             stages[cls] = hbm_entry(kname, transfers * kb * keys, kernels[cls]["avg_us"], workload, tname)
             stages[cls]["ms_per_step"] = kernels[cls]["ms_per_step"]
     dom = max(stages, key=lambda c: stages[c]["ms_per_step"], default=None)

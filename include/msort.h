@@ -191,13 +191,14 @@ ms_status ms_tuning_load(const char* path, const char* arch, int* applied);
  * through a running-max envelope, and beyond that range along its first and
  * last segments (clipped to [0, 1]), so bucket ids floor(F(x) * B) are
  * non-decreasing in the key.
- * Keys are scattered (two levels) into B ~ n / bucket_fill buckets; buckets
- * of at most bucket_capacity keys (64-bit keys: at most 4096, the largest
- * bucket one workgroup sorts in LDS) are sorted in LDS; larger ones spill.  The
- * spill is sorted by the plain merge sort and merged back with one exact
- * merge-path pass.  If more than spill_threshold * n keys spill, or the order
- * check of the buckets fails, the plain merge sort sorts the input instead
- * (decided on the device).  The output is the same bytes as ms_sort's.
+ * Keys are scattered (two levels) into B ~ n / bucket_fill buckets (the
+ * first level into regions sized from a random sample, see coarse_estimate);
+ * buckets of at most bucket_capacity keys (64-bit keys: at most 4096, the
+ * largest bucket one workgroup sorts in LDS) are sorted in LDS; larger ones
+ * spill.  The spill is sorted by the plain merge sort and merged back with
+ * one exact merge-path pass.  If more than spill_threshold * n keys spill, or
+ * the order check of the buckets fails, the plain merge sort sorts the input
+ * instead (decided on the device).  The output is the same bytes as ms_sort's.
  * ------------------------------------------------------------------------ */
 typedef enum ms_algo {
   MS_ALGO_AUTO = 0,            /* learned for 32-bit keys from n = 2^27 and 64-bit keys from 2^26
@@ -230,6 +231,12 @@ typedef struct ms_options {
   uint32_t max_workgroups;   /* merge path only, measurement support: at most this many workgroups per
                                 launch, each looping over tiles (the worker count of a scaling study);
                                 0 (default) = one workgroup per tile */
+  int coarse_estimate;       /* learned form, first scatter level: 1 (default) sizes each coarse
+                                bucket's region from a random sample of the input (n >= 2^23:
+                                min(2^20, n / 128) keys) instead of counting every key first; a
+                                region found too small during the scatter is detected and the exact
+                                count-then-scatter pass runs instead (stats.coarse_recounted);
+                                0: always the exact pass; 2: estimate, then always recount (testing) */
 } ms_options;
 
 /* Written on the device when the sort completes (valid after the stream). */
@@ -243,6 +250,7 @@ typedef struct ms_stats {
   uint64_t buckets;          /* number of buckets B */
   float loss_initial;        /* training loss at the start point */
   float loss_final;          /* training loss before the last step */
+  int32_t coarse_recounted;  /* the estimated first-level regions were replaced by the exact pass */
 } ms_stats;
 
 /* Default options (as documented above). */
@@ -375,8 +383,10 @@ ms_status ms_release_workspace(void);
  * level-1 histogram, 8 learned level-1 scatter, 9 bucket sort, 10 other
  * learned kernels, 11 four-way partition, 12 fused four-run merge,
  * 13 learned level-2 histogram, 14 learned level-2 scatter, 15 the sampling
- * two-run partition of a fused pass), the number of launches and their
- * summed duration in milliseconds since the last ms_profile_reset().
+ * two-run partition of a fused pass, 16 learned level-1 size estimate; the
+ * level-1 exact pass counts as class 10 when it only runs after an estimate
+ * proved too small), the number of launches and their summed duration in
+ * milliseconds since the last ms_profile_reset().
  */
 ms_status ms_profile_enable(int on);
 /* Time only the kernel classes whose bit (1 << class) is set in class_mask

@@ -27,7 +27,7 @@ PROFILE_KERNELS = {"tile_sort": 0, "partition": 1, "merge": 2, "seg_classify": 3
                    "seg_small": 4, "seg_large": 5, "mlp_train": 6, "learned_hist": 7,
                    "learned_scatter": 8, "bucket_sort": 9, "learned_other": 10,
                    "partition4": 11, "merge4": 12, "learned_hist2": 13, "learned_scatter2": 14,
-                   "partition_samples": 15}
+                   "partition_samples": 15, "learned_estimate": 16}
 
 MS_ALGO_AUTO, MS_ALGO_MERGE_PATH, MS_ALGO_LEARNED_BUCKET = 0, 1, 2
 MS_FEATURE_LOG, MS_FEATURE_LINEAR, MS_FEATURE_AUTO = 0, 1, 2
@@ -42,7 +42,7 @@ class MsOptions(ctypes.Structure):
                 ("train_steps", ctypes.c_uint32), ("learning_rate", ctypes.c_float),
                 ("sample_log2", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("feature", ctypes.c_int),
                 ("use_network", ctypes.c_int), ("force_fallback", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("max_workgroups", ctypes.c_uint32)]
+                ("max_workgroups", ctypes.c_uint32), ("coarse_estimate", ctypes.c_int)]
 
 
 class MsStats(ctypes.Structure):
@@ -50,7 +50,7 @@ class MsStats(ctypes.Structure):
     _fields_ = [("algo_used", ctypes.c_int32), ("fallback_taken", ctypes.c_int32),
                 ("misordered", ctypes.c_int32), ("repaired", ctypes.c_int32), ("spilled", ctypes.c_uint64),
                 ("max_bucket", ctypes.c_uint64), ("buckets", ctypes.c_uint64), ("loss_initial", ctypes.c_float),
-                ("loss_final", ctypes.c_float)]
+                ("loss_final", ctypes.c_float), ("coarse_recounted", ctypes.c_int32)]
 
 
 _lib = None

@@ -29,7 +29,8 @@ enum ProfKernel {
   PK_LEARN_HIST2 = 13,
   PK_LEARN_SCATTER2 = 14,
   PK_PARTITION_SAMPLES = 15,
-  PK_COUNT = 16
+  PK_LEARN_EST = 16,
+  PK_COUNT = 17
 };
 
 // Records a start/stop event pair around a launch when profiling is on.

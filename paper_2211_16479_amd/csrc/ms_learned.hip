@@ -31,6 +31,7 @@ __global__ void ls_setup_kernel(LsModel* md, int log_feature, int use_table, int
   md->loss_last = 0.f;
   md->off64 = 0;
   md->scale64 = 1.f;
+  md->l1_over = 0;
 }
 
 __global__ void ls_set_theta_kernel(LsModel* md, const float* theta) {
@@ -84,6 +85,7 @@ __global__ void ls_stats_kernel(const LsModel* md, ms_stats* st, uint64_t bucket
   st->buckets = buckets;
   st->loss_initial = md->loss0;
   st->loss_final = md->loss_last;
+  st->coarse_recounted = md->l1_over;
 }
 
 // 1 for the log feature, 0 for the linear one.  MS_FEATURE_AUTO: log for
@@ -106,6 +108,9 @@ struct LsPlan {
                        // the bucket sort's largest small class for the key type)
   uint64_t spill_cap;  // spill that still takes the learned path
   uint64_t chunk_cap;  // bound on level-2 chunks
+  bool est;            // first level: regions sized from a random sample
+  uint32_t S1, q;      // its sample size, input keys per sampled key
+  uint64_t coarse_keys;  // first-level buffer (keys)
   // scratch offsets
   size_t md, sample, sample_tmp, partial, loss, bins, coarse, xr, part, seg, bytes;
   size_t bins_c_off[9], bins_f_off[3];
@@ -134,6 +139,18 @@ static LsPlan ls_plan(uint64_t n, const ms_options& o) {
   P.B = uint64_t(1) << tb;
   P.spill_cap = std::min<uint64_t>(n, uint64_t(std::ceil(double(o.spill_threshold) * double(n))));
   P.chunk_cap = ceil_div(n, ls_chk<K>()) + P.nbc;
+  // estimated first level from 2^23 keys: a sample of min(2^20, n / 128)
+  // keys (a power of two); the buffer holds the sum of the regions' bounds
+  // (ls_plan1_est_kernel), which must stay below 2^32 keys
+  P.coarse_keys = n;
+  P.est = o.coarse_estimate != 0 && n >= (uint64_t(1) << 23);
+  if (P.est) {
+    P.S1 = 1u << 16;
+    while (P.S1 < (1u << 20) && uint64_t(P.S1) * 2 * 128 <= n) P.S1 *= 2;
+    P.q = uint32_t(ceil_div(n, P.S1));
+    const uint64_t bound = (uint64_t(5) * P.S1 * P.q) / 4 + uint64_t(P.nbc) * (uint64_t(32) * P.q + 63);
+    if (bound < (uint64_t(1) << 32) - 64) P.coarse_keys = std::max<uint64_t>(n, bound); else P.est = false;
+  }
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t at = off; off = align_up(off + bytes, 256); return at; };
   P.md = take(sizeof(LsModel));
@@ -144,7 +161,7 @@ static LsPlan ls_plan(uint64_t n, const ms_options& o) {
   for (int i = 0; i < 9; ++i) P.bins_c_off[i] = take(sizeof(uint32_t) * (P.nbc + 1));
   for (int i = 0; i < 2; ++i) P.bins_f_off[i] = take(sizeof(uint32_t) * P.B);
   P.bins_f_off[2] = take(sizeof(int64_t) * (P.B + 1));
-  P.coarse = take(std::max<size_t>(sizeof(K) * n, plain_temp_bytes<K, NoVal>(n)));
+  P.coarse = take(std::max<size_t>(sizeof(K) * P.coarse_keys, plain_temp_bytes<K, NoVal>(n)));
   P.xr = take(sizeof(K) * n);
   P.part = take(sizeof(int64_t) * (ceil_div(n, PlainCfg<K, NoVal>::MTILE) + 2));  // merge_two_runs
   P.seg = take(seg_temp_bytes<K, NoVal>(P.B, P.capacity));
@@ -225,18 +242,41 @@ static ms_status learned_enqueue(K* keys, uint64_t n, const ms_options& o, ms_st
   if (st != MS_OK) return st;
   ls_compile_kernel<<<1, 64, 0, s>>>(md, int(o.train_steps) & 1, sample, P.S, nullptr);
   // level 1
+  // (gated stages run with a bounded grid: when skipped they cost little)
+  const uint64_t gated_grid = uint64_t(device_cu_count()) * 4;
   ls_clear_kernel<<<dim3(unsigned(ceil_div(std::max<uint64_t>(P.B, P.nbc), 256))), 256, 0, s>>>(bn, P.nbc,
                                                                                                  uint32_t(P.B));
   const unsigned chunks1 = unsigned(ceil_div(n, ls_chk<K>()));
   const uint32_t last_len = uint32_t(n - uint64_t(chunks1 - 1) * ls_chk<K>());
-  {
-    ProfScope ps(PK_LEARN_HIST, s);
-    ls_hist1_kernel<<<unsigned(ceil_div(chunks1, LS_H1)), LS_WG, 0, s>>>(keys, chunks1, last_len, md, bn, rk);
+  unsigned h1_grid = unsigned(ceil_div(chunks1, LS_H1)), s1_grid = chunks1;
+  const int* gate = nullptr;
+  if (P.est) {
+    // regions sized from a random sample, scatter with a bounds check; the
+    // exact pass below runs only if a region was too small
+    {
+      ProfScope ps(PK_LEARN_EST, s);
+      ls_est1_kernel<K><<<P.S1 / (LS_EST * LS_WG), LS_WG, 0, s>>>(keys, n, o.seed, md, bn, rk);
+    }
+    ls_plan1_est_kernel<<<1, LS_WG, 0, s>>>(md, bn, P.q);
+    {
+      ProfScope ps(PK_LEARN_SCATTER, s);
+      ls_scatter1_kernel<<<chunks1, LS_WG, 0, s>>>(keys, chunks1, last_len, md, bn, coarse, rk, nullptr,
+                                                   &md->l1_over);
+    }
+    ls_fin1_kernel<<<1, LS_WG, 0, s>>>(md, bn, uint32_t(ls_chk<K>()), o.coarse_estimate == 2 ? 1 : 0);
+    gate = &md->l1_over;
+    h1_grid = unsigned(std::min<uint64_t>(h1_grid, gated_grid));
+    s1_grid = unsigned(std::min<uint64_t>(s1_grid, gated_grid));
   }
-  ls_plan1_kernel<<<1, LS_WG, 0, s>>>(md, bn, uint32_t(ls_chk<K>()));
+  // exact: count, plan, scatter
   {
-    ProfScope ps(PK_LEARN_SCATTER, s);
-    ls_scatter1_kernel<<<chunks1, LS_WG, 0, s>>>(keys, chunks1, last_len, md, bn, coarse, rk);
+    ProfScope ps(gate ? PK_LEARN_OTHER : PK_LEARN_HIST, s);
+    ls_hist1_kernel<<<h1_grid, LS_WG, 0, s>>>(keys, chunks1, last_len, md, bn, rk, gate);
+  }
+  ls_plan1_kernel<<<1, LS_WG, 0, s>>>(md, bn, uint32_t(ls_chk<K>()), gate);
+  {
+    ProfScope ps(gate ? PK_LEARN_OTHER : PK_LEARN_SCATTER, s);
+    ls_scatter1_kernel<<<s1_grid, LS_WG, 0, s>>>(keys, chunks1, last_len, md, bn, coarse, rk, gate, nullptr);
   }
   // level 2
   {
@@ -263,8 +303,6 @@ static ms_status learned_enqueue(K* keys, uint64_t n, const ms_options& o, ms_st
   if (st != MS_OK) return st;
   ls_check_kernel<K><<<dim3(unsigned(ceil_div(P.B, 256))), 256, 0, s>>>(md, bn, P.B);
   // repair: spill sorted by the plain merge sort, then merged with the kept keys
-  // (gated stages run with a bounded grid: when skipped they cost little)
-  const uint64_t gated_grid = uint64_t(device_cu_count()) * 4;
   const uint64_t* spilled = reinterpret_cast<const uint64_t*>(&md->spilled);
   if (P.spill_cap > 0) {
     st = plain_sort<K, NoVal>(xr, nullptr, P.spill_cap, DevCtl{spilled, &md->do_repair, nullptr}, s, coarse,
@@ -291,6 +329,7 @@ static ms_status check_options(const ms_options& o) {
   if (o.sample_log2 != 0 && (o.sample_log2 < 10 || o.sample_log2 > 20)) return MS_ERR_INVALID_ARG;
   if (o.feature != MS_FEATURE_LOG && o.feature != MS_FEATURE_LINEAR && o.feature != MS_FEATURE_AUTO)
     return MS_ERR_INVALID_ARG;
+  if (o.coarse_estimate < 0 || o.coarse_estimate > 2) return MS_ERR_INVALID_ARG;
   return MS_OK;
 }
 
@@ -312,7 +351,8 @@ static ms_status learned_sort(K* keys, ms_key_type kt, uint64_t n, const ms_opti
   // every launch
   std::vector<uint64_t> key = {2, uint64_t(kt), n, d_stats ? 1u : 0u, th_bits, o.bucket_capacity, o.bucket_fill,
                                o.train_steps, lr_bits, o.sample_log2, o.seed, uint64_t(o.feature),
-                               uint64_t(o.use_network), uint64_t(o.force_fallback)};
+                               uint64_t(o.use_network), uint64_t(o.force_fallback),
+                               uint64_t(o.coarse_estimate)};
   return cached_graph_launch(
       key, P.bytes, {static_cast<void*>(keys), d_stats},
       [&](void* ws, void* const* io, hipStream_t cs, SegFork) {
@@ -411,7 +451,8 @@ static ms_status learned_pairs(K32* keys, V* vals, ms_key_type kt, uint64_t n, c
   std::memcpy(&th_bits, &o.spill_threshold, 4);
   std::vector<uint64_t> key = {3, uint64_t(kt), sizeof(V), n, d_stats ? 1u : 0u, th_bits, o.bucket_capacity,
                                o.bucket_fill, o.train_steps, lr_bits, o.sample_log2, o.seed, uint64_t(o.feature),
-                               uint64_t(o.use_network), uint64_t(o.force_fallback)};
+                               uint64_t(o.use_network), uint64_t(o.force_fallback),
+                               uint64_t(o.coarse_estimate)};
   return cached_graph_launch(
       key, L.bytes, {static_cast<void*>(keys), static_cast<void*>(vals), d_stats},
       [&](void* ws, void* const* io, hipStream_t cs, SegFork) {
@@ -470,6 +511,7 @@ void ms_options_default(ms_options* o) {
   o->use_network = 1;
   o->force_fallback = 0;
   o->use_graph = 1;
+  o->coarse_estimate = 1;
 }
 
 ms_status ms_sort_ex(void* d_keys, size_t n, ms_key_type kt, const ms_options* opt, ms_stats* d_stats, void* stream) {

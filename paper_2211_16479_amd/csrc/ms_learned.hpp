@@ -121,6 +121,7 @@ struct LsModel {
   float loss0, loss_last;
   uint64_t off64;        // keys other than uint32: feature offset (the sample's smallest unsigned image)
   float scale64;         // keys other than uint32: linear feature scale
+  int l1_over;           // estimated first level: a region was too small (the exact pass runs)
 };
 
 // Keys other than uint32: the feature's offset and scale from the sorted
@@ -147,18 +148,25 @@ __global__ void ls_feature_range_kernel(LsModel* md, const K* __restrict__ sampl
 }
 
 // ------------------------------------------------------------ sampling
+// Position of draw `idx` in [0, n): the splitmix64 finaliser of a Weyl
+// sequence point of (seed, idx), mapped to [0, n) by a 64x64 -> high-64
+// product.  The training sample takes draws 0 .. S-1; the first level's
+// size estimate takes draws from 2^32 on.
+__device__ __forceinline__ uint64_t ls_draw(uint64_t seed, uint64_t idx, uint64_t n) {
+  uint64_t z = seed * 0x9E3779B97F4A7C15ull + (idx + 1) * 0xD1B54A32D192ED03ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return __umul64hi(z, n);
+}
+
 template <class K>
 __global__ __launch_bounds__(256) void ls_sample_kernel(const K* __restrict__ keys, uint64_t n, uint32_t S,
                                                         uint64_t seed, K* __restrict__ out, Rebind rk) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S) return;
   keys = rebind(keys, rk);
-  // splitmix64 of (seed, i), mapped to [0, n) by a 64x64 -> high-64 product
-  uint64_t z = seed * 0x9E3779B97F4A7C15ull + (uint64_t(i) + 1) * 0xD1B54A32D192ED03ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z ^= z >> 31;
-  out[i] = keys[__umul64hi(z, n)];
+  out[i] = keys[ls_draw(seed, i, n)];
 }
 
 // ------------------------------------------------------------ start point
@@ -530,19 +538,22 @@ __global__ __launch_bounds__(256) void ls_clear_kernel(LsBins bn, uint32_t nb_c,
   if (i < nb_c) bn.cnt_c[i] = 0;
 }
 
-// Level 1: coarse histogram of LS_H1 consecutive chunks per workgroup (one
-// flush of LDS counts into the global counters per LS_H1 chunks, which
-// keeps the 1024 global counters from serialising the whole launch).
+// Level 1, exact: coarse histogram of groups of LS_H1 consecutive chunks
+// (one flush of LDS counts into the global counters per workgroup, which
+// keeps the 1024 global counters from serialising the whole launch); a
+// workgroup takes groups blockIdx.x, blockIdx.x + gridDim.x, ...
 // The input is nch chunks, all full but the last, of last_len keys; chunk
 // lengths come from these 32-bit counts rather than from a 64-bit
 // min(n - base, chunk), which this compiler has been seen to lower into a
 // select on a stale scalar condition code (every chunk then counted full).
+// gate: if non-null, the launch does nothing unless *gate is set.
 template <class K>
 __global__ __launch_bounds__(LS_WG) void ls_hist1_kernel(const K* __restrict__ keys, uint32_t nch,
                                                          uint32_t last_len, const LsModel* md, LsBins bn,
-                                                         Rebind rk) {
+                                                         Rebind rk, const int* gate) {
   __shared__ LsTable tb;
   __shared__ uint32_t h[LS_MAX_BINS];
+  if (gate && *gate == 0) return;
   keys = rebind(keys, rk);
   ls_load_table(md, &tb);
   const uint32_t nbc = md->nbins_c;
@@ -550,38 +561,41 @@ __global__ __launch_bounds__(LS_WG) void ls_hist1_kernel(const K* __restrict__ k
   __syncthreads();
   const LsUni U = ls_uni(&tb);
   constexpr int CHK = ls_chk<K>();
-  for (int c = 0; c < LS_H1; ++c) {
-    const uint32_t ci = blockIdx.x * LS_H1 + c;  // chunk index
-    if (ci >= nch) break;  // workgroup-uniform
-    const uint32_t lim = ci + 1 < nch ? uint32_t(CHK) : last_len;
-    const K* kb = keys + uint64_t(ci) * CHK;
-    // full chunks (all but the last) run without per-element bounds checks
-    auto body = [&](auto fullc) {
-      constexpr bool FULL = decltype(fullc)::value;
-      K kv[CHK / LS_WG];
+  const uint32_t ngroups = (nch + LS_H1 - 1) / LS_H1;
+  for (uint32_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    const uint32_t c_end = (g + 1) * LS_H1 < nch ? (g + 1) * LS_H1 : nch;
+    for (uint32_t ci = g * LS_H1; ci < c_end; ++ci) {  // chunk index (workgroup-uniform)
+      const uint32_t lim = ci + 1 < nch ? uint32_t(CHK) : last_len;
+      const K* kb = keys + uint64_t(ci) * CHK;
+      // full chunks (all but the last) run without per-element bounds checks
+      auto body = [&](auto fullc) {
+        constexpr bool FULL = decltype(fullc)::value;
+        K kv[CHK / LS_WG];
 #pragma unroll
-      for (int r = 0; r < CHK / LS_WG; ++r) {
-        const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
-        kv[r] = (FULL || i < lim) ? kb[i] : K(0);
-      }
+        for (int r = 0; r < CHK / LS_WG; ++r) {
+          const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
+          kv[r] = (FULL || i < lim) ? kb[i] : K(0);
+        }
 #pragma unroll
-      for (int r = 0; r < CHK / LS_WG; ++r) {
-        const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
-        if (FULL || i < lim) atomicAdd(&h[ls_bucket(&tb, U, kv[r]) >> U.fine_bits], 1u);
-      }
-    };
-    if (lim == uint32_t(CHK)) body(std::true_type{}); else body(std::false_type{});
+        for (int r = 0; r < CHK / LS_WG; ++r) {
+          const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
+          if (FULL || i < lim) atomicAdd(&h[ls_bucket(&tb, U, kv[r]) >> U.fine_bits], 1u);
+        }
+      };
+      if (lim == uint32_t(CHK)) body(std::true_type{}); else body(std::false_type{});
+    }
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG)
     if (h[i]) atomicAdd(&bn.cnt_c[i], h[i]);
 }
 
-// Level 1 plan (one workgroup): coarse offsets, cursors, level-2 chunk map
-// (chunks of `chk` keys).
-__global__ __launch_bounds__(LS_WG) void ls_plan1_kernel(LsModel* md, LsBins bn, uint32_t chk) {
+// Level 1 plan, exact (one workgroup): coarse offsets, cursors, level-2
+// chunk map (chunks of `chk` keys).  gate as in ls_hist1_kernel.
+__global__ __launch_bounds__(LS_WG) void ls_plan1_kernel(LsModel* md, LsBins bn, uint32_t chk, const int* gate) {
   __shared__ uint32_t cnt[LS_MAX_BINS], off[LS_MAX_BINS], ch[LS_MAX_BINS], choff[LS_MAX_BINS], tmp[LS_WG];
   __shared__ uint32_t total, tch;
+  if (gate && *gate == 0) return;
   const uint32_t nbc = md->nbins_c;
   for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) {
     cnt[i] = bn.cnt_c[i];
@@ -597,6 +611,81 @@ __global__ __launch_bounds__(LS_WG) void ls_plan1_kernel(LsModel* md, LsBins bn,
   }
   if (threadIdx.x == 0) {
     bn.off_c[nbc] = total;
+    bn.chunk_start[nbc] = tch;
+    md->total_chunks = tch;
+  }
+}
+
+// Level 1, estimated: coarse-bin counts of LS_EST * LS_WG keys per workgroup
+// at random positions (draws 2^32 + i), added into cnt_c.
+constexpr int LS_EST = 4;
+template <class K>
+__global__ __launch_bounds__(LS_WG) void ls_est1_kernel(const K* __restrict__ keys, uint64_t n, uint64_t seed,
+                                                        const LsModel* md, LsBins bn, Rebind rk) {
+  __shared__ LsTable tb;
+  __shared__ uint32_t h[LS_MAX_BINS];
+  keys = rebind(keys, rk);
+  ls_load_table(md, &tb);
+  const uint32_t nbc = md->nbins_c;
+  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) h[i] = 0;
+  __syncthreads();
+  const LsUni U = ls_uni(&tb);
+  const uint64_t d0 = (uint64_t(1) << 32) + uint64_t(blockIdx.x) * (LS_EST * LS_WG) + threadIdx.x;
+  K kv[LS_EST];
+#pragma unroll
+  for (int r = 0; r < LS_EST; ++r) kv[r] = keys[ls_draw(seed, d0 + uint64_t(r) * LS_WG, n)];
+#pragma unroll
+  for (int r = 0; r < LS_EST; ++r) atomicAdd(&h[ls_bucket(&tb, U, kv[r]) >> U.fine_bits], 1u);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG)
+    if (h[i]) atomicAdd(&bn.cnt_c[i], h[i]);
+}
+
+// Estimated level 1 plan (one workgroup): c sampled keys in bin i, each
+// standing for q input keys, give the bin a region of c q + c q / 4 + 32 q
+// keys rounded up to a multiple of 64 (a bin that truly holds more than
+// that is some 4.5 standard deviations or more out for 64 to 1024 sampled
+// keys per bin); cursors at the region starts, region ends in off_c[i + 1].
+// The host sizes the buffer for the sum of these bounds.
+__global__ __launch_bounds__(LS_WG) void ls_plan1_est_kernel(LsModel* md, LsBins bn, uint32_t q) {
+  __shared__ uint32_t r[LS_MAX_BINS], off[LS_MAX_BINS], tmp[LS_WG];
+  __shared__ uint32_t total;
+  const uint32_t nbc = md->nbins_c;
+  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) {
+    const uint64_t e = uint64_t(bn.cnt_c[i]) * q;
+    r[i] = uint32_t((e + (e >> 2) + uint64_t(32) * q + 63) & ~uint64_t(63));
+  }
+  __syncthreads();
+  ls_block_scan(r, off, nbc, tmp, &total);
+  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) {
+    bn.off_c[i] = off[i];
+    bn.cursor_c[i] = off[i];
+  }
+  if (threadIdx.x == 0) bn.off_c[nbc] = total;
+}
+
+// After the estimated scatter (one workgroup): the exact counts are the
+// cursors' advances; level-2 chunk map from them.  If a region was too
+// small (or `force`), the counts are cleared instead and *l1_over stays set,
+// which opens the gated exact pass that follows.
+__global__ __launch_bounds__(LS_WG) void ls_fin1_kernel(LsModel* md, LsBins bn, uint32_t chk, int force) {
+  __shared__ uint32_t ch[LS_MAX_BINS], choff[LS_MAX_BINS], tmp[LS_WG];
+  __shared__ uint32_t tch;
+  const uint32_t nbc = md->nbins_c;
+  if (force || md->l1_over) {  // workgroup-uniform
+    for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) bn.cnt_c[i] = 0;
+    if (threadIdx.x == 0) md->l1_over = 1;
+    return;
+  }
+  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) {
+    const uint32_t c = bn.cursor_c[i] - bn.off_c[i];
+    bn.cnt_c[i] = c;
+    ch[i] = (c + chk - 1) / chk;
+  }
+  __syncthreads();
+  ls_block_scan(ch, choff, nbc, tmp, &tch);
+  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) bn.chunk_start[i] = choff[i];
+  if (threadIdx.x == 0) {
     bn.chunk_start[nbc] = tch;
     md->total_chunks = tch;
   }
@@ -618,67 +707,87 @@ struct LsScatterLds {
   uint32_t total;
 };
 
-// Level 1 scatter: chunk blockIdx.x of the input into coarse buckets.
-// (chunks as in ls_hist1_kernel)
+// Level 1 scatter: chunks blockIdx.x, blockIdx.x + gridDim.x, ... of the
+// input into coarse buckets (chunks as in ls_hist1_kernel).  gate as in
+// ls_hist1_kernel.  over: if non-null the regions are estimated, and a
+// reservation that would pass its region's end (off_c[bin + 1]) writes
+// nothing and sets *over (the exact pass then redoes the level).
+constexpr uint32_t LS_NO_ROOM = 0xFFFFFFFFu;
 template <class K>
 __global__ __launch_bounds__(LS_WG) void ls_scatter1_kernel(const K* __restrict__ keys, uint32_t nch,
                                                             uint32_t last_len, const LsModel* md, LsBins bn,
-                                                            K* __restrict__ out, Rebind rkeys) {
+                                                            K* __restrict__ out, Rebind rkeys, const int* gate,
+                                                            int* over) {
   __shared__ LsTable tb;
   __shared__ LsScatterLds<K> L;
+  if (gate && *gate == 0) return;
   keys = rebind(keys, rkeys);
   ls_load_table(md, &tb);
   const uint32_t nbc = md->nbins_c;
-  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) L.cnt[i] = 0;
   __syncthreads();
   const LsUni U = ls_uni(&tb);
   constexpr int CHK = ls_chk<K>();
   constexpr int R = CHK / LS_WG;
-  const uint32_t lim = blockIdx.x + 1 < nch ? uint32_t(CHK) : last_len;
-  const K* kb = keys + uint64_t(blockIdx.x) * CHK;
-  K kv[R];
-  uint32_t bin[R], rk[R];
-  // full chunks (all but the last) run without per-element bounds checks
-  auto rank = [&](auto fullc) {
-    constexpr bool FULL = decltype(fullc)::value;
+  for (uint32_t ci = blockIdx.x; ci < nch; ci += gridDim.x) {
+    for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) L.cnt[i] = 0;
+    __syncthreads();
+    const uint32_t lim = ci + 1 < nch ? uint32_t(CHK) : last_len;
+    const K* kb = keys + uint64_t(ci) * CHK;
+    K kv[R];
+    uint32_t bin[R], rk[R];
+    // full chunks (all but the last) run without per-element bounds checks
+    auto rank = [&](auto fullc) {
+      constexpr bool FULL = decltype(fullc)::value;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
-      kv[r] = (FULL || i < lim) ? kb[i] : K(0);
-    }
+      for (int r = 0; r < R; ++r) {
+        const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
+        kv[r] = (FULL || i < lim) ? kb[i] : K(0);
+      }
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
-      if (FULL || i < lim) {
-        bin[r] = ls_bucket(&tb, U, kv[r]) >> U.fine_bits;
-        rk[r] = atomicAdd(&L.cnt[bin[r]], 1u);
+      for (int r = 0; r < R; ++r) {
+        const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
+        if (FULL || i < lim) {
+          bin[r] = ls_bucket(&tb, U, kv[r]) >> U.fine_bits;
+          rk[r] = atomicAdd(&L.cnt[bin[r]], 1u);
+        }
+      }
+    };
+    auto stage = [&](auto fullc) {
+      constexpr bool FULL = decltype(fullc)::value;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
+        if (FULL || i < lim) {
+          const uint32_t p = L.off[bin[r]] + rk[r];
+          L.stage[p] = kv[r];
+          if constexpr (LS_SBIN) L.sbin[p] = uint16_t(bin[r]);
+        }
+      }
+    };
+    const bool full = lim == uint32_t(CHK);
+    if (full) rank(std::true_type{}); else rank(std::false_type{});
+    __syncthreads();
+    ls_block_scan(L.cnt, L.off, nbc, L.tmp, &L.total);
+    for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) {
+      const uint32_t c = L.cnt[i];
+      if (c) {
+        const uint32_t g = atomicAdd(&bn.cursor_c[i], c);
+        if (over && uint64_t(g) + c > bn.off_c[i + 1]) {
+          L.gb[i] = LS_NO_ROOM;
+          *over = 1;
+        } else {
+          L.gb[i] = g;
+        }
       }
     }
-  };
-  auto stage = [&](auto fullc) {
-    constexpr bool FULL = decltype(fullc)::value;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const uint32_t i = threadIdx.x + uint32_t(r) * LS_WG;
-      if (FULL || i < lim) {
-        const uint32_t p = L.off[bin[r]] + rk[r];
-        L.stage[p] = kv[r];
-        if constexpr (LS_SBIN) L.sbin[p] = uint16_t(bin[r]);
-      }
+    if (full) stage(std::true_type{}); else stage(std::false_type{});
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < L.total; i += LS_WG) {
+      const K x = L.stage[i];
+      const uint32_t b = LS_SBIN ? uint32_t(L.sbin[i]) : ls_bucket(&tb, U, x) >> U.fine_bits;
+      const uint32_t g = L.gb[b];
+      if (g != LS_NO_ROOM) out[g + (i - L.off[b])] = x;
     }
-  };
-  const bool full = lim == uint32_t(CHK);
-  if (full) rank(std::true_type{}); else rank(std::false_type{});
-  __syncthreads();
-  ls_block_scan(L.cnt, L.off, nbc, L.tmp, &L.total);
-  for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG)
-    if (L.cnt[i]) L.gb[i] = atomicAdd(&bn.cursor_c[i], L.cnt[i]);
-  if (full) stage(std::true_type{}); else stage(std::false_type{});
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < L.total; i += LS_WG) {
-    const K x = L.stage[i];
-    const uint32_t b = LS_SBIN ? uint32_t(L.sbin[i]) : ls_bucket(&tb, U, x) >> U.fine_bits;
-    out[L.gb[b] + (i - L.off[b])] = x;
   }
 }
 
@@ -693,7 +802,7 @@ __device__ __forceinline__ bool ls_chunk(const LsModel* md, const LsBins& bn, ui
   }
   *c = a;
   const uint32_t j = w - bn.chunk_start[a];
-  const uint32_t s = bn.off_c[a] + j * chk, e = bn.off_c[a + 1];
+  const uint32_t s = bn.off_c[a] + j * chk, e = bn.off_c[a] + bn.cnt_c[a];
   *lo = s;
   *hi = s + chk < e ? s + chk : e;
   return true;

@@ -151,3 +151,11 @@ def test_temp_bytes_of_every_form():
     assert b64 > msort.ms_temp_bytes_learned(1 << 24, msort.MS_KEY_U32) > 0
     assert b64 >= 16 * (1 << 24)
     assert msort.ms_temp_bytes_learned(1 << 24, 7) == 0
+    # from 2^23 keys the first-level buffer takes the estimated regions'
+    # slack (a quarter of n plus a margin per coarse bucket); the exact
+    # pass alone needs n keys
+    est = msort.ms_temp_bytes_learned(1 << 23)
+    exact = msort.ms_temp_bytes_learned(1 << 23, coarse_estimate=0)
+    assert est > exact + 4 * (1 << 23) // 4
+    assert msort.ms_temp_bytes_learned((1 << 23) - 1) <= exact
+    assert msort.ms_temp_bytes_learned(1 << 23, coarse_estimate=3) == 0
