@@ -170,7 +170,10 @@ __global__ __launch_bounds__(256) void partition_kernel(const K* __restrict__ sr
 // or the tile's end picks the piece per lane.  All IPT loads of a thread are
 // issued before the first LDS write waits on them.  Slots at or past c[NP]
 // receive unspecified values and are never read.
-template <int NP, int WG, int IPT, int PAD, bool PAIRS, class K, class VV>
+// GAPS > 0 leaves GAPS slots after every piece: element e of piece p goes to
+// slot e + p * GAPS, and an element past the tile (e >= c[NP]) to slot
+// e + NP * GAPS, beyond the last piece's gap.
+template <int NP, int WG, int IPT, int PAD, bool PAIRS, int GAPS = 0, class K, class VV>
 __device__ __forceinline__ void stage_pieces(const K* __restrict__ src_k, const VV* __restrict__ src_v,
                                              const uint64_t (&D)[NP], const uint32_t (&c)[NP + 1],
                                              K* __restrict__ sk, VV* __restrict__ sv) {
@@ -179,21 +182,25 @@ __device__ __forceinline__ void stage_pieces(const K* __restrict__ src_k, const 
   const uint32_t wbase = wave_uniform(tid & ~63u);
   K kv[IPT];
   VV vv[PAIRS ? IPT : 1];
+  uint32_t gofs[GAPS ? IPT : 1];
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
     const uint32_t cb = wbase + uint32_t(r) * WG;  // the wavefront's first element of this step
     uint32_t pend = c[1];
     uint64_t Dp = D[0];
+    uint32_t gp = 0;
 #pragma unroll
     for (int k = 1; k < NP; ++k) {
       if (cb >= c[k]) {
         pend = c[k + 1];
         Dp = D[k];
+        gp = uint32_t(k) * GAPS;
       }
     }
     if (cb + 63u < pend) {  // wavefront-uniform: the chunk is inside one piece
       kv[r] = (src_k + (Dp + cb))[lane];
       if constexpr (PAIRS) vv[r] = (src_v + (Dp + cb))[lane];
+      if constexpr (GAPS > 0) gofs[r] = gp;
     } else {
       const uint32_t e = cb + lane;
       if (e < c[NP]) {
@@ -203,14 +210,62 @@ __device__ __forceinline__ void stage_pieces(const K* __restrict__ src_k, const 
         kv[r] = src_k[De + e];
         if constexpr (PAIRS) vv[r] = src_v[De + e];
       }
+      if constexpr (GAPS > 0) {
+        uint32_t g = 0;
+#pragma unroll
+        for (int k = 1; k <= NP; ++k) g += e >= c[k] ? uint32_t(GAPS) : 0u;
+        gofs[r] = g;
+      }
     }
   }
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
     const uint32_t e = tid + uint32_t(r) * WG;
-    sk[lds_pad<PAD>(e)] = kv[r];
-    if constexpr (PAIRS) sv[lds_pad<PAD>(e)] = vv[r];
+    if constexpr (GAPS > 0) {
+      sk[lds_pad<PAD>(e + gofs[r])] = kv[r];
+    } else {
+      sk[lds_pad<PAD>(e)] = kv[r];
+      if constexpr (PAIRS) sv[lds_pad<PAD>(e)] = vv[r];
+    }
   }
+}
+
+// Keys-only serial merge of IPT outputs from two runs of s[] that are each
+// followed by at least IPT + 1 slots holding the type's largest key: the
+// current elements are s[ia] and s[jb], the second run's wins only when
+// strictly smaller.  After a run is used up its current element is that
+// largest key, which loses to every smaller key; against an equal key either
+// choice writes the same value (every output still to come is that key), so
+// the loop tests no bounds.  Reads stay within IPT + 1 slots past a run's end.
+template <int IPT, int PAD, class K>
+__device__ __forceinline__ void merge_run_sentinel(const K* __restrict__ s, uint32_t ia, uint32_t jb,
+                                                   K (&ko)[IPT]) {
+  K a = s[lds_pad<PAD>(ia)], b = s[lds_pad<PAD>(jb)];
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const bool tb = b < a;
+    ko[r] = tb ? b : a;
+    const uint32_t nx = (tb ? jb : ia) + 1u;
+    const K x = s[lds_pad<PAD>(nx)];
+    ia = tb ? ia : nx;
+    jb = tb ? nx : jb;
+    a = tb ? a : x;
+    b = tb ? x : b;
+  }
+}
+
+// Merge-path split at diagonal d of merge(s[pa, pa + la), s[pb, pb + lb))
+// (the first run wins ties): the number of its elements among the first d
+// outputs.
+template <int PAD, class K>
+__device__ __forceinline__ uint32_t lds_split(const K* __restrict__ s, uint32_t pa, uint32_t la, uint32_t pb,
+                                              uint32_t lb, uint32_t d) {
+  uint32_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
+  while (lo < hi) {
+    const uint32_t m = (lo + hi) >> 1;
+    if (s[lds_pad<PAD>(pb + d - 1 - m)] < s[lds_pad<PAD>(pa + m)]) hi = m; else lo = m + 1;
+  }
+  return lo;
 }
 
 template <class K, class V, int WG, int IPT, int PAD>
@@ -584,11 +639,103 @@ struct Merge4Tile {
   static constexpr size_t V1_OFF = al16(sizeof(K) * SLOTS);
   static constexpr size_t K2_OFF = V1_OFF + (PAIRS ? al16(sizeof(VV) * SLOTS) : 0);
   static constexpr size_t I2_OFF = K2_OFF + (REUSE ? 0 : al16(sizeof(K) * SLOTS));
-  static constexpr size_t LDS_BYTES = I2_OFF + (PAIRS ? al16(sizeof(uint16_t) * SLOTS) : 0);
+  static constexpr size_t LDS_BYTES_BOUNDED = I2_OFF + (PAIRS ? al16(sizeof(uint16_t) * SLOTS) : 0);
+  // Keys only with separate stage buffers (REUSE = 0): the sentinel form
+  // below.  GAP slots of the largest key follow each of the four pieces
+  // (buffer 1) and each stage-1 result (buffer 2); GAP >= IPT + 1 and a
+  // multiple of 16 bytes, so that the second result stays vector-aligned.
+  // (With REUSE the straddling thread would have to hold two output sets
+  // across the barrier, which costs 64-bit keys occupancy: those keep the
+  // bounded form.)
+  static constexpr bool SENTINEL = !PAIRS && !REUSE;
+  static constexpr uint32_t GAP = uint32_t(((IPT + 1) * sizeof(K) + 15) / 16 * 16 / sizeof(K));
+  static constexpr uint32_t SLOTS1 = lds_padded_size<PAD>(TM + 4 * GAP);
+  static constexpr uint32_t SLOTS2 = lds_padded_size<PAD>(TM + 2 * GAP);
+  static constexpr size_t KK2_OFF = al16(sizeof(K) * SLOTS1);
+  static constexpr size_t LDS_BYTES_SENTINEL = KK2_OFF + al16(sizeof(K) * SLOTS2);
+  static constexpr size_t LDS_BYTES = SENTINEL ? LDS_BYTES_SENTINEL : LDS_BYTES_BOUNDED;
+
+  // Keys only, REUSE = 0.  Buffer 1 holds P0..P3 at o[p] = c[p] + p * GAP, each followed
+  // by GAP largest keys; X = merge(P0, P1) goes to buffer 2 at [0, c2) and
+  // Y = merge(P2, P3) at [c2 + GAP, total + GAP), each followed by GAP largest
+  // keys.  Thread t owns outputs e0 = t * IPT .. e0 + IPT of X|Y in stage 1
+  // and of merge(X, Y) in stage 2; outputs it computes past its run's end are
+  // largest keys and land in that run's gap.  The one thread whose stage-1
+  // outputs straddle c2 also computes Y's first IPT outputs (the next thread
+  // writes the same values to the ones it owns).
+  static __device__ __forceinline__ void run_keys(const K* __restrict__ src_k, K* __restrict__ dst_k,
+                                                  const uint64_t (&s)[4], const uint32_t (&l)[4], uint64_t o0,
+                                                  unsigned char* smem) {
+    const uint32_t tid = threadIdx.x;
+    K* k1 = reinterpret_cast<K*>(smem);
+    K* k2 = reinterpret_cast<K*>(smem + KK2_OFF);
+    const uint32_t c1 = l[0], c2 = c1 + l[1], c3 = c2 + l[2], total = c3 + l[3];
+    const uint32_t o1 = c1 + GAP, o2 = c2 + 2 * GAP, o3 = c3 + 3 * GAP;
+    const K SENT = key_max<K>();
+    // stage 0: P0..P3 into buffer 1, then the gaps
+    {
+      const uint64_t D[4] = {s[0], s[1] - c1, s[2] - c2, s[3] - c3};
+      const uint32_t c[5] = {0u, c1, c2, c3, total};
+      stage_pieces<4, WG, IPT, PAD, false, GAP>(src_k, static_cast<const int*>(nullptr), D, c, k1,
+                                                static_cast<int*>(nullptr));
+      const uint32_t ce[4] = {c1, c2, c3, total};
+      for (uint32_t g = tid; g < 4 * GAP; g += WG) {
+        const uint32_t p = g / GAP;
+        k1[lds_pad<PAD>(ce[p] + p * GAP + (g - p * GAP))] = SENT;
+      }
+      for (uint32_t g = tid; g < 2 * GAP; g += WG) k2[lds_pad<PAD>(g < GAP ? c2 + g : total + g)] = SENT;
+    }
+    __syncthreads();
+    const uint32_t e0 = tid * IPT;
+    // stage 1
+    const bool second = e0 >= c2;
+    const bool straddle = !second && c2 < e0 + IPT;
+    K ko1[IPT], koy[IPT];
+    if (e0 < total) {
+      const uint32_t pa = second ? o2 : 0u, la = second ? l[2] : l[0];
+      const uint32_t pb = second ? o3 : o1, lb = second ? l[3] : l[1];
+      const uint32_t d = second ? e0 - c2 : e0;
+      const uint32_t x = lds_split<PAD>(k1, pa, la, pb, lb, d);
+      merge_run_sentinel<IPT, PAD>(k1, pa + x, pb + d - x, ko1);
+      if (straddle) merge_run_sentinel<IPT, PAD>(k1, o2, o3, koy);
+    }
+    if (e0 < total) {
+      const uint32_t w = second ? e0 + GAP : e0;  // buffer-2 slot of output e0
+      if constexpr (PAD == 0 && (IPT * sizeof(K)) % 16 == 0 && (GAP * sizeof(K)) % 16 == 0) {
+        store_run<K, IPT>(k2 + w, ko1);
+      } else {
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) k2[lds_pad<PAD>(w + r)] = ko1[r];
+      }
+      if (straddle) {
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) k2[lds_pad<PAD>(c2 + GAP + r)] = koy[r];
+      }
+    }
+    __syncthreads();
+    // stage 2: merge(X, Y) -> global
+    if (e0 >= total) return;
+    const uint32_t x = lds_split<PAD>(k2, 0u, c2, c2 + GAP, total - c2, e0);
+    K ko[IPT];
+    merge_run_sentinel<IPT, PAD>(k2, x, c2 + GAP + (e0 - x), ko);
+    const uint32_t cnt = total - e0 < uint32_t(IPT) ? total - e0 : uint32_t(IPT);
+    K* out = dst_k + o0 + e0;
+    if (cnt == IPT && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+      store_run<K, IPT>(out, ko);
+    } else {
+#pragma unroll
+      for (int r = 0; r < IPT; ++r)
+        if (uint32_t(r) < cnt) out[r] = ko[r];
+    }
+  }
 
   static __device__ __forceinline__ void run(const K* __restrict__ src_k, const VV* __restrict__ src_v,
                                              K* __restrict__ dst_k, VV* __restrict__ dst_v, const uint64_t (&s)[4],
                                              const uint32_t (&l)[4], uint64_t o0, unsigned char* smem) {
+    if constexpr (SENTINEL) {
+      run_keys(src_k, dst_k, s, l, o0, smem);
+      return;
+    }
     const uint32_t tid = threadIdx.x;
     K* k1 = reinterpret_cast<K*>(smem + K1_OFF);
     VV* v1 = reinterpret_cast<VV*>(smem + V1_OFF);
