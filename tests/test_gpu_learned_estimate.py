@@ -144,3 +144,23 @@ def test_pairs_with_the_estimate(gpu, mode):
     assert_equal_arrays(from_dev(v, np.uint32), ev, f"pairs values, coarse_estimate={mode}")
     assert st["coarse_recounted"] == (1 if mode == 2 else 0), st
 
+
+
+@pytest.mark.parametrize("dist", ["equal", "two_values", "sorted", "reverse"])
+def test_degenerate_inputs_with_the_estimate(gpu, dist):
+    """All keys in one coarse bin, two bins, and inputs already in (reverse)
+    order: every region bound still holds its bin's keys or the exact pass
+    takes over; the output is the oracle's either way."""
+    n = EST_FROM + 17
+    rng = np.random.default_rng(31)
+    if dist == "equal":
+        keys = np.full(n, 123456789, np.uint32)
+    elif dist == "two_values":
+        keys = np.where(rng.random(n) < 0.3, 5, 4_000_000_000).astype(np.uint32)
+    elif dist == "sorted":
+        keys = np.sort(rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32))
+    else:
+        keys = np.sort(rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32))[::-1].copy()
+    got, st = learned(keys, gpu)
+    assert_equal_arrays(got, oracle.sort(keys, threads=oracle.host_threads()), "estimate, " + dist)
+    assert st["misordered"] == 0, st
