@@ -230,6 +230,41 @@ __device__ __forceinline__ void stage_pieces(const K* __restrict__ src_k, const 
   }
 }
 
+// Stage 0 of the padded-run form for a tile whose pieces lie within 2^32
+// bytes of the first: per lane, in vector registers, with 32-bit offsets
+// from the first piece's base (no per-chunk scalar piece selection).
+// Element e of piece p (c[p] <= e < c[p+1]) is base[inc[1] + ... + inc[p] + e]
+// (inc[k] = D[k] - D[k-1] >= 0) and goes to slot e + p * GAPS; elements past
+// the tile go to slot e + 4 * GAPS and are not loaded.
+template <int WG, int IPT, int PAD, int GAPS, class K>
+__device__ __forceinline__ void stage_pieces_rel(const K* __restrict__ base, const uint32_t (&inc)[4],
+                                                 const uint32_t (&c)[5], K* __restrict__ sk) {
+  const uint32_t tid = threadIdx.x;
+  K kv[IPT];
+  auto load = [&](auto fullc) {
+    constexpr bool FULL = decltype(fullc)::value;  // a whole tile: every element is loaded
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+      const uint32_t e = tid + uint32_t(r) * WG;
+      uint32_t off = e;
+#pragma unroll
+      for (int k = 1; k < 4; ++k) off += e >= c[k] ? inc[k] : 0u;
+      if constexpr (FULL) kv[r] = base[off];
+      else kv[r] = e < c[4] ? base[off] : K(0);
+    }
+  };
+  if (c[4] == uint32_t(WG * IPT)) load(std::true_type{}); else load(std::false_type{});
+  // slots recomputed here rather than kept from the loads (registers)
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const uint32_t e = tid + uint32_t(r) * WG;
+    uint32_t sl = e;
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) sl += e >= c[k] ? uint32_t(GAPS) : 0u;
+    sk[lds_pad<PAD>(sl)] = kv[r];
+  }
+}
+
 // Keys-only serial merge of IPT outputs from two runs of s[] that are each
 // followed by at least IPT + 1 slots holding the type's largest key: the
 // current elements are s[ia] and s[jb], the second run's wins only when
@@ -676,8 +711,13 @@ struct Merge4Tile {
     {
       const uint64_t D[4] = {s[0], s[1] - c1, s[2] - c2, s[3] - c3};
       const uint32_t c[5] = {0u, c1, c2, c3, total};
-      stage_pieces<4, WG, IPT, PAD, false, GAP>(src_k, static_cast<const int*>(nullptr), D, c, k1,
-                                                static_cast<int*>(nullptr));
+      if ((D[3] - D[0] + uint64_t(TM)) * sizeof(K) < (uint64_t(1) << 32)) {
+        const uint32_t inc[4] = {0u, uint32_t(D[1] - D[0]), uint32_t(D[2] - D[1]), uint32_t(D[3] - D[2])};
+        stage_pieces_rel<WG, IPT, PAD, GAP>(src_k + D[0], inc, c, k1);
+      } else {
+        stage_pieces<4, WG, IPT, PAD, false, GAP>(src_k, static_cast<const int*>(nullptr), D, c, k1,
+                                                  static_cast<int*>(nullptr));
+      }
       const uint32_t ce[4] = {c1, c2, c3, total};
       for (uint32_t g = tid; g < 4 * GAP; g += WG) {
         const uint32_t p = g / GAP;
