@@ -463,9 +463,9 @@ static ms_status learned_pairs(K32* keys, V* vals, ms_key_type kt, uint64_t n, c
 
 // Automatic choice of the learned form (MS_ALGO_AUTO): from the sizes at
 // which it was measured faster than the plain sort on one MI355X -- 32-bit
-// keys from 2^27 (uniform uint32 1.2x there, normal int32 1.17x; 0.87x at
-// 2^26), 64-bit keys from 2^26 (normal int64 1.10x, uniform uint64 1.31x;
-// 0.87x and 1.06x at 2^25).
+// keys from 2^27 (uniform uint32 and the lognormal mixture 1.20x there;
+// 0.85-0.89x at 2^26), 64-bit keys from 2^26 (normal int64 1.19x, uniform
+// uint64 1.49x; 0.92x and 1.15x at 2^25).
 static bool learned_auto(ms_key_type kt, uint64_t n) {
   const bool wide = kt == MS_KEY_U64 || kt == MS_KEY_I64;
   return n >= (uint64_t(1) << (wide ? 26 : 27));
