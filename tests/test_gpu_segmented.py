@@ -35,7 +35,9 @@ def offsets_of(lens):
 def test_class_boundaries(gpu, kdt, vdt):
     rng = np.random.default_rng(21)
     off = offsets_of(BOUNDARY_LENS)
-    for dist in ("uniform", "few"):
+    # extremes: heavy ties at the type's largest key, which the keys-only
+    # merges also use to pad their runs in LDS
+    for dist in ("uniform", "few", "extremes"):
         k = keys_fill(int(off[-1]), kdt, dist, rng)
         v = None if vdt is None else np.arange(off[-1], dtype=vdt)
         gk, gv = run_seg(k, off, v, gpu)
@@ -56,7 +58,8 @@ FAMILIES = [(np.uint32, None, msort.MS_KEY_U32), (np.uint32, np.uint32, msort.MS
                          ids=lambda d: "none" if d is None else (np.dtype(d).name if not isinstance(d, int) else str(d)))
 def test_every_class_candidate(gpu, kdt, vdt, kt):
     """Each compiled per-class shape of every tuned family sorts correctly
-    (tuning table entries), against the oracle, heavy ties."""
+    (tuning table entries), against the oracle, heavy ties (few values, and
+    values at the type's limits)."""
     rng = np.random.default_rng(22)
     vb = 0 if vdt is None else np.dtype(vdt).itemsize
     classes = msort.ms_seg_classes(kt, vb)
@@ -66,17 +69,18 @@ def test_every_class_candidate(gpu, kdt, vdt, kt):
             lo = 2 if c == 0 else classes[c - 1][0] + 1
             lens = np.concatenate([[lo, bound, (lo + bound) // 2], rng.integers(lo, bound + 1, size=40)])
             off = offsets_of(lens)
-            k = keys_fill(int(off[-1]), kdt, "few", rng)
-            v = None if vdt is None else np.arange(off[-1], dtype=vdt)
-            exp = oracle.segmented_sort(k, off, v)
-            for wg, ipt in shapes:
-                msort.ms_tuning_set(kt, vb, c, wg, ipt)
-                gk, gv = run_seg(k, off, v, gpu)
-                if v is None:
-                    assert_equal_arrays(gk, exp, f"class {c} shape {wg}x{ipt}")
-                else:
-                    assert_equal_arrays(gk, exp[0], f"class {c} shape {wg}x{ipt} keys")
-                    assert_equal_arrays(gv, exp[1], f"class {c} shape {wg}x{ipt} values")
+            for dist in ("few", "extremes"):
+                k = keys_fill(int(off[-1]), kdt, dist, rng)
+                v = None if vdt is None else np.arange(off[-1], dtype=vdt)
+                exp = oracle.segmented_sort(k, off, v)
+                for wg, ipt in shapes:
+                    msort.ms_tuning_set(kt, vb, c, wg, ipt)
+                    gk, gv = run_seg(k, off, v, gpu)
+                    if v is None:
+                        assert_equal_arrays(gk, exp, f"class {c} shape {wg}x{ipt} {dist}")
+                    else:
+                        assert_equal_arrays(gk, exp[0], f"class {c} shape {wg}x{ipt} {dist} keys")
+                        assert_equal_arrays(gv, exp[1], f"class {c} shape {wg}x{ipt} {dist} values")
     finally:
         for c, (wg, ipt) in enumerate(saved):
             msort.ms_tuning_set(kt, vb, c, wg, ipt)
