@@ -164,3 +164,16 @@ def test_degenerate_inputs_with_the_estimate(gpu, dist):
     got, st = learned(keys, gpu)
     assert_equal_arrays(got, oracle.sort(keys, threads=oracle.host_threads()), "estimate, " + dist)
     assert st["misordered"] == 0, st
+
+
+@pytest.mark.parametrize("n", [(1 << 22) + 5, EST_FROM + 5])
+def test_keys_at_the_limits(gpu, n):
+    """A tenth of the keys at the largest uint32 and a twentieth at 0 among
+    the mixture: ties with the key the bucket sort pads its LDS runs with."""
+    keys = workloads.lognormal_mix_u32(n, seed=41).view(torch.int32).numpy().view(np.uint32).copy()
+    rng = np.random.default_rng(42)
+    keys[rng.random(n) < 0.1] = np.uint32(0xFFFFFFFF)
+    keys[rng.random(n) < 0.05] = np.uint32(0)
+    got, st = learned(keys, gpu)
+    assert_equal_arrays(got, oracle.sort(keys, threads=oracle.host_threads()), f"keys at the limits, n={n}")
+    assert st["misordered"] == 0, st
