@@ -178,12 +178,18 @@ __global__ __launch_bounds__(256) void ls_sample_kernel(const K* __restrict__ ke
 // unit h is relu(x - k_h) with output weight = slope change at k_h.
 template <class K>
 __global__ void ls_init_kernel(const K* __restrict__ sample, uint32_t S, LsModel* md) {
+  // working arrays in LDS rather than in private (scratch) memory
+  __shared__ double k[LS_H + 1], y[LS_H + 1];
   if (threadIdx.x != 0) return;
-  double k[LS_H + 1], y[LS_H + 1];
+  // the knots' sample keys, all loads issued before the first is used
+  K sk[LS_H + 1];
+#pragma unroll
+  for (int i = 0; i <= LS_H; ++i) sk[i] = sample[uint32_t((uint64_t(i) * (S - 1)) / LS_H)];
   int m = 0;
+#pragma unroll
   for (int i = 0; i <= LS_H; ++i) {
     const uint32_t q = uint32_t((uint64_t(i) * (S - 1)) / LS_H);
-    const double kk = double(ls_key_feature(sample[q], md->log_feature, md->off64, md->scale64));
+    const double kk = double(ls_key_feature(sk[i], md->log_feature, md->off64, md->scale64));
     const double yy = (double(q) + 0.5) / double(S);
     if (m > 0 && k[m - 1] == kk) {
       y[m - 1] = yy;  // keep the last of a run of equal knots
@@ -330,13 +336,23 @@ __global__ __launch_bounds__(LS_TRAIN_WG) void ls_train_kernel(const K* __restri
 template <class K>
 __global__ void ls_compile_kernel(LsModel* md, int final_parity, const K* __restrict__ sample, uint32_t S,
                                   const int* gate) {
+  // the working arrays in LDS rather than in private (scratch) memory, which
+  // the indexed accesses below would otherwise use
+  __shared__ double t[LS_H + 2], pts[LS_H + 2], V[LS_H + 2];
   if (gate && *gate == 0) return;
   if (threadIdx.x != 0) return;
-  const float* th = md->theta[final_parity];
+  // the parameters in registers: the loops below read each of them many
+  // times, and as loads beside the table's stores they would stay loads
+  float th[LS_P];
+  {
+    const float* thg = md->theta[final_parity];
+#pragma unroll
+    for (int p = 0; p < LS_P; ++p) th[p] = thg[p];
+  }
   const double xmin = ls_key_feature(sample[0], md->log_feature, md->off64, md->scale64);
   const double xmax = ls_key_feature(sample[S - 1], md->log_feature, md->off64, md->scale64);
-  double t[LS_H + 2];
   int nt = 0;
+#pragma unroll
   for (int h = 0; h < LS_H; ++h) {
     const double w1 = th[h], b1 = th[LS_H + h];
     if (w1 != 0.0) {
@@ -351,17 +367,16 @@ __global__ void ls_compile_kernel(LsModel* md, int final_parity, const K* __rest
     t[j + 1] = x;
   }
   // ends plus the interior points that are distinct floats strictly inside
-  double pts[LS_H + 2];
   int np = 0;
   pts[np++] = xmin;
   for (int i = 0; i < nt; ++i)
     if (float(t[i]) > float(pts[np - 1]) && float(t[i]) < float(xmax)) pts[np++] = t[i];
   pts[np++] = xmax;
   const double lo = 0.5 / double(S), hi = 1.0 - 0.5 / double(S);
-  double V[LS_H + 2];
   double run = -1e300;
   for (int i = 0; i < np; ++i) {
     double F = th[3 * LS_H];
+#pragma unroll
     for (int h = 0; h < LS_H; ++h) {
       const double z = double(th[h]) * pts[i] + double(th[LS_H + h]);
       if (z > 0.0) F += double(th[2 * LS_H + h]) * z;

@@ -175,7 +175,8 @@ ms_status seg_enqueue(K* keys, V* vals, const int64_t* off, uint64_t nseg, uint6
   const uint64_t cus = uint64_t(device_cu_count());
 
   seg_init_kernel<<<1, 64, 0, s>>>(st);
-  seg_classify_kernel<K, V><<<dim3(unsigned(ceil_div(nseg, 256))), dim3(256), 0, s>>>(off, nseg, st);
+  seg_classify_kernel<K, V><<<dim3(unsigned(ceil_div(nseg, 256 * SEG_CLASSIFY_PER))), dim3(256), 0, s>>>(off, nseg,
+                                                                                                        st);
   seg_owner_kernel<K, V><<<dim3(unsigned(std::min<uint64_t>(nseg, cus * 4))), dim3(256), 0, s>>>(off, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "segment classification launch");

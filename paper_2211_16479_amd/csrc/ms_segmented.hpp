@@ -141,41 +141,50 @@ static __global__ void seg_init_kernel(SegState st) {
   }
 }
 
-// One thread per segment.  Slots are reserved in two steps so that a batch
-// of many small segments does not serialise on one global counter: threads
+// SEG_CLASSIFY_PER segments per thread (segment base + p * blockDim.x +
+// thread, coalesced).  Slots are reserved in two steps so that a batch of
+// many small segments does not serialise on one global counter: threads
 // first count into workgroup-local LDS counters, then one thread per class
-// adds the workgroup's total to the global counter, and every thread's slot
-// is the global base plus its local offset.  (Order inside a class queue is
-// arbitrary; each segment is sorted independently, so results do not depend
-// on it.)  The large class uses one packed counter (segments << 40 | merge
-// tiles) so that slot order and merge-tile order agree.
+// adds the workgroup's total to the global counter, and every segment's
+// slot is the global base plus its local offset.  (Order inside a class
+// queue is arbitrary; each segment is sorted independently, so results do
+// not depend on it.)  The large class uses one packed counter (segments <<
+// 40 | merge tiles) so that slot order and merge-tile order agree.
+constexpr int SEG_CLASSIFY_PER = 8;
 template <class K, class V>
 __global__ __launch_bounds__(256) void seg_classify_kernel(const int64_t* __restrict__ off, uint64_t nseg,
                                                            SegState st) {
   using S = SegCfg<K, V>;
+  constexpr int PER = SEG_CLASSIFY_PER;
   __shared__ uint32_t l_cnt[SEG_MAX_CLASSES];
   __shared__ uint32_t g_base[SEG_MAX_CLASSES];
   __shared__ unsigned long long l_large, g_large;
   off = seg_bind_off(st, off);
-  const uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const uint64_t s0 = uint64_t(blockIdx.x) * blockDim.x * PER + threadIdx.x;
   if (threadIdx.x < SEG_MAX_CLASSES) l_cnt[threadIdx.x] = 0;
   if (threadIdx.x == 0) l_large = 0;
   __syncthreads();
-  int c = -1;
-  uint64_t L = 0;
-  uint32_t local = 0;
-  unsigned long long llocal = 0;
-  if (s < nseg) {
-    const int64_t b = off[s], e = off[s + 1];
-    if (e - b > 1) {
-      L = uint64_t(e - b);
-      c = seg_class<K, V>(L);
-      if (c < S::NCLS) {
-        local = atomicAdd(&l_cnt[c], 1u);
-      } else {
-        const unsigned long long mt = ((L + S::TILE - 1) / S::TILE) * S::C;
-        llocal = atomicAdd(&l_large, (1ull << SEG_SLOT_SHIFT) | mt);
-        atomicMax(st.max_steps, uint32_t(seg_steps(seg_passes(L, S::TILE))));
+  int c[PER];
+  uint32_t local[PER];
+  unsigned long long llocal[PER];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const uint64_t s = s0 + uint64_t(p) * blockDim.x;
+    c[p] = -1;
+    local[p] = 0;
+    llocal[p] = 0;
+    if (s < nseg) {
+      const int64_t b = off[s], e = off[s + 1];
+      if (e - b > 1) {
+        const uint64_t L = uint64_t(e - b);
+        c[p] = seg_class<K, V>(L);
+        if (c[p] < S::NCLS) {
+          local[p] = atomicAdd(&l_cnt[c[p]], 1u);
+        } else {
+          const unsigned long long mt = ((L + S::TILE - 1) / S::TILE) * S::C;
+          llocal[p] = atomicAdd(&l_large, (1ull << SEG_SLOT_SHIFT) | mt);
+          atomicMax(st.max_steps, uint32_t(seg_steps(seg_passes(L, S::TILE))));
+        }
       }
     }
   }
@@ -184,14 +193,18 @@ __global__ __launch_bounds__(256) void seg_classify_kernel(const int64_t* __rest
     g_base[threadIdx.x] = atomicAdd(&st.cls_count[threadIdx.x], l_cnt[threadIdx.x]);
   if (threadIdx.x == 0 && l_large != 0) g_large = atomicAdd(st.large_ctr, l_large);
   __syncthreads();
-  if (c < 0) return;
-  if (c < S::NCLS) {
-    st.queues[uint64_t(c) * nseg + g_base[c] + local] = int32_t(s);
-  } else {
-    const unsigned long long at = g_large + llocal;
-    const uint64_t slot = at >> SEG_SLOT_SHIFT;
-    st.large_seg[slot] = int32_t(s);
-    st.large_mbase[slot] = int64_t(at & SEG_TILE_MASK);
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const uint64_t s = s0 + uint64_t(p) * blockDim.x;
+    if (c[p] < 0) continue;
+    if (c[p] < S::NCLS) {
+      st.queues[uint64_t(c[p]) * nseg + g_base[c[p]] + local[p]] = int32_t(s);
+    } else {
+      const unsigned long long at = g_large + llocal[p];
+      const uint64_t slot = at >> SEG_SLOT_SHIFT;
+      st.large_seg[slot] = int32_t(s);
+      st.large_mbase[slot] = int64_t(at & SEG_TILE_MASK);
+    }
   }
 }
 
