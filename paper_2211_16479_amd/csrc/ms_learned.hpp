@@ -793,7 +793,10 @@ __global__ __launch_bounds__(LS_WG) void ls_scatter1_kernel(const K* __restrict_
       const uint32_t c = L.cnt[i];
       if (c) {
         const uint32_t g = atomicAdd(&bn.cursor_c[i], c);
-        if (over && uint64_t(g) + c > bn.off_c[i + 1]) {
+        // checked on the keys the bin reserved before this chunk, g - off_c[i]
+        // (exact: fewer than n < 2^32), not on g itself, which passes 2^32
+        // and wraps when a region near the buffer's end is far too small
+        if (over && uint64_t(g - bn.off_c[i]) + c > uint64_t(bn.off_c[i + 1] - bn.off_c[i])) {
           L.gb[i] = LS_NO_ROOM;
           *over = 1;
         } else {
