@@ -198,7 +198,10 @@ ms_status ms_tuning_load(const char* path, const char* arch, int* applied);
  * spill.  The spill is sorted by the plain merge sort and merged back with
  * one exact merge-path pass.  If more than spill_threshold * n keys spill, or
  * the order check of the buckets fails, the plain merge sort sorts the input
- * instead (decided on the device).  The output is the same bytes as ms_sort's.
+ * instead (decided on the device); where the sorted sample already shows
+ * more than twice that many keys in over-full buckets (heavy ties), the plain
+ * sort runs before any pass over the input (stats.sample_fallback).  The
+ * output is the same bytes as ms_sort's.
  * ------------------------------------------------------------------------ */
 typedef enum ms_algo {
   MS_ALGO_AUTO = 0,            /* learned for 32-bit keys from n = 2^27 and 64-bit keys from 2^26
@@ -245,12 +248,17 @@ typedef struct ms_stats {
   int32_t fallback_taken;    /* the learned path handed over to the plain sort */
   int32_t misordered;        /* the bucket order check failed */
   int32_t repaired;          /* a spill was sorted and merged back */
-  uint64_t spilled;          /* keys in over-full buckets */
-  uint64_t max_bucket;       /* largest bucket */
+  uint64_t spilled;          /* keys in over-full buckets (estimated from the sample when
+                                sample_fallback is set) */
+  uint64_t max_bucket;       /* largest bucket (likewise) */
   uint64_t buckets;          /* number of buckets B */
   float loss_initial;        /* training loss at the start point */
   float loss_final;          /* training loss before the last step */
   int32_t coarse_recounted;  /* the estimated first-level regions were replaced by the exact pass */
+  int32_t sample_fallback;   /* the sorted sample already showed more than twice spill_threshold * n
+                                keys in over-full buckets (runs of sample keys that stand for at
+                                least twice a bucket's capacity each), so the plain sort ran with no
+                                pass of the learned form over the input */
 } ms_stats;
 
 /* Default options (as documented above). */

@@ -50,7 +50,8 @@ class MsStats(ctypes.Structure):
     _fields_ = [("algo_used", ctypes.c_int32), ("fallback_taken", ctypes.c_int32),
                 ("misordered", ctypes.c_int32), ("repaired", ctypes.c_int32), ("spilled", ctypes.c_uint64),
                 ("max_bucket", ctypes.c_uint64), ("buckets", ctypes.c_uint64), ("loss_initial", ctypes.c_float),
-                ("loss_final", ctypes.c_float), ("coarse_recounted", ctypes.c_int32)]
+                ("loss_final", ctypes.c_float), ("coarse_recounted", ctypes.c_int32),
+                ("sample_fallback", ctypes.c_int32)]
 
 
 _lib = None

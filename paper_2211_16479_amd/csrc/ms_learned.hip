@@ -32,6 +32,11 @@ __global__ void ls_setup_kernel(LsModel* md, int log_feature, int use_table, int
   md->off64 = 0;
   md->scale64 = 1.f;
   md->l1_over = 0;
+  md->sample_heavy = 0;
+  md->sample_run = 0;
+  md->sample_fb = 0;
+  md->sample_spill = 0;
+  md->sample_maxb = 0;
 }
 
 __global__ void ls_set_theta_kernel(LsModel* md, const float* theta) {
@@ -86,6 +91,7 @@ __global__ void ls_stats_kernel(const LsModel* md, ms_stats* st, uint64_t bucket
   st->loss_initial = md->loss0;
   st->loss_final = md->loss_last;
   st->coarse_recounted = md->l1_over;
+  st->sample_fallback = md->sample_fb;
 }
 
 // 1 for the log feature, 0 for the linear one.  MS_FEATURE_AUTO: log for
@@ -241,6 +247,17 @@ static ms_status learned_enqueue(K* keys, uint64_t n, const ms_options& o, ms_st
   st = ls_train_enqueue(sample, P.S, md, partial, int(o.train_steps), o.learning_rate, loss, true, s);
   if (st != MS_OK) return st;
   ls_compile_kernel<<<1, 64, 0, s>>>(md, int(o.train_steps) & 1, sample, P.S, nullptr);
+  // decision from the sample: runs of T sample keys in one bucket stand for
+  // at least twice its capacity (T >= 8, so that a bucket near its capacity
+  // rarely shows such a run by chance)
+  {
+    const uint64_t T = std::max<uint64_t>(8, ceil_div(uint64_t(2) * P.capacity * P.S, n));
+    if (T <= P.S) {
+      ls_sample_heavy_kernel<K><<<dim3(unsigned(ceil_div(P.S - T + 1, 256))), 256, 0, s>>>(sample, P.S,
+                                                                                         uint32_t(T), md);
+      ls_sample_decide_kernel<<<1, 64, 0, s>>>(md, n, P.S, P.spill_cap);
+    }
+  }
   // level 1
   // (gated stages run with a bounded grid: when skipped they cost little)
   const uint64_t gated_grid = uint64_t(device_cu_count()) * 4;

@@ -125,6 +125,11 @@ struct LsModel {
   uint64_t off64;        // keys other than uint32: feature offset (the sample's smallest unsigned image)
   float scale64;         // keys other than uint32: linear feature scale
   int l1_over;           // estimated first level: a region was too small (the exact pass runs)
+  // decision from the sorted sample, before any pass over the input
+  uint32_t sample_heavy; // sample windows that lie in one over-full bucket (ls_sample_heavy_kernel)
+  uint32_t sample_run;   // longest run of sample keys in one such bucket
+  int sample_fb;         // the sample shows too many keys in over-full buckets: fall back at once
+  unsigned long long sample_spill, sample_maxb;  // the windows' and the run's input keys (estimates)
 };
 
 // Keys other than uint32: the feature's offset and scale from the sorted
@@ -571,7 +576,7 @@ __global__ __launch_bounds__(LS_WG) void ls_hist1_kernel(const K* __restrict__ k
                                                          Rebind rk, const int* gate) {
   __shared__ LsTable tb;
   __shared__ uint32_t h[LS_MAX_BINS];
-  if (gate && *gate == 0) return;
+  if (md->sample_fb || (gate && *gate == 0)) return;
   keys = rebind(keys, rk);
   ls_load_table(md, &tb);
   const uint32_t nbc = md->nbins_c;
@@ -613,7 +618,7 @@ __global__ __launch_bounds__(LS_WG) void ls_hist1_kernel(const K* __restrict__ k
 __global__ __launch_bounds__(LS_WG) void ls_plan1_kernel(LsModel* md, LsBins bn, uint32_t chk, const int* gate) {
   __shared__ uint32_t cnt[LS_MAX_BINS], off[LS_MAX_BINS], ch[LS_MAX_BINS], choff[LS_MAX_BINS], tmp[LS_WG];
   __shared__ uint32_t total, tch;
-  if (gate && *gate == 0) return;
+  if (md->sample_fb || (gate && *gate == 0)) return;
   const uint32_t nbc = md->nbins_c;
   for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) {
     cnt[i] = bn.cnt_c[i];
@@ -634,6 +639,52 @@ __global__ __launch_bounds__(LS_WG) void ls_plan1_kernel(LsModel* md, LsBins bn,
   }
 }
 
+// Decision from the sorted sample, before any pass over the input.  The
+// bucket function is non-decreasing, so the T sample keys s[i .. i+T-1] lie
+// in one bucket exactly when b(s[i]) == b(s[i+T-1]); the host picks T so that
+// T sample keys stand for at least twice a bucket's capacity.  Counts such
+// windows (a run of L >= T sample keys in one bucket gives L - T + 1 of them)
+// and the longest run, whose first key's thread finds the run's end by a
+// binary search.  One thread per window start.
+template <class K>
+__global__ __launch_bounds__(256) void ls_sample_heavy_kernel(const K* __restrict__ sample, uint32_t S, uint32_t T,
+                                                              LsModel* md) {
+  __shared__ LsTable tb;
+  __shared__ uint32_t cnt;
+  ls_load_table(md, &tb);
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  const LsUni U = ls_uni(&tb);
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i + T - 1 < S) {  // T >= 2, S - T + 1 window starts
+    const uint32_t b = ls_bucket(&tb, U, sample[i]);
+    if (b == ls_bucket(&tb, U, sample[i + T - 1])) {
+      atomicAdd(&cnt, 1u);
+      if (i == 0 || ls_bucket(&tb, U, sample[i - 1]) != b) {
+        uint32_t lo = i + T - 1, hi = S - 1;  // last j with b(s[j]) == b
+        while (lo < hi) {
+          const uint32_t m = lo + (hi - lo + 1) / 2;
+          if (ls_bucket(&tb, U, sample[m]) == b) lo = m; else hi = m - 1;
+        }
+        atomicMax(&md->sample_run, lo - i + 1);
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && cnt) atomicAdd(&md->sample_heavy, cnt);
+}
+
+// One thread: fall back before level 1 when the windows, each standing for
+// n / S input keys, exceed twice the spill limit (a margin over the exact
+// decision's limit, so the sample decides only clear cases).
+__global__ void ls_sample_decide_kernel(LsModel* md, uint64_t n, uint32_t S, uint64_t spill_limit) {
+  if (threadIdx.x != 0) return;
+  const uint64_t est = uint64_t(md->sample_heavy) * n / S;  // < 2^20 * 2^32
+  md->sample_spill = est;
+  md->sample_maxb = uint64_t(md->sample_run) * n / S;
+  md->sample_fb = est > 2 * spill_limit ? 1 : 0;
+}
+
 // Level 1, estimated: coarse-bin counts of LS_EST * LS_WG keys per workgroup
 // at random positions (draws 2^32 + i), added into cnt_c.
 constexpr int LS_EST = 4;
@@ -642,6 +693,7 @@ __global__ __launch_bounds__(LS_WG) void ls_est1_kernel(const K* __restrict__ ke
                                                         const LsModel* md, LsBins bn, Rebind rk) {
   __shared__ LsTable tb;
   __shared__ uint32_t h[LS_MAX_BINS];
+  if (md->sample_fb) return;
   keys = rebind(keys, rk);
   ls_load_table(md, &tb);
   const uint32_t nbc = md->nbins_c;
@@ -668,6 +720,7 @@ __global__ __launch_bounds__(LS_WG) void ls_est1_kernel(const K* __restrict__ ke
 __global__ __launch_bounds__(LS_WG) void ls_plan1_est_kernel(LsModel* md, LsBins bn, uint32_t q) {
   __shared__ uint32_t r[LS_MAX_BINS], off[LS_MAX_BINS], tmp[LS_WG];
   __shared__ uint32_t total;
+  if (md->sample_fb) return;
   const uint32_t nbc = md->nbins_c;
   for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) {
     const uint64_t e = uint64_t(bn.cnt_c[i]) * q;
@@ -689,6 +742,7 @@ __global__ __launch_bounds__(LS_WG) void ls_plan1_est_kernel(LsModel* md, LsBins
 __global__ __launch_bounds__(LS_WG) void ls_fin1_kernel(LsModel* md, LsBins bn, uint32_t chk, int force) {
   __shared__ uint32_t ch[LS_MAX_BINS], choff[LS_MAX_BINS], tmp[LS_WG];
   __shared__ uint32_t tch;
+  if (md->sample_fb) return;  // (l1_over stays clear: the gated exact pass stays off)
   const uint32_t nbc = md->nbins_c;
   if (force || md->l1_over) {  // workgroup-uniform
     for (uint32_t i = threadIdx.x; i < nbc; i += LS_WG) bn.cnt_c[i] = 0;
@@ -741,7 +795,7 @@ __global__ __launch_bounds__(LS_WG) void ls_scatter1_kernel(const K* __restrict_
                                                             int* over) {
   __shared__ LsTable tb;
   __shared__ LsScatterLds<K> L;
-  if (gate && *gate == 0) return;
+  if (md->sample_fb || (gate && *gate == 0)) return;
   keys = rebind(keys, rkeys);
   ls_load_table(md, &tb);
   const uint32_t nbc = md->nbins_c;
@@ -838,6 +892,7 @@ __global__ __launch_bounds__(LS_WG) void ls_hist2_kernel(const K* __restrict__ k
                                                          LsBins bn) {
   __shared__ LsTable tb;
   __shared__ uint32_t h[LS_MAX_BINS];
+  if (md->sample_fb) return;  // (the chunk map was not built)
   constexpr int CHK = ls_chk<K>();
   uint32_t c, lo, hi;
   if (!ls_chunk(md, bn, blockIdx.x, CHK, &c, &lo, &hi)) return;
@@ -924,14 +979,16 @@ __global__ __launch_bounds__(LS_WG) void ls_plan2_kernel(LsModel* md, LsBins bn,
     uint32_t maxb = 0;
     for (uint32_t c = 0; c < nbc; ++c) maxb = cm[c] > maxb ? cm[c] : maxb;
     const uint64_t s = stot;
-    const int fb = (force_fallback || s > spill_limit || uint64_t(ktot) + s != n) ? 1 : 0;
+    const int sfb = md->sample_fb;
+    const int fb = (sfb || force_fallback || s > spill_limit || uint64_t(ktot) + s != n) ? 1 : 0;
     md->misordered = 0;
     md->fallback = fb;
     md->do_learned = fb ? 0 : 1;
     md->do_repair = (!fb && s > 0) ? 1 : 0;
-    md->spilled = s;
+    // after the sample's decision no key was counted: its estimates instead
+    md->spilled = sfb ? md->sample_spill : s;
     md->kept = ktot;
-    md->max_bucket = maxb;
+    md->max_bucket = sfb ? md->sample_maxb : maxb;
     md->r_keys = (s == 0) ? static_cast<void*>(d_keys) : static_cast<void*>(xr);
     md->r_base = (s == 0) ? 0 : s;
   }

@@ -137,6 +137,28 @@ def test_forced_spill_is_repaired_exactly(gpu):
     assert st["fallback_taken"] == 0 and st["repaired"] == 1 and st["spilled"] > 0
 
 
+@pytest.mark.parametrize("share,sample_fb,fb", [(0.04, 0, 0), (0.07, 0, 1), (0.25, 1, 1)])
+def test_sample_decision_on_heavy_ties(gpu, share, sample_fb, fb):
+    """A share of 2^21 mixture keys set to one value, more than a bucket's
+    capacity (16384).  4%: under the spill threshold (5%), the spill is
+    repaired; 7%: over it, the exact decision falls back, but under twice it,
+    where the sorted sample decides; 25%: the sample decides at once
+    (windows of T = 1024 of its 2^16 keys in one bucket, about 0.23 n keys
+    estimated).  All three share one cached graph, run in this order."""
+    n = 1 << 21
+    keys = u32_np(workloads.lognormal_mix_u32(n, seed=12))
+    pos = np.random.default_rng(12).choice(n, size=int(share * n), replace=False)
+    keys[pos] = keys[n // 2]
+    got, st = learned_sort(keys, gpu)
+    assert_equal_arrays(got, oracle.sort(keys), f"ties {share}")
+    assert st["sample_fallback"] == sample_fb and st["fallback_taken"] == fb, st
+    assert st["spilled"] > 0 and st["max_bucket"] > 16384, st
+    if sample_fb:
+        assert abs(st["spilled"] - share * n) < 0.05 * n and abs(st["max_bucket"] - share * n) < 0.05 * n, st
+    else:
+        assert st["repaired"] == 1 - fb, st
+
+
 def test_forced_fallback_is_exact(gpu):
     keys = u32_np(workloads.lognormal_mix_u32(1 << 21, seed=10))
     got, st = learned_sort(keys, gpu, force_fallback=1)
