@@ -159,6 +159,22 @@ def test_sample_decision_on_heavy_ties(gpu, share, sample_fb, fb):
         assert st["repaired"] == 1 - fb, st
 
 
+def test_auto_on_heavy_ties_takes_the_sample_decision(gpu):
+    """2^27 Zipf keys alone, a size where the automatic choice takes the
+    learned form: the sorted sample shows the heavy keys and the plain sort
+    runs with no learned pass over the input.  Output: the plain sort's
+    bytes, and torch.sort's values."""
+    k, _ = workloads.zipf_pairs_u32(1 << 27, seed=0, device=gpu)
+    a, st = msort.ms_sort_ex(k.clone(), algo=msort.MS_ALGO_AUTO)
+    assert st["sample_fallback"] == 1 and st["fallback_taken"] == 1, st
+    assert st["algo_used"] == msort.MS_ALGO_MERGE_PATH, st
+    b = k.clone()
+    msort.ms_sort(b)
+    assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+    ref = torch.sort(k.view(torch.int32).to(torch.int64) & 0xFFFFFFFF).values
+    assert torch.equal(a.view(torch.int32).to(torch.int64) & 0xFFFFFFFF, ref)
+
+
 def test_forced_fallback_is_exact(gpu):
     keys = u32_np(workloads.lognormal_mix_u32(1 << 21, seed=10))
     got, st = learned_sort(keys, gpu, force_fallback=1)
