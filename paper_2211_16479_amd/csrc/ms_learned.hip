@@ -328,8 +328,14 @@ static ms_status learned_enqueue(K* keys, uint64_t n, const ms_options& o, ms_st
     st = merge_two_runs<K, NoVal>(xr, keys, n, DevCtl{nullptr, &md->do_repair, spilled, rk}, part, s, gated_grid);
     if (st != MS_OK) return st;
   }
-  // fallback: the plain merge sort of the untouched input
-  st = plain_sort<K, NoVal>(keys, nullptr, n, DevCtl{nullptr, &md->fallback, nullptr, rk}, s, coarse, gated_grid);
+  // fallback: the plain merge sort of the untouched input, on a bounded grid
+  // four times wider than the other gated stages'.  Where the fallback runs,
+  // 4 workgroups per CU looping over tiles cost it about 5% (2^27 Zipf keys
+  // under the automatic choice: 3.86 ms, 3.73 with 16 per CU, plain sort
+  // 3.22); skipped, its launches of 16 per CU still cost the learned path
+  // nothing measurable (2^29 mixture 7.80 / 7.79 ms).
+  const uint64_t fallback_grid = uint64_t(device_cu_count()) * 16;
+  st = plain_sort<K, NoVal>(keys, nullptr, n, DevCtl{nullptr, &md->fallback, nullptr, rk}, s, coarse, fallback_grid);
   if (st != MS_OK) return st;
   if (d_stats) ls_stats_kernel<<<1, 64, 0, s>>>(md, d_stats, P.B, rs);
   e = hipGetLastError();
