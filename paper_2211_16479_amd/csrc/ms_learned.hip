@@ -37,6 +37,7 @@ __global__ void ls_setup_kernel(LsModel* md, int log_feature, int use_table, int
   md->sample_fb = 0;
   md->sample_spill = 0;
   md->sample_maxb = 0;
+  md->do_train = 1;
 }
 
 __global__ void ls_set_theta_kernel(LsModel* md, const float* theta) {
@@ -207,11 +208,11 @@ static const int* learned_bucket_shapes() {
 // Model training on an already sorted sample: start point, then T Adam steps.
 template <class K>
 static ms_status ls_train_enqueue(const K* sample, uint32_t S, LsModel* md, float* partial, int T, float lr,
-                                  float* loss_hist, bool init, hipStream_t s) {
+                                  float* loss_hist, bool init, hipStream_t s, const int* gate = nullptr) {
   if (init) ls_init_kernel<<<1, 64, 0, s>>>(sample, S, md);
   for (int t = 0; t <= T; ++t) {
     ProfScope ps(PK_LEARN_TRAIN, s);
-    ls_train_kernel<<<LS_TRAIN_G, LS_TRAIN_WG, 0, s>>>(sample, S, md, partial, t, T, lr, loss_hist, nullptr, nullptr);
+    ls_train_kernel<<<LS_TRAIN_G, LS_TRAIN_WG, 0, s>>>(sample, S, md, partial, t, T, lr, loss_hist, nullptr, gate);
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? MS_OK : hip_fail(e, "training launch");
@@ -243,21 +244,23 @@ static ms_status learned_enqueue(K* keys, uint64_t n, const ms_options& o, ms_st
   ms_status st = plain_sort<K, NoVal>(sample, nullptr, P.S, none, s, w + P.sample_tmp);
   if (st != MS_OK) return st;
   ls_feature_range_kernel<K><<<1, 64, 0, s>>>(md, sample, P.S);
-  // train and compile the network
-  st = ls_train_enqueue(sample, P.S, md, partial, int(o.train_steps), o.learning_rate, loss, true, s);
-  if (st != MS_OK) return st;
-  ls_compile_kernel<<<1, 64, 0, s>>>(md, int(o.train_steps) & 1, sample, P.S, nullptr);
   // decision from the sample: runs of T sample keys in one bucket stand for
   // at least twice its capacity (T >= 8, so that a bucket near its capacity
-  // rarely shows such a run by chance)
-  {
-    const uint64_t T = std::max<uint64_t>(8, ceil_div(uint64_t(2) * P.capacity * P.S, n));
-    if (T <= P.S) {
-      ls_sample_heavy_kernel<K><<<dim3(unsigned(ceil_div(P.S - T + 1, 256))), 256, 0, s>>>(sample, P.S,
-                                                                                         uint32_t(T), md);
-      ls_sample_decide_kernel<<<1, 64, 0, s>>>(md, n, P.S, P.spill_cap);
-    }
-  }
+  // rarely shows such a run by chance); equal keys first, before training,
+  // then the trained table's buckets
+  const uint64_t T = std::max<uint64_t>(8, ceil_div(uint64_t(2) * P.capacity * P.S, n));
+  auto sample_check = [&](auto by_key) {
+    if (T > P.S) return;
+    ls_sample_heavy_kernel<K, decltype(by_key)::value>
+        <<<dim3(unsigned(ceil_div(P.S - T + 1, 256))), 256, 0, s>>>(sample, P.S, uint32_t(T), md);
+    ls_sample_decide_kernel<<<1, 64, 0, s>>>(md, n, P.S, P.spill_cap);
+  };
+  sample_check(std::true_type{});
+  // train and compile the network (skipped after a fallback decided above)
+  st = ls_train_enqueue(sample, P.S, md, partial, int(o.train_steps), o.learning_rate, loss, true, s, &md->do_train);
+  if (st != MS_OK) return st;
+  ls_compile_kernel<<<1, 64, 0, s>>>(md, int(o.train_steps) & 1, sample, P.S, &md->do_train);
+  sample_check(std::false_type{});
   // level 1
   // (gated stages run with a bounded grid: when skipped they cost little)
   const uint64_t gated_grid = uint64_t(device_cu_count()) * 4;

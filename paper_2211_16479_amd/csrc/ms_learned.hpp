@@ -130,6 +130,7 @@ struct LsModel {
   uint32_t sample_run;   // longest run of sample keys in one such bucket
   int sample_fb;         // the sample shows too many keys in over-full buckets: fall back at once
   unsigned long long sample_spill, sample_maxb;  // the windows' and the run's input keys (estimates)
+  int do_train;          // training and the table compile run (cleared by a fallback decided before them)
 };
 
 // Keys other than uint32: the feature's offset and scale from the sorted
@@ -642,29 +643,37 @@ __global__ __launch_bounds__(LS_WG) void ls_plan1_kernel(LsModel* md, LsBins bn,
 // Decision from the sorted sample, before any pass over the input.  The
 // bucket function is non-decreasing, so the T sample keys s[i .. i+T-1] lie
 // in one bucket exactly when b(s[i]) == b(s[i+T-1]); the host picks T so that
-// T sample keys stand for at least twice a bucket's capacity.  Counts such
-// windows (a run of L >= T sample keys in one bucket gives L - T + 1 of them)
-// and the longest run, whose first key's thread finds the run's end by a
-// binary search.  One thread per window start.
-template <class K>
+// T sample keys stand for at least twice a bucket's capacity.  BY_KEY: the
+// pass before training, on equal keys (s[i] == s[i+T-1]), which share a
+// bucket under any bucket function; else the pass on the compiled table's
+// buckets.  Counts such windows (a run of L >= T sample keys gives L - T + 1
+// of them) and the longest run, whose first key's thread finds the run's
+// end by a binary search.  One thread per window start.
+template <bool BY_KEY, class K>
+__device__ __forceinline__ auto ls_run_id(const LsTable* tb, const LsUni& U, K key) {
+  if constexpr (BY_KEY) return key; else return ls_bucket(tb, U, key);
+}
+template <class K, bool BY_KEY>
 __global__ __launch_bounds__(256) void ls_sample_heavy_kernel(const K* __restrict__ sample, uint32_t S, uint32_t T,
                                                               LsModel* md) {
   __shared__ LsTable tb;
   __shared__ uint32_t cnt;
-  ls_load_table(md, &tb);
+  if (md->sample_fb) return;  // decided by the pass before
+  if constexpr (!BY_KEY) ls_load_table(md, &tb);
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
-  const LsUni U = ls_uni(&tb);
+  LsUni U{};
+  if constexpr (!BY_KEY) U = ls_uni(&tb);
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i + T - 1 < S) {  // T >= 2, S - T + 1 window starts
-    const uint32_t b = ls_bucket(&tb, U, sample[i]);
-    if (b == ls_bucket(&tb, U, sample[i + T - 1])) {
+    const auto b = ls_run_id<BY_KEY>(&tb, U, sample[i]);
+    if (b == ls_run_id<BY_KEY>(&tb, U, sample[i + T - 1])) {
       atomicAdd(&cnt, 1u);
-      if (i == 0 || ls_bucket(&tb, U, sample[i - 1]) != b) {
-        uint32_t lo = i + T - 1, hi = S - 1;  // last j with b(s[j]) == b
+      if (i == 0 || ls_run_id<BY_KEY>(&tb, U, sample[i - 1]) != b) {
+        uint32_t lo = i + T - 1, hi = S - 1;  // last j with the same id
         while (lo < hi) {
           const uint32_t m = lo + (hi - lo + 1) / 2;
-          if (ls_bucket(&tb, U, sample[m]) == b) lo = m; else hi = m - 1;
+          if (ls_run_id<BY_KEY>(&tb, U, sample[m]) == b) lo = m; else hi = m - 1;
         }
         atomicMax(&md->sample_run, lo - i + 1);
       }
@@ -674,15 +683,20 @@ __global__ __launch_bounds__(256) void ls_sample_heavy_kernel(const K* __restric
   if (threadIdx.x == 0 && cnt) atomicAdd(&md->sample_heavy, cnt);
 }
 
-// One thread: fall back before level 1 when the windows, each standing for
-// n / S input keys, exceed twice the spill limit (a margin over the exact
-// decision's limit, so the sample decides only clear cases).
+// One thread, after each pass: fall back when the windows, each standing
+// for n / S input keys, exceed twice the spill limit (a margin over the
+// exact decision's limit, so the sample decides only clear cases); a
+// fallback decided before training also skips it.  The counters start
+// again from zero for the next pass.
 __global__ void ls_sample_decide_kernel(LsModel* md, uint64_t n, uint32_t S, uint64_t spill_limit) {
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x != 0 || md->sample_fb) return;
   const uint64_t est = uint64_t(md->sample_heavy) * n / S;  // < 2^20 * 2^32
   md->sample_spill = est;
   md->sample_maxb = uint64_t(md->sample_run) * n / S;
   md->sample_fb = est > 2 * spill_limit ? 1 : 0;
+  md->do_train = md->sample_fb ? 0 : 1;
+  md->sample_heavy = 0;
+  md->sample_run = 0;
 }
 
 // Level 1, estimated: coarse-bin counts of LS_EST * LS_WG keys per workgroup
